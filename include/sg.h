@@ -1,0 +1,195 @@
+/*
+ * sg.h -- C ABI of the MI355X (gfx950) shard-graph build library.
+ *
+ * The library builds the per-shard graph index of ScaleGANN's divide-and-merge
+ * workflow (Sec. IV, "Workflow": partition the data with k-means into
+ * overlapping shards, build every shard's graph independently on a GPU, merge
+ * the shard graphs by edge union over the replicated vectors) and queries it.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  * Pointers are DEVICE pointers unless the name ends in `_h` (host).
+ *  * Matrices are row-major; `ld` is the row stride in elements (>= d).
+ *  * Ids are int32; SG_NONE (-1) pads lists that have fewer valid entries.
+ *  * The caller owns every input, output and workspace buffer; the library
+ *    never frees caller memory.  `ws` is a device workspace of at least the
+ *    size returned by the matching *_workspace_size call (NULL allowed when
+ *    that size is 0); it must stay untouched until the stream reaches the
+ *    call's last kernel.
+ *  * `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *    asynchronous on it unless stated otherwise.
+ *  * Arguments are validated on the host before any launch; a bad argument
+ *    returns SG_ERR_ARG (or SG_ERR_WORKSPACE) and launches nothing.  Launch
+ *    and runtime failures return SG_ERR_HIP.  Outputs are undefined after an
+ *    error.  sg_last_error() gives the calling thread's last error text.
+ *  * Calls are re-entrant and thread-safe; calls that share output or
+ *    workspace memory must be ordered by the caller.
+ *  * Every kernel is deterministic: the same call on the same inputs writes
+ *    the same bytes.
+ */
+#ifndef SG_H
+#define SG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sg_status;
+enum {
+    SG_OK = 0,
+    SG_ERR_ARG = -1,          /* invalid argument (checked on the host)         */
+    SG_ERR_HIP = -2,          /* HIP runtime or launch failure                  */
+    SG_ERR_WORKSPACE = -3,    /* workspace missing or too small                 */
+    SG_ERR_UNSUPPORTED = -4,  /* valid but not implemented shape / type combo   */
+    SG_ERR_INTERNAL = -5      /* unexpected internal failure                    */
+};
+#define SG_NONE (-1)
+
+typedef enum { SG_L2 = 0, SG_IP = 1 } sg_metric;
+typedef enum { SG_F32 = 0, SG_F16 = 1, SG_BF16 = 2, SG_U8 = 3 } sg_dtype;
+
+/* Arithmetic of the distance contraction in sg_knn_graph.
+ *  SG_PREC_FP32 : FP32 inputs to FP32 MFMA, FP32 accumulation (the plain build).
+ *  SG_PREC_F16  : FP16 inputs to FP16 MFMA, FP32 accumulation.  Exact for U8
+ *                 data with d <= 128 (every product and partial sum is an
+ *                 integer below 2^24), and the native type of FP16 data.
+ *  SG_PREC_BF16 : rows rounded to BF16 (nearest even), BF16 MFMA, FP32
+ *                 accumulation; a reduced-precision key followed by an FP32
+ *                 re-rank when rerank > k.
+ *  SG_PREC_FP8  : rows scaled per row by a power of two and rounded to OCP FP8
+ *                 E4M3 (nearest even, saturating), FP8 MFMA, FP32
+ *                 accumulation; followed by an FP32 re-rank when rerank > k. */
+typedef enum { SG_PREC_FP32 = 0, SG_PREC_F16 = 1, SG_PREC_BF16 = 2, SG_PREC_FP8 = 3 } sg_prec;
+
+const char* sg_status_str(sg_status s);   /* static text for a status code            */
+const char* sg_last_error(void);          /* detail of this thread's last failing call */
+const char* sg_version(void);
+
+/* ------------------------------------------------------------------------
+ * sg_partition -- k-means partition with selective replication
+ *
+ * Follows Sec. IV step 1 and Sec. V (Algorithm 1) for one in-memory block:
+ *  1. Lloyd k-means: centroids start at rows init_idx_h[0..S-1]; `iters`
+ *     iterations of (assign each row to the nearest centroid by squared L2,
+ *     ties to the lower index; replace each centroid by the FP64 mean of its
+ *     members, an empty cluster keeping its centroid).  Distances are FP32;
+ *     centroid sums are FP64 in a fixed-order two-level reduction.
+ *  2. primary[i] = nearest centroid under the final centroids.
+ *  3. Replicas (Sec. V-B): radius r[c] = largest Euclidean distance of c's
+ *     primary members.  Row i with primary c at distance d visits the other
+ *     centroids in ascending distance d' (ties to the lower index) and joins
+ *     c' when d' < epsilon*d and d' < epsilon*tau*r[c'], until it is in omega
+ *     shards.  epsilon = +inf accepts every visited centroid, i.e. each row
+ *     joins its omega nearest centroids (the replicate-to-nearest policy).
+ *  4. Membership: shard s holds member_ids[shard_offsets_h[s] ..
+ *     shard_offsets_h[s+1]), ascending global row ids.
+ *
+ *  X        : n x d rows (stride ld) of `dtype`.
+ *  S        : number of shards, 1..256;  omega: 1..min(S, 8);  iters >= 0.
+ *  centroids: out, S x d FP64.   primary: out, n int32.
+ *  shard_offsets_h: out (host), S+1 int64.
+ *  member_ids: out, `capacity` int32 (capacity >= n*omega always suffices).
+ *  Synchronises `stream` (the membership sizes are data dependent).  Returns
+ *  SG_ERR_ARG if the membership does not fit in `capacity`.
+ * ---------------------------------------------------------------------- */
+sg_status sg_partition_workspace_size(int64_t n, int32_t d, int32_t S, int32_t omega,
+                                      size_t* bytes);
+sg_status sg_partition(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t ld,
+                       int32_t S, int32_t omega, int32_t iters, float epsilon, float tau,
+                       const int64_t* init_idx_h, double* centroids, int32_t* primary,
+                       int64_t* shard_offsets_h, int32_t* member_ids, int64_t capacity,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * sg_knn_graph -- exact (or reduced-precision + re-ranked) kNN graph of one shard
+ *
+ * The per-shard index build of Sec. IV step 2, done as a tiled all-pairs
+ * distance contraction (the dense-product formulation of Sec. II-A) fused
+ * with a per-row top-k.  For rows i != j of the shard:
+ *    L2: delta(i,j) = ||x_i - x_j||^2,   IP: delta(i,j) = -x_i . x_j.
+ * Row i's list holds the k ids j != i (self excluded by index) with the
+ * smallest (delta, j), ascending; fewer than k candidates pad with SG_NONE /
+ * +inf.  dist[i][t] is delta(i, nbr[i][t]) in FP32.
+ *  X      : n x d rows (stride ld) of `dtype`; ids are row indices 0..n-1.
+ *  k      : 1..256.   prec: see sg_prec (FP32 needs F32/U8/F16/BF16 input,
+ *           F16 needs F16 or U8 input, BF16 / FP8 need F32, F16 or U8 input).
+ *  rerank : 0 for none, else c with k <= c <= 256: the top c by the `prec` key
+ *           are re-scored with the exact FP32 difference-form distance and
+ *           the best k by (delta, id) kept.
+ *  nbr    : out, n x k int32.   dist: out, n x k FP32, may be NULL.
+ *  d      : 1..1024.
+ * ---------------------------------------------------------------------- */
+sg_status sg_knn_graph_workspace_size(int64_t n, int32_t d, int32_t k, sg_prec prec,
+                                      int32_t rerank, size_t* bytes);
+sg_status sg_knn_graph(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t ld,
+                       sg_metric metric, int32_t k, sg_prec prec, int32_t rerank, int32_t* nbr,
+                       float* dist, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * sg_prune -- rank-based edge prune + reverse-edge pass to out-degree R
+ *
+ * The graph-optimisation step of the CAGRA shard build the paper uses
+ * (Sec. II-A, Sec. IV step 2), in this reading:
+ *  1. detour(x,j) = #{ i < j : y_j occurs in N(y_i) at a position < j },
+ *     N(x) = [y_0 .. y_{K-1}] = knn row x.  Valid positions are ordered by
+ *     (detour ascending, j ascending); the first R are P(x), in that order.
+ *  2. Every x and p < R with y = P(x)[p] valid puts x into Rev(y) with key
+ *     (p, x); Rev(y) is ordered by that key.  With h = ceil(R/2):
+ *     F(y) = P(y)[0:h] ++ (Rev(y) entries not yet present)
+ *            ++ (P(y)[h:R] entries not yet present), cut at R.
+ *  knn : n x K int32, each row's valid ids distinct, in [0, n), != the row,
+ *        followed by any SG_NONE padding (as sg_knn_graph writes it).
+ *  K   : 1..256;  R: 1..min(K, 128).   out: n x R int32 (SG_NONE padded).
+ * ---------------------------------------------------------------------- */
+sg_status sg_prune_workspace_size(int64_t n, int32_t K, int32_t R, size_t* bytes);
+sg_status sg_prune(const int32_t* knn, int64_t n, int32_t K, int32_t R, int32_t* out, void* ws,
+                   size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * sg_merge -- edge-union merge of shard graphs (Sec. II-A, Sec. IV step 3)
+ *
+ * graphs holds shards 0..S-1's R-wide lists (local ids) back to back, shard
+ * s's rows at [shard_offsets_h[s], shard_offsets_h[s+1]); member_ids maps a
+ * local row of shard s to its global id (ascending within each shard, as
+ * sg_partition writes it).  For a global id g present in shards s_1 < .. <
+ * s_m with lists L_1..L_m translated to global ids:
+ *   for pos = 0..R-1, for t = 1..m: append L_t[pos] if valid, not yet in the
+ *   list and != g; stop at max_degree.
+ * max_degree = omega*R keeps the plain union; a smaller value caps it.
+ *  out: n_global x max_degree int32 (SG_NONE padded);  degree: n_global int32.
+ *  S: 1..65536;  R: 1..256;  max_degree: 1..1024.
+ * ---------------------------------------------------------------------- */
+sg_status sg_merge_workspace_size(int32_t S, const int64_t* shard_offsets_h, int64_t n_global,
+                                  size_t* bytes);
+sg_status sg_merge(int32_t S, const int64_t* shard_offsets_h, const int32_t* member_ids,
+                   const int32_t* graphs, int32_t R, int64_t n_global, int32_t max_degree,
+                   int32_t* out, int32_t* degree, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * sg_search -- greedy best-first beam search on the merged graph
+ *
+ * The DiskANN-style search used to query the merged index (Sec. VI).  A beam
+ * of capacity L ordered by (delta, id) starts at `entry` (entry < 0: the
+ * medoid, the row nearest to the mean of X, computed on the GPU).  Repeat:
+ * expand the first unexpanded beam entry, visiting its neighbours in list
+ * order, each id evaluated once per query, inserting those that beat the
+ * L-th entry; stop when every beam entry is expanded.  The first topk entries
+ * are returned.
+ *  X: n x d (stride ld);  Q: nq x d (stride ldq), same dtype as X.
+ *  graph: n x max_degree int32 (SG_NONE padded).
+ *  topk <= L <= 512;  max_degree <= 256.
+ *  out_ids: nq x topk;  out_dist: nq x topk FP32, may be NULL.
+ * ---------------------------------------------------------------------- */
+sg_status sg_search_workspace_size(int64_t n, int32_t d, int64_t nq, size_t* bytes);
+sg_status sg_search(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t ld,
+                    sg_metric metric, const int32_t* graph, int32_t max_degree, const void* Q,
+                    int64_t nq, int64_t ldq, int32_t topk, int32_t L, int64_t entry,
+                    int32_t* out_ids, float* out_dist, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SG_H */

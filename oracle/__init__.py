@@ -100,6 +100,18 @@ def knn(X64: np.ndarray, K: int, metric: int = L2, rows=None):
     return nbr, dist
 
 
+def pair_dist(X64: np.ndarray, rows, cols, metric: int = L2) -> np.ndarray:
+    """delta(rows[p], cols[p]) in FP64; -1 in either gives +inf."""
+    X64 = np.ascontiguousarray(X64, np.float64)
+    n, d = X64.shape
+    pairs = np.ascontiguousarray(np.stack([np.asarray(rows, np.int64).ravel(),
+                                           np.asarray(cols, np.int64).ravel()], 1))
+    out = np.empty((pairs.shape[0],), np.float64)
+    _check(_load().orc_pair_dist(_p(X64), _i64(n), C.c_int(d), C.c_int(metric), _p(pairs),
+                                 _i64(pairs.shape[0]), _p(out)), "pair_dist")
+    return out.reshape(np.shape(cols))
+
+
 def detour_prune(knn_ids: np.ndarray, R: int) -> np.ndarray:
     knn_ids = np.ascontiguousarray(knn_ids, np.int32)
     n, K = knn_ids.shape

@@ -139,6 +139,21 @@ int orc_knn(const double* X, int64_t n, int d, int metric, int K,
     return bad ? -1 : 0;
 }
 
+int orc_pair_dist(const double* X, int64_t n, int d, int metric, const int64_t* pairs,
+                  int64_t npairs, double* out) {
+    if (n < 0 || d <= 0 || (metric != ORC_L2 && metric != ORC_IP)) return -1;
+    for (int64_t p = 0; p < npairs; ++p) {
+        int64_t a = pairs[2 * p], b = pairs[2 * p + 1];
+        if (a == ORC_NONE || b == ORC_NONE) {
+            out[p] = INFINITY;
+            continue;
+        }
+        if (a < 0 || a >= n || b < 0 || b >= n) return -1;
+        out[p] = delta(X + a * d, X + b * d, d, metric);
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* detour-count prune                                                  */
 /* ------------------------------------------------------------------ */

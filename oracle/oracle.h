@@ -38,6 +38,11 @@ int orc_widen(const void* X, int dtype, int64_t n, int d, int64_t ld, double* ou
 int orc_knn(const double* X, int64_t n, int d, int metric, int K,
             const int64_t* rows, int64_t nrows, int32_t* nbr, double* dist);
 
+/* delta(pairs[2p], pairs[2p+1]) for npairs (row, row) pairs, FP64 as in orc_knn;
+ * ORC_NONE in either slot gives +inf. */
+int orc_pair_dist(const double* X, int64_t n, int d, int metric, const int64_t* pairs,
+                  int64_t npairs, double* out);
+
 /* Rank-based (detour-count) prune of a kNN graph down to out-degree R.
  * detour(x,j) = #{ i < j : y_j occurs in N(y_i) at a position < j }, with
  * N(x) = [y_0 .. y_{K-1}].  Valid positions are ordered by (detour, j); the

@@ -1,0 +1,224 @@
+"""MI355X (gfx950) shard-graph build for divide-and-merge graph ANN indexing.
+
+Thin Python binding over the C ABI of ``libsg.so`` (declared in include/sg.h).
+Every function here only marshals arguments: torch tensors provide device
+memory and the current HIP stream, and every step runs in the library's HIP
+kernels.  There is no CPU fallback: if the library is not built, importing the
+binding functions raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsg.so")
+
+SG_NONE = -1
+METRICS = {"l2": 0, "ip": 1}
+PRECS = {"fp32": 0, "f16": 1, "bf16": 2, "fp8": 3}
+_DTYPES = {torch.float32: 0, torch.float16: 1, torch.bfloat16: 2, torch.uint8: 3}
+
+_lib = None
+_lock = threading.Lock()
+
+
+class SgError(RuntimeError):
+    def __init__(self, call, status, detail):
+        super().__init__("%s failed: %s (%s)" % (call, status, detail))
+        self.status = status
+
+
+def lib():
+    """Load libsg.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("libsg.so not found at %s: build it with "
+                                   "paper_2605_10135_amd.build.build()" % LIB_PATH)
+            L = C.CDLL(LIB_PATH)
+            _declare(L)
+            _lib = L
+    return _lib
+
+
+vp, i32, i64, f32, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_size_t
+psz = C.POINTER(C.c_size_t)
+
+_SIGS = {
+    "sg_status_str": (C.c_char_p, [i32]),
+    "sg_last_error": (C.c_char_p, []),
+    "sg_version": (C.c_char_p, []),
+    "sg_partition_workspace_size": (i32, [i64, i32, i32, i32, psz]),
+    "sg_partition": (i32, [vp, i32, i64, i32, i64, i32, i32, i32, f32, f32, vp, vp, vp, vp, vp,
+                           i64, vp, sz, vp]),
+    "sg_knn_graph_workspace_size": (i32, [i64, i32, i32, i32, i32, psz]),
+    "sg_knn_graph": (i32, [vp, i32, i64, i32, i64, i32, i32, i32, i32, vp, vp, vp, sz, vp]),
+    "sg_prune_workspace_size": (i32, [i64, i32, i32, psz]),
+    "sg_prune": (i32, [vp, i64, i32, i32, vp, vp, sz, vp]),
+    "sg_merge_workspace_size": (i32, [i32, vp, i64, psz]),
+    "sg_merge": (i32, [i32, vp, vp, vp, i32, i64, i32, vp, vp, vp, sz, vp]),
+    "sg_search_workspace_size": (i32, [i64, i32, i64, psz]),
+    "sg_search": (i32, [vp, i32, i64, i32, i64, i32, vp, i32, vp, i64, i64, i32, i32, i64, vp, vp,
+                        vp, sz, vp]),
+}
+
+
+def exported_symbols():
+    """Names of the C ABI entry points this binding expects."""
+    return sorted(_SIGS)
+
+
+def _declare(L):
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+
+
+def _check(call, rc):
+    if rc != 0:
+        L = lib()
+        raise SgError(call, L.sg_status_str(rc).decode(), L.sg_last_error().decode())
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_tensor(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    return t
+
+
+def _rows(X, name="X"):
+    _dev_tensor(X, name)
+    if X.dim() != 2:
+        raise ValueError("%s must be 2-D" % name)
+    if X.stride(1) != 1:
+        raise ValueError("%s rows must be contiguous" % name)
+    if X.dtype not in _DTYPES:
+        raise TypeError("%s dtype %s not supported" % (name, X.dtype))
+    return _DTYPES[X.dtype], X.shape[0], X.shape[1], X.stride(0)
+
+
+class _Workspace:
+    """Grow-only device workspace per (device, tag)."""
+
+    def __init__(self):
+        self.bufs = {}
+
+    def get(self, nbytes, device, tag="default"):
+        key = (str(device), tag)
+        b = self.bufs.get(key)
+        if b is None or b.numel() < nbytes:
+            b = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+            self.bufs[key] = b
+        return b
+
+
+_ws = _Workspace()
+
+
+def _size(fn, *args):
+    out = C.c_size_t(0)
+    _check(fn.__name__, fn(*args, C.byref(out)))
+    return out.value
+
+
+# ---------------------------------------------------------------------------
+# calls
+# ---------------------------------------------------------------------------
+
+def sg_knn_graph(X, k, metric="l2", prec="fp32", rerank=0, dist=True, stream=None, out=None):
+    """kNN graph of one shard: (nbr int32 [n,k], dist float32 [n,k] or None)."""
+    L = lib()
+    dt, n, d, ld = _rows(X)
+    m, p = METRICS[metric], PRECS[prec]
+    nbytes = _size(L.sg_knn_graph_workspace_size, n, d, k, p, rerank)
+    ws = _ws.get(nbytes, X.device, "knn")
+    if out is not None:
+        nbr, dd = out
+    else:
+        nbr = torch.empty((n, k), dtype=torch.int32, device=X.device)
+        dd = torch.empty((n, k), dtype=torch.float32, device=X.device) if dist else None
+    _check("sg_knn_graph", L.sg_knn_graph(_ptr(X), dt, n, d, ld, m, k, p, rerank, _ptr(nbr), _ptr(dd),
+                                          _ptr(ws), ws.numel(), _stream(stream)))
+    return nbr, dd
+
+
+def sg_prune(knn, R, stream=None, out=None):
+    """Detour-count prune + reverse-edge pass: int32 [n, R]."""
+    L = lib()
+    _dev_tensor(knn, "knn")
+    if knn.dtype != torch.int32 or not knn.is_contiguous():
+        raise TypeError("knn must be a contiguous int32 tensor")
+    n, K = knn.shape
+    ws = _ws.get(_size(L.sg_prune_workspace_size, n, K, R), knn.device, "prune")
+    o = out if out is not None else torch.empty((n, R), dtype=torch.int32, device=knn.device)
+    _check("sg_prune", L.sg_prune(_ptr(knn), n, K, R, _ptr(o), _ptr(ws), ws.numel(), _stream(stream)))
+    return o
+
+
+def sg_merge(shard_offsets, member_ids, graphs, R, n_global, max_degree, stream=None):
+    """Edge-union merge: (out int32 [n_global, max_degree], degree int32 [n_global])."""
+    L = lib()
+    _dev_tensor(member_ids, "member_ids")
+    _dev_tensor(graphs, "graphs")
+    off = torch.as_tensor(shard_offsets, dtype=torch.int64).cpu().contiguous()
+    S = off.numel() - 1
+    offp = C.c_void_p(off.data_ptr())
+    ws = _ws.get(_size(L.sg_merge_workspace_size, S, offp, n_global), member_ids.device, "merge")
+    out = torch.empty((n_global, max_degree), dtype=torch.int32, device=member_ids.device)
+    deg = torch.empty((n_global,), dtype=torch.int32, device=member_ids.device)
+    _check("sg_merge", L.sg_merge(S, offp, _ptr(member_ids.contiguous()), _ptr(graphs.contiguous()), R,
+                                  n_global, max_degree, _ptr(out), _ptr(deg), _ptr(ws), ws.numel(),
+                                  _stream(stream)))
+    return out, deg
+
+
+def sg_partition(X, S, omega, iters, init_idx, epsilon=float("inf"), tau=1.0, stream=None):
+    """k-means + selective replication: (centroids f64 [S,d], primary int32 [n],
+    shard_offsets int64 [S+1] (host), member_ids int32 [total])."""
+    L = lib()
+    dt, n, d, ld = _rows(X)
+    init = torch.as_tensor(init_idx, dtype=torch.int64).cpu().contiguous()
+    ws = _ws.get(_size(L.sg_partition_workspace_size, n, d, S, omega), X.device, "partition")
+    cent = torch.empty((S, d), dtype=torch.float64, device=X.device)
+    prim = torch.empty((n,), dtype=torch.int32, device=X.device)
+    off = torch.empty((S + 1,), dtype=torch.int64)
+    cap = n * omega
+    mem = torch.empty((cap,), dtype=torch.int32, device=X.device)
+    _check("sg_partition", L.sg_partition(_ptr(X), dt, n, d, ld, S, omega, iters, float(epsilon),
+                                          float(tau), C.c_void_p(init.data_ptr()), _ptr(cent),
+                                          _ptr(prim), C.c_void_p(off.data_ptr()), _ptr(mem), cap,
+                                          _ptr(ws), ws.numel(), _stream(stream)))
+    return cent, prim, off, mem[: int(off[-1])]
+
+
+def sg_search(X, graph, Q, topk, L_beam, metric="l2", entry=-1, stream=None):
+    """Greedy beam search: (ids int32 [nq, topk], dist float32 [nq, topk])."""
+    L = lib()
+    dt, n, d, ld = _rows(X)
+    dq, nq, dq_, ldq = _rows(Q, "Q")
+    if dq != dt or dq_ != d:
+        raise ValueError("Q must match X in dtype and width")
+    _dev_tensor(graph, "graph")
+    graph = graph.contiguous()
+    ws = _ws.get(_size(L.sg_search_workspace_size, n, d, nq), X.device, "search")
+    ids = torch.empty((nq, topk), dtype=torch.int32, device=X.device)
+    dist = torch.empty((nq, topk), dtype=torch.float32, device=X.device)
+    _check("sg_search", L.sg_search(_ptr(X), dt, n, d, ld, METRICS[metric], _ptr(graph), graph.shape[1],
+                                    _ptr(Q), nq, ldq, topk, L_beam, entry, _ptr(ids), _ptr(dist),
+                                    _ptr(ws), ws.numel(), _stream(stream)))
+    return ids, dist

@@ -1,0 +1,185 @@
+// common.hpp -- internal helpers of the shard-graph library (gfx950 only).
+//
+// Error reporting for the C ABI, argument-check macros, the (distance, id)
+// 64-bit ordering key, and wave64 primitives shared by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/sg.h"
+
+namespace sg {
+
+// ---------------------------------------------------------------------------
+// error state (one text per calling thread)
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+const char* get_error();
+
+struct Fail {
+    sg_status code;
+};
+
+#define SG_REQUIRE(cond, msg)                                                    \
+    do {                                                                         \
+        if (!(cond)) {                                                           \
+            ::sg::set_error(std::string(__func__) + ": " + (msg));              \
+            throw ::sg::Fail{SG_ERR_ARG};                                        \
+        }                                                                        \
+    } while (0)
+
+#define SG_HIP(call)                                                             \
+    do {                                                                         \
+        hipError_t e_ = (call);                                                  \
+        if (e_ != hipSuccess) {                                                  \
+            ::sg::set_error(std::string(__func__) + ": " #call " -> " +        \
+                            hipGetErrorString(e_));                              \
+            throw ::sg::Fail{SG_ERR_HIP};                                        \
+        }                                                                        \
+    } while (0)
+
+#define SG_LAUNCH_CHECK() SG_HIP(hipGetLastError())
+
+// Runs `body` and maps exceptions to a status (no exception crosses the ABI).
+template <class F>
+sg_status guarded(F&& body) {
+    try {
+        body();
+        return SG_OK;
+    } catch (const Fail& f) {
+        return f.code;
+    } catch (const std::exception& e) {
+        set_error(std::string("internal: ") + e.what());
+        return SG_ERR_INTERNAL;
+    } catch (...) {
+        set_error("internal: unknown exception");
+        return SG_ERR_INTERNAL;
+    }
+}
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Carves aligned sub-buffers out of a caller workspace.
+struct Carver {
+    char* base;
+    size_t used = 0;
+    explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+    template <class T>
+    T* take(size_t count) {
+        used = align_up(used, 256);
+        T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+        used += count * sizeof(T);
+        return p;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// (distance, id) ordering key: the float is mapped to an unsigned integer
+// with the same order, placed above the id, so that comparing keys compares
+// (distance, id) lexicographically.  ~0 marks an empty slot.
+// ---------------------------------------------------------------------------
+constexpr uint64_t EMPTY_KEY = ~0ull;
+
+__host__ __device__ inline uint32_t f2ord(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    uint32_t mask = (uint32_t)((int32_t)u >> 31) | 0x80000000u;
+    return u ^ mask;
+}
+
+__host__ __device__ inline float ord2f(uint32_t o) {
+    uint32_t u = (o & 0x80000000u) ? (o ^ 0x80000000u) : ~o;
+    return __builtin_bit_cast(float, u);
+}
+
+__host__ __device__ inline uint64_t make_key(float dist, int32_t id) {
+    return ((uint64_t)f2ord(dist) << 32) | (uint32_t)id;
+}
+
+__host__ __device__ inline int32_t key_id(uint64_t k) {
+    return k == EMPTY_KEY ? SG_NONE : (int32_t)(uint32_t)k;
+}
+
+__host__ __device__ inline float key_dist(uint64_t k) {
+    return k == EMPTY_KEY ? __builtin_inff() : ord2f((uint32_t)(k >> 32));
+}
+
+// ---------------------------------------------------------------------------
+// wave64 helpers
+// ---------------------------------------------------------------------------
+__device__ inline int lane_id() { return __lane_id(); }
+
+__device__ inline uint64_t shfl_xor_u64(uint64_t v, int mask) {
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    lo = __shfl_xor((int)lo, mask, 64);
+    hi = __shfl_xor((int)hi, mask, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t shfl_u64(uint64_t v, int src) {
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    lo = __shfl((int)lo, src, 64);
+    hi = __shfl((int)hi, src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Ascending bitonic sort of one 64-bit key per lane across the wave.
+__device__ inline uint64_t wave_sort_u64(uint64_t x) {
+    const int l = lane_id();
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            uint64_t o = shfl_xor_u64(x, j);
+            bool up = (l & k) == 0;
+            bool lower = (l & j) == 0;
+            uint64_t mn = x < o ? x : o;
+            uint64_t mx = x < o ? o : x;
+            x = (lower == up) ? mn : mx;
+        }
+    }
+    return x;
+}
+
+// Number of elements of the ascending array a[0..len) that are < v.
+__device__ inline int lower_bound_u64(const uint64_t* a, int len, uint64_t v) {
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] < v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Grid-stride fill (used instead of hipMemsetAsync so that every clear is a
+// kernel and stays valid inside captured graphs).
+template <class T>
+__global__ void fill_kernel(T* __restrict__ p, T v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <class T>
+void fill(T* p, T v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    fill_kernel<T><<<blocks, 256, 0, s>>>(p, v, n);
+    SG_LAUNCH_CHECK();
+}
+
+// Exclusive scan of int64 counts (n entries) into out (n+1 entries).
+void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t s);
+size_t exclusive_scan_tmp_bytes(int64_t n);
+
+}  // namespace sg

@@ -1,0 +1,796 @@
+// knn.hip -- exact (and reduced-precision) kNN graph of one shard.
+//
+// The shard build of Sec. IV step 2 as a tiled all-pairs distance contraction
+// (the dense-product formulation named in Sec. II-A) fused with a per-row
+// top-k selection, for gfx950:
+//
+//  * prep: rows -> MFMA operand rows (FP32 / FP16 / BF16 / FP8 with a
+//    power-of-two per-row scale), zero-padded to the k granule, plus the
+//    squared norms of the operand rows (+inf for padding rows).
+//  * dist_topk: a 256-thread workgroup owns 128 query rows (32 per wave) and
+//    streams every candidate row of the shard through LDS, 64 at a time.  Each
+//    32x32 MFMA output tile holds candidates on its rows and queries on its
+//    columns, so every lane sees 16 candidates of ONE query and keeps that
+//    query's admission threshold in a register.  The accumulator starts at
+//    ||c||^2 and the query operand is pre-scaled by -2 (exact), so the MFMA
+//    result is already the ranking key ||c||^2 - 2 q.c (L2) or -q.c (IP).
+//    Keys below the threshold go to a per-query LDS buffer; a full buffer is
+//    merged (wave bitonic sort + merge by rank) into the query's sorted top-K
+//    list kept in the workspace, which lowers the threshold.
+//  * rerank: the top-c candidates of a reduced-precision key re-scored with
+//    the exact FP32 difference-form distance, best k kept.
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace sg {
+namespace knn {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
+typedef int intx4 __attribute__((ext_vector_type(4)));
+
+constexpr int WAVES = 4;
+constexpr int BQ = 32 * WAVES;   // query rows per workgroup
+constexpr int BC = 64;           // candidate rows per LDS tile
+constexpr int CB = 64;           // per-query candidate buffer
+constexpr int PAD_ROWS = BQ;     // operand rows are padded to a multiple of this
+
+// ---------------------------------------------------------------------------
+// operand traits: element bytes, elements per lane per MFMA step
+// ---------------------------------------------------------------------------
+template <int P> struct Tr;
+template <> struct Tr<SG_PREC_FP32> { static constexpr int EB = 4, VEC = 1; };
+template <> struct Tr<SG_PREC_F16> { static constexpr int EB = 2, VEC = 8; };
+template <> struct Tr<SG_PREC_BF16> { static constexpr int EB = 2, VEC = 8; };
+template <> struct Tr<SG_PREC_FP8> { static constexpr int EB = 1, VEC = 32; };
+
+// padded row length (elements) for a given d: two lane-halves, each a whole
+// number of MFMA steps
+__host__ __device__ inline int padded_d(int prec, int d) {
+    int g = 2 * (prec == SG_PREC_FP32 ? 2 : prec == SG_PREC_FP8 ? 32 : 8);
+    return (d + g - 1) / g * g;
+}
+__host__ __device__ inline int elem_bytes(int prec) {
+    return prec == SG_PREC_FP32 ? 4 : prec == SG_PREC_FP8 ? 1 : 2;
+}
+
+// ---------------------------------------------------------------------------
+// prep: conversion, norms, FP8 scales
+// ---------------------------------------------------------------------------
+__device__ inline float load_elem(const void* X, int dtype, int64_t idx) {
+    switch (dtype) {
+        case SG_F32: return static_cast<const float*>(X)[idx];
+        case SG_F16: return (float)static_cast<const _Float16*>(X)[idx];
+        case SG_BF16: {
+            uint32_t b = (uint32_t) static_cast<const uint16_t*>(X)[idx] << 16;
+            return __builtin_bit_cast(float, b);
+        }
+        default: return (float)static_cast<const uint8_t*>(X)[idx];
+    }
+}
+
+// FP32 -> BF16 bits, round to nearest even (NaN kept quiet)
+__device__ inline uint16_t to_bf16_bits(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// FP32 -> OCP E4M3 code, round to nearest even, saturating at 448.  Works on
+// the bit pattern: normal codes carry 3 mantissa bits, subnormals are
+// multiples of 2^-9.
+__device__ inline uint8_t to_fp8_bits(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    uint8_t sign = (uint8_t)((u >> 24) & 0x80);
+    uint32_t a = u & 0x7fffffffu;
+    if (a > 0x7f800000u) return 0x7f;                       // NaN
+    if (a >= 0x43e00000u) return sign | 0x7e;               // |f| >= 448
+    int e = (int)(a >> 23) - 127;                           // unbiased exponent
+    if (e < -6) {
+        // subnormal range: value / 2^-9 rounded to an integer 0..8
+        float v = __builtin_bit_cast(float, a) * 512.0f;    // exact (power of two)
+        float r = __builtin_rintf(v);                       // ties to even
+        return sign | (uint8_t)r;
+    }
+    uint32_t mant = a & 0x7fffffu;                          // 23 bits, keep 3
+    uint32_t keep = mant >> 20;
+    uint32_t rest = mant & 0xfffffu;
+    if (rest > 0x80000u || (rest == 0x80000u && (keep & 1u))) keep += 1;
+    int ex = e + 7;
+    if (keep == 8) {
+        keep = 0;
+        ex += 1;
+    }
+    uint32_t code = ((uint32_t)ex << 3) | keep;
+    if (code > 0x7e) code = 0x7e;
+    return sign | (uint8_t)code;
+}
+
+__device__ inline float fp8_value(uint8_t c) {
+    int e = (c >> 3) & 15, m = c & 7;
+    float v = e == 0 ? (float)m * (1.0f / 512.0f)
+                     : __builtin_ldexpf(1.0f + (float)m * 0.125f, e - 7);
+    return (c & 0x80) ? -v : v;
+}
+
+// One wave per operand row.  Writes the converted row (zero padded to DP),
+// the squared norm of the converted values (FP32, +inf for padding rows) and,
+// for FP8, the row's scale exponent.
+__global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_t n, int d, int64_t ld,
+                            int64_t n_pad, int DP, int prec, uint8_t* __restrict__ ops,
+                            float* __restrict__ norms, int32_t* __restrict__ sexp) {
+    const int l = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= n_pad) return;
+    const int eb = elem_bytes(prec);
+    uint8_t* out = ops + row * (int64_t)DP * eb;
+    if (row >= n) {
+        for (int t = l; t < DP; t += 64) {
+            if (eb == 4) reinterpret_cast<float*>(out)[t] = 0.f;
+            else if (eb == 2) reinterpret_cast<uint16_t*>(out)[t] = 0;
+            else out[t] = 0;
+        }
+        if (l == 0) {
+            norms[row] = __builtin_inff();
+            if (sexp) sexp[row] = 0;
+        }
+        return;
+    }
+    const int64_t base = row * ld;
+    int sx = 0;
+    float inv = 1.0f;
+    if (prec == SG_PREC_FP8) {
+        float amax = 0.f;
+        for (int t = l; t < d; t += 64) amax = fmaxf(amax, fabsf(load_elem(X, dtype, base + t)));
+        for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+        // smallest power of two s with amax / s <= 448
+        if (amax > 0.f) {
+            sx = (int)ceilf(log2f(amax / 448.0f));
+            while (__builtin_ldexpf(amax, -sx) > 448.0f) ++sx;
+            while (sx > -126 && __builtin_ldexpf(amax, -(sx - 1)) <= 448.0f) --sx;
+        }
+        inv = __builtin_ldexpf(1.0f, -sx);
+    }
+    float ss = 0.f;
+    for (int t = l; t < DP; t += 64) {
+        float v = t < d ? load_elem(X, dtype, base + t) : 0.f;
+        float q;
+        switch (prec) {
+            case SG_PREC_FP32:
+                reinterpret_cast<float*>(out)[t] = v;
+                q = v;
+                break;
+            case SG_PREC_F16: {
+                _Float16 h = (_Float16)v;
+                reinterpret_cast<_Float16*>(out)[t] = h;
+                q = (float)h;
+                break;
+            }
+            case SG_PREC_BF16: {
+                uint16_t b = to_bf16_bits(v);
+                reinterpret_cast<uint16_t*>(out)[t] = b;
+                q = __builtin_bit_cast(float, (uint32_t)b << 16);
+                break;
+            }
+            default: {
+                uint8_t c = to_fp8_bits(v * inv);
+                out[t] = c;
+                q = __builtin_ldexpf(fp8_value(c), sx);
+                break;
+            }
+        }
+        ss += q * q;
+    }
+    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
+    if (l == 0) {
+        norms[row] = ss;
+        if (sexp) sexp[row] = sx;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fused distance tile + top-k
+// ---------------------------------------------------------------------------
+
+// row of the 32x32 MFMA output held by accumulator register i of lane l
+__device__ inline int out_row(int i, int l) { return ((i >> 2) << 3) + ((l >> 5) << 2) + (i & 3); }
+
+template <int P, int NSTEP>
+struct Frag;
+
+template <int NSTEP>
+struct Frag<SG_PREC_FP32, NSTEP> {
+    float v[NSTEP];
+};
+template <int NSTEP>
+struct Frag<SG_PREC_F16, NSTEP> {
+    half8 v[NSTEP];
+};
+template <int NSTEP>
+struct Frag<SG_PREC_BF16, NSTEP> {
+    bf16x8 v[NSTEP];
+};
+template <int NSTEP>
+struct Frag<SG_PREC_FP8, NSTEP> {
+    intx8 v[NSTEP];
+};
+
+// Load lane l's half-row (elements [h*DH, (h+1)*DH)) from a byte row.
+template <int P, int NSTEP>
+__device__ inline void load_frag(Frag<P, NSTEP>& f, const uint8_t* rowp) {
+    if constexpr (P == SG_PREC_FP32) {
+#pragma unroll
+        for (int s = 0; s < NSTEP; s += 2) {
+            float2 v = *reinterpret_cast<const float2*>(rowp + s * 4);
+            f.v[s] = v.x;
+            f.v[s + 1] = v.y;
+        }
+    } else if constexpr (P == SG_PREC_FP8) {
+#pragma unroll
+        for (int s = 0; s < NSTEP; ++s) {
+            intx4 a = *reinterpret_cast<const intx4*>(rowp + s * 32);
+            intx4 b = *reinterpret_cast<const intx4*>(rowp + s * 32 + 16);
+            f.v[s] = intx8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < NSTEP; ++s) {
+            intx4 a = *reinterpret_cast<const intx4*>(rowp + s * 16);
+            if constexpr (P == SG_PREC_F16)
+                f.v[s] = __builtin_bit_cast(half8, a);
+            else
+                f.v[s] = __builtin_bit_cast(bf16x8, a);
+        }
+    }
+}
+
+// Scale the query fragment so that the MFMA yields the ranking key:
+// L2: -2 q (exact), IP: -q.  FP8 flips the code signs and carries the x2 in
+// the scale exponent.
+template <int P, int NSTEP>
+__device__ inline void scale_query(Frag<P, NSTEP>& f, int metric) {
+    if constexpr (P == SG_PREC_FP8) {
+#pragma unroll
+        for (int s = 0; s < NSTEP; ++s)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) f.v[s][e] ^= (int)0x80808080u;
+    } else {
+        const float m = metric == SG_L2 ? -2.0f : -1.0f;
+#pragma unroll
+        for (int s = 0; s < NSTEP; ++s) {
+            if constexpr (P == SG_PREC_FP32) {
+                f.v[s] *= m;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    if constexpr (P == SG_PREC_F16)
+                        f.v[s][e] = (_Float16)((float)f.v[s][e] * m);
+                    else
+                        f.v[s][e] = (__bf16)((float)f.v[s][e] * m);
+                }
+            }
+        }
+    }
+}
+
+template <int P>
+__device__ inline floatx16 mfma_step(const void* a, const void* b, floatx16 acc, int sa, int sb);
+
+template <int P, int NSTEP>
+__device__ inline floatx16 mfma_tile(const uint8_t* arow, const Frag<P, NSTEP>& q, floatx16 acc,
+                                     int sa, int sb) {
+    if constexpr (P == SG_PREC_FP32) {
+#pragma unroll
+        for (int s = 0; s < NSTEP; s += 4) {
+            floatx4 a = *reinterpret_cast<const floatx4*>(arow + s * 4);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0], q.v[s], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1], q.v[s + 1], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[2], q.v[s + 2], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[3], q.v[s + 3], acc, 0, 0, 0);
+        }
+    } else if constexpr (P == SG_PREC_F16) {
+#pragma unroll
+        for (int s = 0; s < NSTEP; ++s) {
+            half8 a = *reinterpret_cast<const half8*>(arow + s * 16);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, q.v[s], acc, 0, 0, 0);
+        }
+    } else if constexpr (P == SG_PREC_BF16) {
+#pragma unroll
+        for (int s = 0; s < NSTEP; ++s) {
+            bf16x8 a = *reinterpret_cast<const bf16x8*>(arow + s * 16);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, q.v[s], acc, 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < NSTEP; ++s) {
+            intx4 lo = *reinterpret_cast<const intx4*>(arow + s * 32);
+            intx4 hi = *reinterpret_cast<const intx4*>(arow + s * 32 + 16);
+            intx8 a = intx8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+            acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, q.v[s], acc, 0, 0, 0, sa, 0,
+                                                                   sb);
+        }
+    }
+    return acc;
+}
+
+template <int P, int NSTEP>
+struct Shape {
+    static constexpr int DH = NSTEP * Tr<P>::VEC;             // elements per lane-half
+    static constexpr int ROW_BYTES = 2 * DH * Tr<P>::EB;      // padded operand row
+    static constexpr int RS = ROW_BYTES + 16;                 // LDS row stride
+};
+
+// Merge query qi's LDS buffer into its sorted top-KSEL list; returns the new
+// admission threshold (the KSEL-th distance, +inf while the list has room).
+template <int KSEL>
+__device__ float merge_query(uint64_t* __restrict__ gstate, uint64_t* buf, int* cnt,
+                             uint64_t* scratch) {
+    constexpr int PER = (KSEL + 63) / 64;
+    const int l = lane_id();
+    const int c = __builtin_amdgcn_readfirstlane(*cnt);
+    uint64_t b = l < c ? buf[l] : EMPTY_KEY;
+    b = wave_sort_u64(b);
+    uint64_t* sb = scratch;          // 64 sorted buffer keys
+    uint64_t* ss = scratch + 64;     // KSEL current keys
+    uint64_t* thr_slot = scratch + 64 + KSEL;
+    sb[l] = b;
+    uint64_t sv[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        int idx = l + 64 * t;
+        sv[t] = idx < KSEL ? gstate[idx] : EMPTY_KEY;
+        if (idx < KSEL) ss[idx] = sv[t];
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)\n s_waitcnt vmcnt(0)" ::: "memory");
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        int idx = l + 64 * t;
+        if (idx < KSEL) {
+            int pos = idx + lower_bound_u64(sb, 64, sv[t]);
+            if (pos < KSEL) {
+                gstate[pos] = sv[t];
+                if (pos == KSEL - 1) *thr_slot = sv[t];
+            }
+        }
+    }
+    if (l < c) {
+        int pos = l + lower_bound_u64(ss, KSEL, b);
+        if (pos < KSEL) {
+            gstate[pos] = b;
+            if (pos == KSEL - 1) *thr_slot = b;
+        }
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)\n s_waitcnt vmcnt(0)" ::: "memory");
+    uint64_t tk = *thr_slot;
+    if (l == 0) *cnt = 0;
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    return key_dist(tk);
+}
+
+template <int P, int NSTEP, int KSEL>
+__global__ __launch_bounds__(256, 1) void dist_topk_kernel(
+    const uint8_t* __restrict__ ops, const float* __restrict__ norms,
+    const int32_t* __restrict__ sexp, int n, int metric, uint64_t* __restrict__ state,
+    int32_t* __restrict__ nbr, float* __restrict__ dist, int k_out) {
+    using S = Shape<P, NSTEP>;
+    __shared__ __align__(16) uint8_t s_tile[BC * S::RS];
+    __shared__ float s_norm[BC];
+    __shared__ int32_t s_sexp[BC];
+    __shared__ uint64_t s_buf[BQ * CB];
+    __shared__ int s_cnt[BQ];
+    __shared__ uint64_t s_scr[WAVES][64 + KSEL + 1];
+
+    const int tid = threadIdx.x;
+    const int l = tid & 63;
+    const int w = tid >> 6;
+    const int h = l >> 5;
+    const int qloc = w * 32 + (l & 31);
+    const int64_t qbase = (int64_t)blockIdx.x * BQ + w * 32;   // first query of this wave
+    const int64_t qg = qbase + (l & 31);
+
+    if (tid < BQ) s_cnt[tid] = 0;
+
+    // resident query fragment, scaled to produce the ranking key
+    Frag<P, NSTEP> qf;
+    load_frag<P, NSTEP>(qf, ops + qg * S::ROW_BYTES + h * (S::ROW_BYTES / 2));
+    scale_query<P, NSTEP>(qf, metric);
+    int q_scale = 127;
+    if constexpr (P == SG_PREC_FP8) q_scale = 127 + sexp[qg] + (metric == SG_L2 ? 1 : 0);
+
+    float thr = __builtin_inff();
+    uint64_t* gstate = state + qg * KSEL;
+    __syncthreads();
+
+    for (int j0 = 0; j0 < n; j0 += BC) {
+        // stage the candidate tile (operand rows are padded, so no bounds checks)
+        {
+            const uint8_t* src = ops + (int64_t)j0 * S::ROW_BYTES;
+            constexpr int CHUNKS = BC * S::ROW_BYTES / 16;
+            constexpr int CPR = S::ROW_BYTES / 16;
+            for (int c = tid; c < CHUNKS; c += 256) {
+                int r = c / CPR, o = c % CPR;
+                intx4 v = *reinterpret_cast<const intx4*>(src + (int64_t)r * S::ROW_BYTES + o * 16);
+                *reinterpret_cast<intx4*>(s_tile + r * S::RS + o * 16) = v;
+            }
+            if (tid < BC) {
+                // ranking-key offset: ||c||^2 for L2, 0 for IP; +inf marks padding rows
+                float nv = norms[j0 + tid];
+                s_norm[tid] = (metric == SG_L2 || nv == __builtin_inff()) ? nv : 0.0f;
+                if constexpr (P == SG_PREC_FP8) s_sexp[tid] = sexp[j0 + tid];
+            }
+        }
+        __syncthreads();
+
+#pragma unroll 1
+        for (int sub = 0; sub < BC / 32; ++sub) {
+            const int cbase = j0 + sub * 32;
+            floatx16 acc;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[i] = s_norm[sub * 32 + out_row(i, l)];
+            int a_scale = 127;
+            if constexpr (P == SG_PREC_FP8) a_scale = 127 + s_sexp[sub * 32 + (l & 31)];
+            acc = mfma_tile<P, NSTEP>(s_tile + (sub * 32 + (l & 31)) * S::RS + h * (S::ROW_BYTES / 2),
+                                      qf, acc, a_scale, q_scale);
+            if (cbase == qbase) {            // exclude self by index
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    if (out_row(i, l) == (l & 31)) acc[i] = __builtin_inff();
+            }
+            bool any = false;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) any |= acc[i] < thr;
+            if (__builtin_amdgcn_ballot_w64(any)) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    if (acc[i] < thr) {
+                        int slot = atomicAdd(&s_cnt[qloc], 1);
+                        s_buf[qloc * CB + slot] = make_key(acc[i], cbase + out_row(i, l));
+                    }
+                }
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+                uint64_t need = __builtin_amdgcn_ballot_w64(l < 32 && s_cnt[qloc] > CB - 32);
+                while (need) {
+                    int qi = __builtin_ctzll(need);
+                    need &= need - 1;
+                    float t = merge_query<KSEL>(state + (qbase + qi) * KSEL, s_buf + (w * 32 + qi) * CB,
+                                                &s_cnt[w * 32 + qi], s_scr[w]);
+                    if ((l & 31) == qi) thr = t;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // drain the buffers
+    {
+        uint64_t need = __builtin_amdgcn_ballot_w64(l < 32 && s_cnt[qloc] > 0);
+        while (need) {
+            int qi = __builtin_ctzll(need);
+            need &= need - 1;
+            merge_query<KSEL>(state + (qbase + qi) * KSEL, s_buf + (w * 32 + qi) * CB,
+                              &s_cnt[w * 32 + qi], s_scr[w]);
+        }
+    }
+    (void)gstate;
+    if (nbr) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        for (int qi = 0; qi < 32; ++qi) {
+            int64_t q = qbase + qi;
+            if (q >= n) break;
+            float qn = metric == SG_L2 ? norms[q] : 0.f;
+            for (int t = l; t < k_out; t += 64) {
+                uint64_t key = state[q * KSEL + t];
+                nbr[q * k_out + t] = key_id(key);
+                if (dist) dist[q * k_out + t] = key == EMPTY_KEY ? __builtin_inff() : key_dist(key) + qn;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 re-rank of the top-c candidates (difference form)
+// ---------------------------------------------------------------------------
+
+// Ascending bitonic sort of 64*PER keys held as v[p] in lane l (element p*64+l).
+template <int PER>
+__device__ inline void wave_sort_multi(uint64_t (&v)[PER]) {
+    const int l = lane_id();
+    constexpr int N = 64 * PER;
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 64) {
+                const int jp = j >> 6;
+#pragma unroll
+                for (int p = 0; p < PER; ++p) {
+                    int q = p ^ jp;
+                    if (q > p) {
+                        int e = p * 64 + l;
+                        bool up = (e & k) == 0;
+                        uint64_t a = v[p], b = v[q];
+                        uint64_t mn = a < b ? a : b, mx = a < b ? b : a;
+                        v[p] = up ? mn : mx;
+                        v[q] = up ? mx : mn;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int p = 0; p < PER; ++p) {
+                    int e = p * 64 + l;
+                    uint64_t o = shfl_xor_u64(v[p], j);
+                    bool up = (e & k) == 0;
+                    bool lower = (l & j) == 0;
+                    uint64_t mn = v[p] < o ? v[p] : o, mx = v[p] < o ? o : v[p];
+                    v[p] = (lower == up) ? mn : mx;
+                }
+            }
+        }
+    }
+}
+
+template <int PER>
+__global__ __launch_bounds__(256) void rerank_kernel(const void* __restrict__ X, int dtype, int64_t n,
+                                                     int d, int64_t ld, int metric,
+                                                     const uint64_t* __restrict__ cand, int kstate,
+                                                     int c, int k, int32_t* __restrict__ nbr,
+                                                     float* __restrict__ dist) {
+    extern __shared__ float s_q[];   // 4 waves x d
+    const int l = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 4 + w;
+    float* q = s_q + w * d;
+    if (i < n)
+        for (int t = l; t < d; t += 64) q[t] = load_elem(X, dtype, i * ld + t);
+    __syncthreads();
+    if (i >= n) return;
+    uint64_t v[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        int e = p * 64 + l;
+        uint64_t key = e < c ? cand[i * kstate + e] : EMPTY_KEY;
+        int32_t j = key_id(key);
+        if (j < 0) {
+            v[p] = EMPTY_KEY;
+            continue;
+        }
+        const int64_t jb = (int64_t)j * ld;
+        float s = 0.f;
+        if (metric == SG_L2) {
+            for (int t = 0; t < d; ++t) {
+                float u = q[t] - load_elem(X, dtype, jb + t);
+                s = fmaf(u, u, s);
+            }
+        } else {
+            for (int t = 0; t < d; ++t) s = fmaf(q[t], load_elem(X, dtype, jb + t), s);
+            s = -s;
+        }
+        v[p] = make_key(s, j);
+    }
+    wave_sort_multi<PER>(v);
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        int e = p * 64 + l;
+        if (e < k) {
+            nbr[i * k + e] = key_id(v[p]);
+            if (dist) dist[i * k + e] = key_dist(v[p]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+inline int ksel_for(int k) { return k <= 32 ? 32 : k <= 64 ? 64 : k <= 128 ? 128 : 256; }
+
+// Largest resident query half-row supported: the query fragment of 32 rows
+// lives in 64 VGPRs per lane at most.
+inline int nstep_for(int prec, int DP) {
+    int vec = prec == SG_PREC_FP32 ? 1 : prec == SG_PREC_FP8 ? 32 : 8;
+    return DP / 2 / vec;
+}
+
+struct Layout {
+    int64_t n_pad;
+    int DP;
+    int ksel;
+    size_t ops_bytes, norms_bytes, sexp_bytes, state_bytes, total;
+};
+
+inline Layout layout(int64_t n, int d, int k, int prec, int rerank) {
+    Layout L;
+    L.n_pad = (n + PAD_ROWS - 1) / PAD_ROWS * PAD_ROWS;
+    L.DP = padded_d(prec, d);
+    L.ksel = ksel_for(rerank > 0 ? rerank : k);
+    L.ops_bytes = (size_t)L.n_pad * L.DP * elem_bytes(prec);
+    L.norms_bytes = (size_t)L.n_pad * 4;
+    L.sexp_bytes = prec == SG_PREC_FP8 ? (size_t)L.n_pad * 4 : 0;
+    L.state_bytes = (size_t)L.n_pad * L.ksel * 8;
+    L.total = align_up(L.ops_bytes, 256) + align_up(L.norms_bytes, 256) + align_up(L.sexp_bytes, 256) +
+              align_up(L.state_bytes, 256) + 1024;
+    return L;
+}
+
+typedef void (*topk_fn)(const uint8_t*, const float*, const int32_t*, int, int, uint64_t*, int32_t*,
+                        float*, int);
+
+template <int P, int NSTEP>
+topk_fn pick_ksel(int ksel) {
+    switch (ksel) {
+        case 32: return dist_topk_kernel<P, NSTEP, 32>;
+        case 64: return dist_topk_kernel<P, NSTEP, 64>;
+        case 128: return dist_topk_kernel<P, NSTEP, 128>;
+        default: return dist_topk_kernel<P, NSTEP, 256>;
+    }
+}
+
+// Resident-query kernels are instantiated for the padded half-row lengths
+// below; a smaller d pads up to the next one.
+topk_fn pick_kernel(int prec, int DP, int ksel, int* DP_used) {
+    int need = nstep_for(prec, DP);
+    switch (prec) {
+        case SG_PREC_FP32: {
+            static const int steps[] = {16, 32, 48, 64};
+            for (int s : steps)
+                if (need <= s) {
+                    *DP_used = 2 * s;
+                    switch (s) {
+                        case 16: return pick_ksel<SG_PREC_FP32, 16>(ksel);
+                        case 32: return pick_ksel<SG_PREC_FP32, 32>(ksel);
+                        case 48: return pick_ksel<SG_PREC_FP32, 48>(ksel);
+                        default: return pick_ksel<SG_PREC_FP32, 64>(ksel);
+                    }
+                }
+            return nullptr;
+        }
+        case SG_PREC_F16:
+        case SG_PREC_BF16: {
+            static const int steps[] = {2, 4, 6, 8, 12, 16};
+            for (int s : steps)
+                if (need <= s) {
+                    *DP_used = 2 * s * 8;
+                    if (prec == SG_PREC_F16) {
+                        switch (s) {
+                            case 2: return pick_ksel<SG_PREC_F16, 2>(ksel);
+                            case 4: return pick_ksel<SG_PREC_F16, 4>(ksel);
+                            case 6: return pick_ksel<SG_PREC_F16, 6>(ksel);
+                            case 8: return pick_ksel<SG_PREC_F16, 8>(ksel);
+                            case 12: return pick_ksel<SG_PREC_F16, 12>(ksel);
+                            default: return pick_ksel<SG_PREC_F16, 16>(ksel);
+                        }
+                    } else {
+                        switch (s) {
+                            case 2: return pick_ksel<SG_PREC_BF16, 2>(ksel);
+                            case 4: return pick_ksel<SG_PREC_BF16, 4>(ksel);
+                            case 6: return pick_ksel<SG_PREC_BF16, 6>(ksel);
+                            case 8: return pick_ksel<SG_PREC_BF16, 8>(ksel);
+                            case 12: return pick_ksel<SG_PREC_BF16, 12>(ksel);
+                            default: return pick_ksel<SG_PREC_BF16, 16>(ksel);
+                        }
+                    }
+                }
+            return nullptr;
+        }
+        default: {
+            static const int steps[] = {1, 2, 4, 8};
+            for (int s : steps)
+                if (need <= s) {
+                    *DP_used = 2 * s * 32;
+                    switch (s) {
+                        case 1: return pick_ksel<SG_PREC_FP8, 1>(ksel);
+                        case 2: return pick_ksel<SG_PREC_FP8, 2>(ksel);
+                        case 4: return pick_ksel<SG_PREC_FP8, 4>(ksel);
+                        default: return pick_ksel<SG_PREC_FP8, 8>(ksel);
+                    }
+                }
+            return nullptr;
+        }
+    }
+}
+
+// padded row length actually used by the kernel for (prec, d)
+inline int kernel_dp(int prec, int d, int ksel) {
+    int used = 0;
+    pick_kernel(prec, padded_d(prec, d), ksel, &used);
+    return used;
+}
+
+inline Layout layout_k(int64_t n, int d, int k, int prec, int rerank) {
+    Layout L = layout(n, d, k, prec, rerank);
+    int used = kernel_dp(prec, d, L.ksel);
+    if (used > 0) {
+        L.DP = used;
+        L.ops_bytes = (size_t)L.n_pad * L.DP * elem_bytes(prec);
+        L.total = align_up(L.ops_bytes, 256) + align_up(L.norms_bytes, 256) +
+                  align_up(L.sexp_bytes, 256) + align_up(L.state_bytes, 256) + 1024;
+    }
+    return L;
+}
+
+void check_args(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int k, int prec,
+                int rerank) {
+    SG_REQUIRE(n >= 0 && n < (1ll << 31) - PAD_ROWS, "n out of range");
+    SG_REQUIRE(d >= 1 && d <= 1024, "d must be in 1..1024");
+    SG_REQUIRE(ld >= d, "ld must be >= d");
+    SG_REQUIRE(k >= 1 && k <= 256, "k must be in 1..256");
+    SG_REQUIRE(metric == SG_L2 || metric == SG_IP, "unknown metric");
+    SG_REQUIRE(dtype >= SG_F32 && dtype <= SG_U8, "unknown dtype");
+    SG_REQUIRE(prec >= SG_PREC_FP32 && prec <= SG_PREC_FP8, "unknown precision");
+    SG_REQUIRE(rerank == 0 || (rerank >= k && rerank <= 256), "rerank must be 0 or in k..256");
+    SG_REQUIRE(!(prec == SG_PREC_F16 && dtype != SG_F16 && dtype != SG_U8),
+               "SG_PREC_F16 needs F16 or U8 input");
+    SG_REQUIRE(!(prec == SG_PREC_F16 && dtype == SG_U8 && d > 128),
+               "SG_PREC_F16 is exact on U8 input only for d <= 128");
+    SG_REQUIRE(n == 0 || X != nullptr, "X is NULL");
+}
+
+}  // namespace knn
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" sg_status sg_knn_graph_workspace_size(int64_t n, int32_t d, int32_t k, sg_prec prec,
+                                                 int32_t rerank, size_t* bytes) {
+    return guarded([&] {
+        SG_REQUIRE(bytes != nullptr, "bytes is NULL");
+        SG_REQUIRE(n >= 0 && d >= 1 && d <= 1024 && k >= 1 && k <= 256, "bad sizes");
+        knn::Layout L = knn::layout_k(n, d, k, prec, rerank);
+        *bytes = n == 0 ? 0 : L.total;
+    });
+}
+
+extern "C" sg_status sg_knn_graph(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t ld,
+                                  sg_metric metric, int32_t k, sg_prec prec, int32_t rerank,
+                                  int32_t* nbr, float* dist, void* ws, size_t ws_bytes, void* stream) {
+    return guarded([&] {
+        knn::check_args(X, dtype, n, d, ld, metric, k, prec, rerank);
+        SG_REQUIRE(nbr != nullptr || n == 0, "nbr is NULL");
+        if (n == 0) return;
+        if (rerank == k) rerank = 0;
+        knn::Layout L = knn::layout_k(n, d, k, prec, rerank);
+        int used = 0;
+        knn::topk_fn fn = knn::pick_kernel(prec, knn::padded_d(prec, d), L.ksel, &used);
+        if (!fn) {
+            set_error("sg_knn_graph: d too large for the resident-query kernel of this precision");
+            throw Fail{SG_ERR_UNSUPPORTED};
+        }
+        if (ws_bytes < L.total || ws == nullptr) {
+            set_error("sg_knn_graph: workspace too small (need " + std::to_string(L.total) + " bytes)");
+            throw Fail{SG_ERR_WORKSPACE};
+        }
+        hipStream_t s = as_stream(stream);
+        Carver cv(ws);
+        uint8_t* ops = cv.take<uint8_t>(L.ops_bytes);
+        float* norms = cv.take<float>(L.n_pad);
+        int32_t* sexp = prec == SG_PREC_FP8 ? cv.take<int32_t>(L.n_pad) : nullptr;
+        uint64_t* state = cv.take<uint64_t>((size_t)L.n_pad * L.ksel);
+
+        knn::prep_kernel<<<(unsigned)cdiv(L.n_pad, 4), 256, 0, s>>>(X, dtype, n, d, ld, L.n_pad, L.DP,
+                                                                     prec, ops, norms, sexp);
+        SG_LAUNCH_CHECK();
+        fill<uint64_t>(state, EMPTY_KEY, (int64_t)L.n_pad * L.ksel, s);
+        const bool final_here = rerank == 0;
+        fn<<<(unsigned)(L.n_pad / knn::BQ), 256, 0, s>>>(ops, norms, sexp, (int)n, metric, state,
+                                                          final_here ? nbr : nullptr,
+                                                          final_here ? dist : nullptr, k);
+        SG_LAUNCH_CHECK();
+        if (!final_here) {
+            size_t shm = (size_t)4 * d * sizeof(float);
+            unsigned grid = (unsigned)cdiv(n, 4);
+            if (rerank <= 64)
+                knn::rerank_kernel<1><<<grid, 256, shm, s>>>(X, dtype, n, d, ld, metric, state, L.ksel,
+                                                             rerank, k, nbr, dist);
+            else if (rerank <= 128)
+                knn::rerank_kernel<2><<<grid, 256, shm, s>>>(X, dtype, n, d, ld, metric, state, L.ksel,
+                                                             rerank, k, nbr, dist);
+            else
+                knn::rerank_kernel<4><<<grid, 256, shm, s>>>(X, dtype, n, d, ld, metric, state, L.ksel,
+                                                             rerank, k, nbr, dist);
+            SG_LAUNCH_CHECK();
+        }
+    });
+}

@@ -1,0 +1,119 @@
+"""GPU parity of the integer passes (sg_prune, sg_merge) against the oracle:
+bit-exact on the hand-worked examples, on exact kNN graphs of seeded data and
+on seeded random graphs (with padding, odd R, K = R, high in-degree)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2605_10135_amd as sg
+import synthdata
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def _prune_gpu(knn, R):
+    out = sg.sg_prune(torch.from_numpy(np.ascontiguousarray(knn, np.int32)).to(DEV), R)
+    return out.cpu().numpy()
+
+
+def test_prune_worked_example():
+    g = _gold("detour_prune_5.json")
+    knn = np.array(g["knn"], np.int32)
+    # the worked example fixes P; the reverse pass then adds nothing at R = 2
+    assert _prune_gpu(knn, g["R"]).tolist() == oracle.prune(knn, g["R"]).tolist()
+    assert oracle.detour_prune(knn, g["R"]).tolist() == g["expected_P"]
+
+
+def test_reverse_combine_worked_example_through_prune():
+    # a K = R input makes the detour step a permutation; compare the whole pass
+    g = _gold("reverse_combine_7.json")
+    P = np.array(g["P"], np.int32)
+    exp = oracle.reverse_combine(oracle.detour_prune(P, P.shape[1]))
+    assert _prune_gpu(P, P.shape[1]).tolist() == exp.tolist()
+
+
+@pytest.mark.parametrize("n,K,R", [(300, 32, 16), (1000, 64, 32), (257, 64, 64), (500, 20, 7),
+                                   (130, 128, 64), (90, 256, 33)])
+def test_prune_on_random_graphs(n, K, R):
+    knn = synthdata.local_graph(n, K, seed=n + K + R) if n > 2 * K + 2 else synthdata.random_graph(n, K, seed=n)
+    np.testing.assert_array_equal(_prune_gpu(knn, R), oracle.prune(knn, R))
+
+
+def test_prune_with_padding():
+    knn = synthdata.random_graph(400, 24, seed=5, n_none=5)
+    np.testing.assert_array_equal(_prune_gpu(knn, 12), oracle.prune(knn, 12))
+
+
+@pytest.mark.parametrize("n,d,K,R", [(2000, 128, 64, 32), (3000, 96, 32, 16), (40, 8, 64, 32)])
+def test_prune_on_exact_knn(n, d, K, R):
+    X = synthdata.sift_like_u8(n=n, d=d, seed=n, n_comp=max(2, n // 100))
+    knn, _ = oracle.knn(oracle.widen(X), K)
+    np.testing.assert_array_equal(_prune_gpu(knn, R), oracle.prune(knn, R))
+
+
+def test_prune_hub_in_degree():
+    # many rows point at a few hubs: in-degree >> 64 exercises the chunked selection
+    rng = np.random.default_rng(0)
+    n, K = 3000, 16
+    knn = np.empty((n, K), np.int32)
+    for i in range(n):
+        hubs = [h for h in range(8) if h != i][:4]
+        rest = rng.choice([j for j in range(n) if j != i and j not in hubs][:200], K - 4, replace=False)
+        knn[i] = np.concatenate([hubs, rest])
+    np.testing.assert_array_equal(_prune_gpu(knn, 8), oracle.prune(knn, 8))
+
+
+def _merge_gpu(off, mem, graphs, R, n_global, cap):
+    out, deg = sg.sg_merge(off, torch.from_numpy(np.asarray(mem, np.int32)).to(DEV),
+                           torch.from_numpy(np.asarray(graphs, np.int32)).to(DEV), R, n_global, cap)
+    return out.cpu().numpy(), deg.cpu().numpy()
+
+
+@pytest.mark.parametrize("cap", [4, 3, 2])
+def test_merge_worked_example(cap):
+    g = _gold("merge_2shards.json")
+    out, deg = _merge_gpu(g["offsets"], g["member_ids"], g["graphs_local"], g["R"], g["n_global"], cap)
+    assert out.tolist() == g["expected"][str(cap)]["out"]
+    assert deg.tolist() == g["expected"][str(cap)]["degree"]
+
+
+@pytest.mark.parametrize("overlap,R", [(0.25, 8), (0.5, 16), (0.0, 5)])
+def test_merge_overlapping_windows(overlap, R):
+    sizes = synthdata.batched_shard_sizes(12, seed=3, mu=np.log(400), sigma=0.5, lo=100, hi=900)
+    N, off, mem = synthdata.overlapping_windows(sizes, overlap)
+    graphs = np.concatenate([synthdata.random_graph(int(s), R, seed=t, n_none=2) for t, s in enumerate(sizes)])
+    for cap in (R, 2 * R, 3 * R):
+        out, deg = _merge_gpu(off, mem, graphs, R, N, cap)
+        oout, odeg = oracle.merge(off, mem, graphs, R, N, cap)
+        np.testing.assert_array_equal(out, oout)
+        np.testing.assert_array_equal(deg, odeg)
+
+
+def test_merge_identity_and_absent_ids():
+    n, R = 500, 12
+    g = synthdata.random_graph(n, R, seed=9)
+    off = [0, n, 2 * n]
+    mem = np.concatenate([np.arange(n), np.arange(n)])
+    out, deg = _merge_gpu(off, mem, np.concatenate([g, g]), R, n + 7, 2 * R)
+    oout, odeg = oracle.merge(off, mem, np.concatenate([g, g]), R, n + 7, 2 * R)
+    np.testing.assert_array_equal(out, oout)
+    np.testing.assert_array_equal(deg, odeg)
+    assert (deg[n:] == 0).all()
+
+
+def test_prune_merge_deterministic():
+    knn = synthdata.local_graph(2000, 32, seed=1)
+    a = _prune_gpu(knn, 16)
+    b = _prune_gpu(knn, 16)
+    np.testing.assert_array_equal(a, b)

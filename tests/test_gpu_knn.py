@@ -1,0 +1,114 @@
+"""GPU parity of sg_knn_graph against the FP64 oracle (through the C ABI).
+
+Integer-valued rows (uint8, d <= 128) make every FP32 product and partial sum
+exact, so the FP32-MFMA and FP16-MFMA builds must equal the oracle bit for bit,
+ties included.  Float rows are compared under the tie rule in parity.py.
+Reduced-precision keys (BF16, FP8) with the FP32 re-rank are judged by recall
+and by the exactness of the re-ranked distances they return.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2605_10135_amd as sg
+import synthdata
+from parity import check_rows, recall
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _u8(n, d, seed, levels=256):
+    rng = np.random.default_rng(seed)
+    if levels < 256:
+        return rng.integers(0, levels, size=(n, d)).astype(np.uint8)
+    return synthdata.sift_like_u8(n=n, d=d, seed=seed, n_comp=max(2, n // 50))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "f16"])
+@pytest.mark.parametrize("n,d,K", [(1, 128, 4), (5, 128, 8), (33, 16, 32), (200, 128, 64),
+                                   (1000, 96, 32), (2100, 128, 64), (700, 24, 100), (300, 8, 256)])
+def test_knn_u8_bit_exact(prec, n, d, K):
+    X = _u8(n, d, seed=n * 7 + d)
+    nbr, dist = sg.sg_knn_graph(torch.from_numpy(X).to(DEV), K, "l2", prec)
+    torch.cuda.synchronize()
+    onbr, odist = oracle.knn(oracle.widen(X), K)
+    np.testing.assert_array_equal(nbr.cpu().numpy(), onbr)
+    np.testing.assert_array_equal(dist.cpu().numpy(), odist.astype(np.float32))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "f16"])
+def test_knn_u8_heavy_ties(prec):
+    # 4 levels in 6 dims: huge numbers of exactly equal distances -> the id rule decides
+    X = _u8(900, 6, seed=3, levels=4)
+    nbr, dist = sg.sg_knn_graph(torch.from_numpy(X).to(DEV), 40, "l2", prec)
+    onbr, odist = oracle.knn(oracle.widen(X), 40)
+    np.testing.assert_array_equal(nbr.cpu().numpy(), onbr)
+    np.testing.assert_array_equal(dist.cpu().numpy(), odist.astype(np.float32))
+
+
+def test_knn_u8_ip_bit_exact():
+    X = _u8(600, 32, seed=11, levels=16)
+    nbr, dist = sg.sg_knn_graph(torch.from_numpy(X).to(DEV), 24, "ip", "fp32")
+    onbr, odist = oracle.knn(oracle.widen(X), 24, oracle.IP)
+    np.testing.assert_array_equal(nbr.cpu().numpy(), onbr)
+    np.testing.assert_array_equal(dist.cpu().numpy(), odist.astype(np.float32))
+
+
+@pytest.mark.parametrize("n,d,K", [(2048, 96, 32), (1500, 100, 64), (333, 7, 16)])
+def test_knn_f32_tie_rule(n, d, K):
+    X = synthdata.mixture(n, d, 16, 0.3, seed=n + d)
+    nbr, dist = sg.sg_knn_graph(torch.from_numpy(X).to(DEV), K, "l2", "fp32")
+    X64 = oracle.widen(X)
+    onbr, odist = oracle.knn(X64, K)
+    bad = check_rows(X64, np.arange(n), nbr.cpu().numpy(), dist.cpu().numpy(), onbr, odist)
+    assert not bad, bad[:5]
+
+
+def test_knn_ip_unit_tie_rule():
+    X = synthdata.unit_rows(synthdata.mixture(1200, 64, 20, 0.15, seed=4))
+    nbr, dist = sg.sg_knn_graph(torch.from_numpy(X).to(DEV), 48, "ip", "fp32")
+    X64 = oracle.widen(X)
+    onbr, odist = oracle.knn(X64, 48, oracle.IP)
+    bad = check_rows(X64, np.arange(len(X)), nbr.cpu().numpy(), dist.cpu().numpy(), onbr, odist,
+                     oracle.IP)
+    assert not bad, bad[:5]
+
+
+def test_knn_f16_input_tie_rule():
+    X = synthdata.unit_rows(synthdata.mixture(1000, 96, 10, 0.15, seed=8)).astype(np.float16)
+    nbr, dist = sg.sg_knn_graph(torch.from_numpy(X).to(DEV), 32, "ip", "f16")
+    X64 = oracle.widen(X)
+    onbr, odist = oracle.knn(X64, 32, oracle.IP)
+    bad = check_rows(X64, np.arange(len(X)), nbr.cpu().numpy(), dist.cpu().numpy(), onbr, odist,
+                     oracle.IP)
+    assert not bad, bad[:5]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("metric", ["ip", "l2"])
+def test_knn_reduced_precision_with_rerank(prec, metric):
+    X = synthdata.unit_rows(synthdata.mixture(3000, 96, 40, 0.15, seed=21))
+    K, c = 32, 64
+    nbr, dist = sg.sg_knn_graph(torch.from_numpy(X).to(DEV), K, metric, prec, rerank=c)
+    X64 = oracle.widen(X)
+    m = oracle.IP if metric == "ip" else oracle.L2
+    onbr, odist = oracle.knn(X64, K, m)
+    g = nbr.cpu().numpy()
+    assert recall(g, onbr) >= 0.99
+    # the re-ranked distances are the FP32 distances of the returned pairs
+    d64 = oracle.pair_dist(X64, np.repeat(np.arange(len(X))[:, None], K, 1), g, m)
+    gd = dist.cpu().numpy()
+    scale = np.maximum(np.abs(d64), 1e-3)
+    assert np.max(np.abs(gd - d64) / scale) < 1e-5
+    for row in g[:50]:
+        assert len(set(row.tolist())) == K
+
+
+def test_knn_deterministic():
+    X = synthdata.mixture(1500, 64, 8, 0.5, seed=2)
+    Xg = torch.from_numpy(X).to(DEV)
+    a = sg.sg_knn_graph(Xg, 32, "l2", "fp32")
+    b = sg.sg_knn_graph(Xg, 32, "l2", "fp32")
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])

@@ -149,3 +149,17 @@ def test_rerank_skips_none_and_pads():
     nbr, dist = oracle.rerank(oracle.widen(X), cand, 2)
     assert nbr.tolist() == [[1, 2], [-1, -1], [1, 3], [2, 4], [3, -1]]
     assert np.isinf(dist[1]).all()
+
+
+def test_pair_dist_line_and_knn_agree():
+    n, d = 20, 2
+    X = np.zeros((n, d), np.float32)
+    X[:, 1] = np.arange(n)
+    X64 = oracle.widen(X)
+    rows = np.array([0, 3, 19, 5, -1])
+    cols = np.array([19, 3, 0, 9, 2])
+    got = oracle.pair_dist(X64, rows, cols)
+    assert got[:4].tolist() == [361.0, 0.0, 361.0, 16.0] and np.isinf(got[4])
+    assert oracle.pair_dist(X64, [2], [7], oracle.IP).tolist() == [-14.0]
+    nbr, dist = oracle.knn(X64, 5)
+    np.testing.assert_array_equal(oracle.pair_dist(X64, np.repeat(np.arange(n)[:, None], 5, 1), nbr), dist)
