@@ -61,7 +61,11 @@ typedef enum { SG_F32 = 0, SG_F16 = 1, SG_BF16 = 2, SG_U8 = 3 } sg_dtype;
  *                 re-rank when rerank > k.
  *  SG_PREC_FP8  : rows scaled per row by a power of two and rounded to OCP FP8
  *                 E4M3 (nearest even, saturating), FP8 MFMA, FP32
- *                 accumulation; followed by an FP32 re-rank when rerank > k. */
+ *                 accumulation; followed by an FP32 re-rank when rerank > k.
+ *  With BF16 / FP8 and the IP metric the candidate key is the L2 key of the
+ *  rounded rows with the candidate's exact squared norm put back,
+ *  ||c~||^2 - ||c||^2 - 2 q~.c~: the same ranking as -q.c up to rounding, with
+ *  a rounding error that scales with ||q - c||. */
 typedef enum { SG_PREC_FP32 = 0, SG_PREC_F16 = 1, SG_PREC_BF16 = 2, SG_PREC_FP8 = 3 } sg_prec;
 
 const char* sg_status_str(sg_status s);   /* static text for a status code            */
@@ -88,7 +92,8 @@ const char* sg_version(void);
  *     shard_offsets_h[s+1]), ascending global row ids.
  *
  *  X        : n x d rows (stride ld) of `dtype`.
- *  S        : number of shards, 1..256;  omega: 1..min(S, 8);  iters >= 0.
+ *  S        : number of shards, 1..64;  omega: 1..min(S, 8);  iters >= 0.
+ *  d        : 1..4096.
  *  centroids: out, S x d FP64.   primary: out, n int32.
  *  shard_offsets_h: out (host), S+1 int64.
  *  member_ids: out, `capacity` int32 (capacity >= n*omega always suffices).
@@ -120,7 +125,9 @@ sg_status sg_partition(const void* X, sg_dtype dtype, int64_t n, int32_t d, int6
  *           are re-scored with the exact FP32 difference-form distance and
  *           the best k by (delta, id) kept.
  *  nbr    : out, n x k int32.   dist: out, n x k FP32, may be NULL.
- *  d      : 1..1024.
+ *  d      : 1..1024; the query tile of this kernel is register resident, which
+ *           bounds d by precision: FP32 <= 128, FP16 / BF16 <= 256, FP8 <= 512
+ *           (larger d returns SG_ERR_UNSUPPORTED).
  * ---------------------------------------------------------------------- */
 sg_status sg_knn_graph_workspace_size(int64_t n, int32_t d, int32_t k, sg_prec prec,
                                       int32_t rerank, size_t* bytes);
@@ -142,7 +149,8 @@ sg_status sg_knn_graph(const void* X, sg_dtype dtype, int64_t n, int32_t d, int6
  *            ++ (P(y)[h:R] entries not yet present), cut at R.
  *  knn : n x K int32, each row's valid ids distinct, in [0, n), != the row,
  *        followed by any SG_NONE padding (as sg_knn_graph writes it).
- *  K   : 1..256;  R: 1..min(K, 128).   out: n x R int32 (SG_NONE padded).
+ *  K   : 1..256;  R: 1..min(K, 64).   out: n x R int32 (SG_NONE padded).
+ *  Ids outside [0, n) in knn are treated as SG_NONE.
  * ---------------------------------------------------------------------- */
 sg_status sg_prune_workspace_size(int64_t n, int32_t K, int32_t R, size_t* bytes);
 sg_status sg_prune(const int32_t* knn, int64_t n, int32_t K, int32_t R, int32_t* out, void* ws,
@@ -188,6 +196,19 @@ sg_status sg_search(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t
                     sg_metric metric, const int32_t* graph, int32_t max_degree, const void* Q,
                     int64_t nq, int64_t ldq, int32_t topk, int32_t L, int64_t entry,
                     int32_t* out_ids, float* out_dist, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Profiling of the distance kernel (host-side, per process)
+ *
+ * sg_profile_begin() starts recording a pair of HIP events around every
+ * launch of the fused distance + top-k kernel made by sg_knn_graph, on the
+ * stream that launch uses.  sg_profile_end() waits for those events and
+ * returns the summed kernel time (ms) and the number of launches since the
+ * matching begin, then stops recording.  Not meant to be called concurrently
+ * from several threads.
+ * ---------------------------------------------------------------------- */
+sg_status sg_profile_begin(void);
+sg_status sg_profile_end(double* kernel_ms, int64_t* launches);
 
 #ifdef __cplusplus
 }

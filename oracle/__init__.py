@@ -60,6 +60,11 @@ def _i64(v):
     return C.c_int64(int(v))
 
 
+def num_threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(_load().orc_num_threads())
+
+
 # ---------------------------------------------------------------------------
 # inputs
 # ---------------------------------------------------------------------------

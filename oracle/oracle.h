@@ -25,6 +25,9 @@ enum { ORC_F32 = 0, ORC_F16 = 1, ORC_BF16 = 2, ORC_U8 = 3 };
 enum { ORC_L2 = 0, ORC_IP = 1 };
 #define ORC_NONE (-1)
 
+/* Threads the OpenMP loops of this library use. */
+int orc_num_threads(void);
+
 /* Widen an n x d row-major array (row stride ld elements) of the given dtype to FP64. */
 int orc_widen(const void* X, int dtype, int64_t n, int d, int64_t ld, double* out);
 

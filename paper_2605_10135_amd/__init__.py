@@ -63,6 +63,8 @@ _SIGS = {
     "sg_merge_workspace_size": (i32, [i32, vp, i64, psz]),
     "sg_merge": (i32, [i32, vp, vp, vp, i32, i64, i32, vp, vp, vp, sz, vp]),
     "sg_search_workspace_size": (i32, [i64, i32, i64, psz]),
+    "sg_profile_begin": (i32, []),
+    "sg_profile_end": (i32, [C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "sg_search": (i32, [vp, i32, i64, i32, i64, i32, vp, i32, vp, i64, i64, i32, i32, i64, vp, vp,
                         vp, sz, vp]),
 }
@@ -222,3 +224,15 @@ def sg_search(X, graph, Q, topk, L_beam, metric="l2", entry=-1, stream=None):
                                     _ptr(Q), nq, ldq, topk, L_beam, entry, _ptr(ids), _ptr(dist),
                                     _ptr(ws), ws.numel(), _stream(stream)))
     return ids, dist
+
+
+def sg_profile_begin():
+    """Start recording HIP events around each distance-kernel launch."""
+    _check("sg_profile_begin", lib().sg_profile_begin())
+
+
+def sg_profile_end():
+    """(summed distance-kernel milliseconds, launches) since sg_profile_begin."""
+    ms, n = C.c_double(0.0), C.c_int64(0)
+    _check("sg_profile_end", lib().sg_profile_end(C.byref(ms), C.byref(n)))
+    return ms.value, n.value

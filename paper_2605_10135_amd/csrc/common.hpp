@@ -178,6 +178,9 @@ void fill(T* p, T v, int64_t n, hipStream_t s) {
     SG_LAUNCH_CHECK();
 }
 
+// Event pair around a distance-kernel launch while sg_profile_begin is active.
+void profile_record(hipStream_t s, bool before);
+
 // Exclusive scan of int64 counts (n entries) into out (n+1 entries).
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t s);
 size_t exclusive_scan_tmp_bytes(int64_t n);

@@ -118,12 +118,25 @@ __device__ inline float fp8_value(uint8_t c) {
     return (c & 0x80) ? -v : v;
 }
 
+// Ranking-key form per (metric, precision):
+//   L2             key = ||c~||^2 - 2 q~.c~            dist = key + ||q~||^2
+//   IP, FP32/F16   key = -q.c                           dist = key
+//   IP, BF16/FP8   key = ||c~||^2 - ||c||^2 - 2 q~.c~   dist = (key + ||q~||^2 - ||q||^2) / 2
+// (x~ = the rounded operand row).  The reduced-precision IP key is the L2 key
+// of the rounded rows with the exact norm put back: its rounding error scales
+// with ||q - c|| instead of ||q|| ||c||, which keeps near neighbours apart.
+__host__ __device__ inline bool norm_corrected_ip(int metric, int prec) {
+    return metric == SG_IP && (prec == SG_PREC_BF16 || prec == SG_PREC_FP8);
+}
+
 // One wave per operand row.  Writes the converted row (zero padded to DP),
-// the squared norm of the converted values (FP32, +inf for padding rows) and,
-// for FP8, the row's scale exponent.
+// the accumulator start of the row as a candidate (ninit, +inf for padding
+// rows), its output offset as a query (nout) and, for FP8, the row's scale
+// exponent.
 __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_t n, int d, int64_t ld,
-                            int64_t n_pad, int DP, int prec, uint8_t* __restrict__ ops,
-                            float* __restrict__ norms, int32_t* __restrict__ sexp) {
+                            int64_t n_pad, int DP, int prec, int metric, uint8_t* __restrict__ ops,
+                            float* __restrict__ ninit, float* __restrict__ nout,
+                            int32_t* __restrict__ sexp) {
     const int l = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (row >= n_pad) return;
@@ -136,7 +149,8 @@ __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_t n, in
             else out[t] = 0;
         }
         if (l == 0) {
-            norms[row] = __builtin_inff();
+            ninit[row] = __builtin_inff();
+            nout[row] = 0.f;
             if (sexp) sexp[row] = 0;
         }
         return;
@@ -156,7 +170,7 @@ __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_t n, in
         }
         inv = __builtin_ldexpf(1.0f, -sx);
     }
-    float ss = 0.f;
+    float ssq = 0.f, ssx = 0.f;
     for (int t = l; t < DP; t += 64) {
         float v = t < d ? load_elem(X, dtype, base + t) : 0.f;
         float q;
@@ -184,11 +198,24 @@ __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_t n, in
                 break;
             }
         }
-        ss += q * q;
+        ssq += q * q;
+        ssx += v * v;
     }
-    for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
+    for (int o = 32; o > 0; o >>= 1) {
+        ssq += __shfl_xor(ssq, o, 64);
+        ssx += __shfl_xor(ssx, o, 64);
+    }
     if (l == 0) {
-        norms[row] = ss;
+        if (metric == SG_L2) {
+            ninit[row] = ssq;
+            nout[row] = ssq;
+        } else if (norm_corrected_ip(metric, prec)) {
+            ninit[row] = ssq - ssx;
+            nout[row] = ssq - ssx;
+        } else {
+            ninit[row] = 0.f;
+            nout[row] = 0.f;
+        }
         if (sexp) sexp[row] = sx;
     }
 }
@@ -249,18 +276,18 @@ __device__ inline void load_frag(Frag<P, NSTEP>& f, const uint8_t* rowp) {
     }
 }
 
-// Scale the query fragment so that the MFMA yields the ranking key:
-// L2: -2 q (exact), IP: -q.  FP8 flips the code signs and carries the x2 in
-// the scale exponent.
+// Scale the query fragment by qmul (-2 or -1, exact) so that the MFMA yields
+// the ranking key.  FP8 (always the -2 form) flips the code signs and carries
+// the x2 in the scale exponent.
 template <int P, int NSTEP>
-__device__ inline void scale_query(Frag<P, NSTEP>& f, int metric) {
+__device__ inline void scale_query(Frag<P, NSTEP>& f, float qmul) {
     if constexpr (P == SG_PREC_FP8) {
 #pragma unroll
         for (int s = 0; s < NSTEP; ++s)
 #pragma unroll
             for (int e = 0; e < 8; ++e) f.v[s][e] ^= (int)0x80808080u;
     } else {
-        const float m = metric == SG_L2 ? -2.0f : -1.0f;
+        const float m = qmul;
 #pragma unroll
         for (int s = 0; s < NSTEP; ++s) {
             if constexpr (P == SG_PREC_FP32) {
@@ -374,8 +401,8 @@ __device__ float merge_query(uint64_t* __restrict__ gstate, uint64_t* buf, int* 
 
 template <int P, int NSTEP, int KSEL>
 __global__ __launch_bounds__(256, 1) void dist_topk_kernel(
-    const uint8_t* __restrict__ ops, const float* __restrict__ norms,
-    const int32_t* __restrict__ sexp, int n, int metric, uint64_t* __restrict__ state,
+    const uint8_t* __restrict__ ops, const float* __restrict__ ninit, const float* __restrict__ nout,
+    const int32_t* __restrict__ sexp, int n, float qmul, float osc, uint64_t* __restrict__ state,
     int32_t* __restrict__ nbr, float* __restrict__ dist, int k_out) {
     using S = Shape<P, NSTEP>;
     __shared__ __align__(16) uint8_t s_tile[BC * S::RS];
@@ -398,9 +425,9 @@ __global__ __launch_bounds__(256, 1) void dist_topk_kernel(
     // resident query fragment, scaled to produce the ranking key
     Frag<P, NSTEP> qf;
     load_frag<P, NSTEP>(qf, ops + qg * S::ROW_BYTES + h * (S::ROW_BYTES / 2));
-    scale_query<P, NSTEP>(qf, metric);
+    scale_query<P, NSTEP>(qf, qmul);
     int q_scale = 127;
-    if constexpr (P == SG_PREC_FP8) q_scale = 127 + sexp[qg] + (metric == SG_L2 ? 1 : 0);
+    if constexpr (P == SG_PREC_FP8) q_scale = 127 + sexp[qg] + 1;
 
     float thr = __builtin_inff();
     uint64_t* gstate = state + qg * KSEL;
@@ -418,9 +445,7 @@ __global__ __launch_bounds__(256, 1) void dist_topk_kernel(
                 *reinterpret_cast<intx4*>(s_tile + r * S::RS + o * 16) = v;
             }
             if (tid < BC) {
-                // ranking-key offset: ||c||^2 for L2, 0 for IP; +inf marks padding rows
-                float nv = norms[j0 + tid];
-                s_norm[tid] = (metric == SG_L2 || nv == __builtin_inff()) ? nv : 0.0f;
+                s_norm[tid] = ninit[j0 + tid];
                 if constexpr (P == SG_PREC_FP8) s_sexp[tid] = sexp[j0 + tid];
             }
         }
@@ -481,11 +506,12 @@ __global__ __launch_bounds__(256, 1) void dist_topk_kernel(
         for (int qi = 0; qi < 32; ++qi) {
             int64_t q = qbase + qi;
             if (q >= n) break;
-            float qn = metric == SG_L2 ? norms[q] : 0.f;
+            const float qn = nout[q];
             for (int t = l; t < k_out; t += 64) {
                 uint64_t key = state[q * KSEL + t];
                 nbr[q * k_out + t] = key_id(key);
-                if (dist) dist[q * k_out + t] = key == EMPTY_KEY ? __builtin_inff() : key_dist(key) + qn;
+                if (dist)
+                    dist[q * k_out + t] = key == EMPTY_KEY ? __builtin_inff() : (key_dist(key) + qn) * osc;
             }
         }
     }
@@ -607,7 +633,7 @@ inline Layout layout(int64_t n, int d, int k, int prec, int rerank) {
     L.DP = padded_d(prec, d);
     L.ksel = ksel_for(rerank > 0 ? rerank : k);
     L.ops_bytes = (size_t)L.n_pad * L.DP * elem_bytes(prec);
-    L.norms_bytes = (size_t)L.n_pad * 4;
+    L.norms_bytes = (size_t)L.n_pad * 4 * 2;
     L.sexp_bytes = prec == SG_PREC_FP8 ? (size_t)L.n_pad * 4 : 0;
     L.state_bytes = (size_t)L.n_pad * L.ksel * 8;
     L.total = align_up(L.ops_bytes, 256) + align_up(L.norms_bytes, 256) + align_up(L.sexp_bytes, 256) +
@@ -615,8 +641,8 @@ inline Layout layout(int64_t n, int d, int k, int prec, int rerank) {
     return L;
 }
 
-typedef void (*topk_fn)(const uint8_t*, const float*, const int32_t*, int, int, uint64_t*, int32_t*,
-                        float*, int);
+typedef void (*topk_fn)(const uint8_t*, const float*, const float*, const int32_t*, int, float, float,
+                        uint64_t*, int32_t*, float*, int);
 
 template <int P, int NSTEP>
 topk_fn pick_ksel(int ksel) {
@@ -765,19 +791,25 @@ extern "C" sg_status sg_knn_graph(const void* X, sg_dtype dtype, int64_t n, int3
         hipStream_t s = as_stream(stream);
         Carver cv(ws);
         uint8_t* ops = cv.take<uint8_t>(L.ops_bytes);
-        float* norms = cv.take<float>(L.n_pad);
+        float* ninit = cv.take<float>(L.n_pad);
+        float* nout = cv.take<float>(L.n_pad);
         int32_t* sexp = prec == SG_PREC_FP8 ? cv.take<int32_t>(L.n_pad) : nullptr;
         uint64_t* state = cv.take<uint64_t>((size_t)L.n_pad * L.ksel);
 
         knn::prep_kernel<<<(unsigned)cdiv(L.n_pad, 4), 256, 0, s>>>(X, dtype, n, d, ld, L.n_pad, L.DP,
-                                                                     prec, ops, norms, sexp);
+                                                                     prec, metric, ops, ninit, nout, sexp);
         SG_LAUNCH_CHECK();
         fill<uint64_t>(state, EMPTY_KEY, (int64_t)L.n_pad * L.ksel, s);
         const bool final_here = rerank == 0;
-        fn<<<(unsigned)(L.n_pad / knn::BQ), 256, 0, s>>>(ops, norms, sexp, (int)n, metric, state,
+        const bool plain_ip = metric == SG_IP && !knn::norm_corrected_ip(metric, prec);
+        const float qmul = plain_ip ? -1.0f : -2.0f;
+        const float osc = knn::norm_corrected_ip(metric, prec) ? 0.5f : 1.0f;
+        profile_record(s, true);
+        fn<<<(unsigned)(L.n_pad / knn::BQ), 256, 0, s>>>(ops, ninit, nout, sexp, (int)n, qmul, osc, state,
                                                           final_here ? nbr : nullptr,
                                                           final_here ? dist : nullptr, k);
         SG_LAUNCH_CHECK();
+        profile_record(s, false);
         if (!final_here) {
             size_t shm = (size_t)4 * d * sizeof(float);
             unsigned grid = (unsigned)cdiv(n, 4);

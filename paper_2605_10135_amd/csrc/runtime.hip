@@ -1,5 +1,8 @@
 // runtime.hip -- status strings, per-thread error text, device exclusive scan.
+#include <mutex>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "common.hpp"
 
@@ -113,9 +116,69 @@ void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, void* tmp, h
     SG_LAUNCH_CHECK();
 }
 
+// ---------------------------------------------------------------------------
+// distance-kernel profiling (event pairs around each launch)
+// ---------------------------------------------------------------------------
+namespace {
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_events;
+}  // namespace
+
+bool profiling_on() {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    return g_prof_on;
+}
+
+void profile_record(hipStream_t s, bool before) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (!g_prof_on) return;
+    if (before) {
+        hipEvent_t a, b;
+        SG_HIP(hipEventCreate(&a));
+        SG_HIP(hipEventCreate(&b));
+        g_prof_events.emplace_back(a, b);
+        SG_HIP(hipEventRecord(a, s));
+    } else if (!g_prof_events.empty()) {
+        SG_HIP(hipEventRecord(g_prof_events.back().second, s));
+    }
+}
+
 }  // namespace sg
 
 extern "C" {
+
+sg_status sg_profile_begin(void) {
+    return sg::guarded([&] {
+        std::lock_guard<std::mutex> g(sg::g_prof_mu);
+        for (auto& e : sg::g_prof_events) {
+            hipEventDestroy(e.first);
+            hipEventDestroy(e.second);
+        }
+        sg::g_prof_events.clear();
+        sg::g_prof_on = true;
+    });
+}
+
+sg_status sg_profile_end(double* kernel_ms, int64_t* launches) {
+    return sg::guarded([&] {
+        SG_REQUIRE(kernel_ms != nullptr && launches != nullptr, "NULL pointer");
+        std::lock_guard<std::mutex> g(sg::g_prof_mu);
+        double total = 0.0;
+        for (auto& e : sg::g_prof_events) {
+            SG_HIP(hipEventSynchronize(e.second));
+            float ms = 0.f;
+            SG_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+            total += ms;
+            hipEventDestroy(e.first);
+            hipEventDestroy(e.second);
+        }
+        *kernel_ms = total;
+        *launches = (int64_t)sg::g_prof_events.size();
+        sg::g_prof_events.clear();
+        sg::g_prof_on = false;
+    });
+}
 
 const char* sg_status_str(sg_status s) {
     switch (s) {

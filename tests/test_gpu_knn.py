@@ -13,7 +13,7 @@ import torch
 import oracle
 import paper_2605_10135_amd as sg
 import synthdata
-from parity import check_rows, recall
+from parity import check_rows, l2_form_violations, recall
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -74,6 +74,8 @@ def test_knn_ip_unit_tie_rule():
     bad = check_rows(X64, np.arange(len(X)), nbr.cpu().numpy(), dist.cpu().numpy(), onbr, odist,
                      oracle.IP)
     assert not bad, bad[:5]
+    # in the stricter L2 form only a handful of near-duplicate rows may differ
+    assert len(l2_form_violations(X64, np.arange(len(X)), nbr.cpu().numpy(), odist)) <= len(X) // 200
 
 
 def test_knn_f16_input_tie_rule():
