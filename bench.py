@@ -178,10 +178,11 @@ def main():
     cpu = None
     if not args.no_cpu:
         n0 = X0.shape[0]
-        probe = rng.choice(n0, size=8, replace=False)
+        nprobe = 2 * oracle.num_threads()
+        probe = rng.choice(n0, size=nprobe, replace=False)
         t = time.perf_counter()
         oracle.knn(X0_64, K, rows=probe)
-        per_row = (time.perf_counter() - t) / 8
+        per_row = (time.perf_counter() - t) / nprobe
         m = int(max(8, min(n0, args.cpu_seconds / max(per_row, 1e-9))))
         sample = rng.choice(n0, size=m, replace=False)
         t = time.perf_counter()
