@@ -7,16 +7,22 @@
 //  * prep: rows -> MFMA operand rows (FP32 / FP16 / BF16 / FP8 with a
 //    power-of-two per-row scale), zero-padded to the k granule, plus the
 //    squared norms of the operand rows (+inf for padding rows).
-//  * dist_topk: a 256-thread workgroup owns 128 query rows (32 per wave) and
-//    streams every candidate row of the shard through LDS, 64 at a time.  Each
-//    32x32 MFMA output tile holds candidates on its rows and queries on its
-//    columns, so every lane sees 16 candidates of ONE query and keeps that
-//    query's admission threshold in a register.  The accumulator starts at
-//    ||c||^2 and the query operand is pre-scaled by -2 (exact), so the MFMA
-//    result is already the ranking key ||c||^2 - 2 q.c (L2) or -q.c (IP).
-//    Keys below the threshold go to a per-query LDS buffer; a full buffer is
-//    merged (wave bitonic sort + merge by rank) into the query's sorted top-K
-//    list kept in the workspace, which lowers the threshold.
+//  * dist_topk: a 512-thread workgroup (8 waves, two per SIMD so that one
+//    wave's selection overlaps the other's MFMAs) owns 256 query rows, 32
+//    per wave, and streams every candidate row of the shard through LDS in
+//    double-buffered tiles (the next tile is already loading into registers
+//    while the current one is computed).  Each 32x32 MFMA output tile holds
+//    candidates on its rows and queries on its columns, so every lane sees
+//    16 candidates of ONE query and keeps that query's admission threshold in
+//    a register.  The accumulator starts at ||c||^2 and the query operand is
+//    pre-scaled by -2 (exact), so the MFMA result is already the ranking key
+//    ||c||^2 - 2 q.c (L2) or -q.c (IP).  Keys below the threshold go to a
+//    32-entry LDS buffer per query; a buffer that overflows is merged in
+//    registers (wave bitonic sort + bitonic merge) into the query's sorted
+//    top-K list kept in the workspace, which lowers the threshold, and the
+//    overflowing keys are re-admitted against it.  Candidates are visited in
+//    ascending id order, so a key equal to the threshold can never enter the
+//    list and the strict comparison is exact.
 //  * rerank: the top-c candidates of a reduced-precision key re-scored with
 //    the exact FP32 difference-form distance, best k kept.
 #include <algorithm>
@@ -33,11 +39,11 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int intx8 __attribute__((ext_vector_type(8)));
 typedef int intx4 __attribute__((ext_vector_type(4)));
 
-constexpr int WAVES = 4;
-constexpr int BQ = 32 * WAVES;   // query rows per workgroup
-constexpr int BC = 64;           // candidate rows per LDS tile
-constexpr int CB = 64;           // per-query candidate buffer
-constexpr int PAD_ROWS = BQ;     // operand rows are padded to a multiple of this
+constexpr int TWAVES = 8;        // waves per workgroup of the distance kernel
+constexpr int TQB = 1;           // 32-query blocks per wave
+constexpr int BQ = 32 * TQB * TWAVES;   // query rows per workgroup
+constexpr int CB = 32;           // per-query candidate buffer
+constexpr int PAD_ROWS = BQ;     // operand rows are padded to a multiple of this (>= any tile)
 
 // ---------------------------------------------------------------------------
 // operand traits: element bytes, elements per lane per MFMA step
@@ -349,166 +355,283 @@ template <int P, int NSTEP>
 struct Shape {
     static constexpr int DH = NSTEP * Tr<P>::VEC;             // elements per lane-half
     static constexpr int ROW_BYTES = 2 * DH * Tr<P>::EB;      // padded operand row
-    static constexpr int RS = ROW_BYTES + 16;                 // LDS row stride
+    static constexpr int RS = ROW_BYTES + 16;                 // LDS row stride (bank spread)
+    // candidate rows per LDS tile: two tiles (double buffer) stay within ~70 KB
+    static constexpr int BC = ROW_BYTES <= 256 ? 128 : ROW_BYTES <= 512 ? 64 : 32;
+    static constexpr int NSUB = BC / 32;
 };
 
-// Merge query qi's LDS buffer into its sorted top-KSEL list; returns the new
-// admission threshold (the KSEL-th distance, +inf while the list has room).
-template <int KSEL>
-__device__ float merge_query(uint64_t* __restrict__ gstate, uint64_t* buf, int* cnt,
-                             uint64_t* scratch) {
-    constexpr int PER = (KSEL + 63) / 64;
+// Bitonic merge (ascending) of 64*PER keys held as v[p] (element p*64 + lane)
+// that already form a bitonic sequence.
+template <int PER>
+__device__ inline void bitonic_merge_multi(uint64_t (&v)[PER]) {
     const int l = lane_id();
-    const int c = __builtin_amdgcn_readfirstlane(*cnt);
-    uint64_t b = l < c ? buf[l] : EMPTY_KEY;
-    b = wave_sort_u64(b);
-    uint64_t* sb = scratch;          // 64 sorted buffer keys
-    uint64_t* ss = scratch + 64;     // KSEL current keys
-    uint64_t* thr_slot = scratch + 64 + KSEL;
-    sb[l] = b;
-    uint64_t sv[PER];
 #pragma unroll
-    for (int t = 0; t < PER; ++t) {
-        int idx = l + 64 * t;
-        sv[t] = idx < KSEL ? gstate[idx] : EMPTY_KEY;
-        if (idx < KSEL) ss[idx] = sv[t];
-    }
-    asm volatile("s_waitcnt lgkmcnt(0)\n s_waitcnt vmcnt(0)" ::: "memory");
+    for (int j = 32 * PER; j > 0; j >>= 1) {
+        if (j >= 64) {
+            const int jp = j >> 6;
 #pragma unroll
-    for (int t = 0; t < PER; ++t) {
-        int idx = l + 64 * t;
-        if (idx < KSEL) {
-            int pos = idx + lower_bound_u64(sb, 64, sv[t]);
-            if (pos < KSEL) {
-                gstate[pos] = sv[t];
-                if (pos == KSEL - 1) *thr_slot = sv[t];
+            for (int p = 0; p < PER; ++p) {
+                const int q = p ^ jp;
+                if (q > p) {
+                    uint64_t a = v[p], b = v[q];
+                    v[p] = a < b ? a : b;
+                    v[q] = a < b ? b : a;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                uint64_t o = shfl_xor_u64(v[p], j);
+                bool lower = (l & j) == 0;
+                uint64_t mn = v[p] < o ? v[p] : o, mx = v[p] < o ? o : v[p];
+                v[p] = lower ? mn : mx;
             }
         }
     }
-    if (l < c) {
-        int pos = l + lower_bound_u64(ss, KSEL, b);
-        if (pos < KSEL) {
-            gstate[pos] = b;
-            if (pos == KSEL - 1) *thr_slot = b;
-        }
-    }
-    asm volatile("s_waitcnt lgkmcnt(0)\n s_waitcnt vmcnt(0)" ::: "memory");
-    uint64_t tk = *thr_slot;
-    if (l == 0) *cnt = 0;
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    return key_dist(tk);
 }
 
-template <int P, int NSTEP, int KSEL>
-__global__ __launch_bounds__(256, 1) void dist_topk_kernel(
+// Merge one query's candidate buffer (<= CB keys in LDS) into its sorted
+// top-KSEL list in the workspace, all in registers: sort the buffer across the
+// wave, take the element-wise minimum of the list and the reversed buffer
+// (which holds the KSEL smallest of both as a bitonic sequence), bitonic-merge
+// it.  Returns the new admission threshold: the KSEL-th distance (+inf while
+// the list is not full).
+template <int KSEL>
+__device__ float merge_query(uint64_t* __restrict__ gstate, const uint64_t* buf, int c) {
+    constexpr int PER = KSEL >= 64 ? KSEL / 64 : 1;
+    const int l = lane_id();
+    uint64_t b = l < c ? buf[l] : EMPTY_KEY;
+    uint64_t v[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int e = p * 64 + l;
+        v[p] = e < KSEL ? gstate[e] : EMPTY_KEY;
+    }
+    b = wave_sort_u64(b);
+    const uint64_t r = shfl_u64(b, 63 - l);
+    v[PER - 1] = v[PER - 1] < r ? v[PER - 1] : r;
+    bitonic_merge_multi<PER>(v);
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int e = p * 64 + l;
+        if (e < KSEL) gstate[e] = v[p];
+    }
+    const uint64_t last = shfl_u64(v[(KSEL - 1) / 64], (KSEL - 1) & 63);
+    return key_dist(last);
+}
+
+// Fused distance tile + top-k.  WAVES waves per workgroup, QB blocks of 32
+// queries per wave (NQ = 32*QB*WAVES queries per workgroup).  Candidate
+// tiles (BC rows) are staged in LDS, double buffered, the next tile already
+// in flight in registers while the current one is computed.  Within a tile
+// the MFMAs of subtile s+1 are issued before the selection epilogue of
+// subtile s so that both run at once.
+template <int P, int NSTEP, int KSEL, int WAVES, int QB>
+__global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_kernel(
     const uint8_t* __restrict__ ops, const float* __restrict__ ninit, const float* __restrict__ nout,
     const int32_t* __restrict__ sexp, int n, float qmul, float osc, uint64_t* __restrict__ state,
     int32_t* __restrict__ nbr, float* __restrict__ dist, int k_out) {
     using S = Shape<P, NSTEP>;
-    __shared__ __align__(16) uint8_t s_tile[BC * S::RS];
-    __shared__ float s_norm[BC];
-    __shared__ int32_t s_sexp[BC];
-    __shared__ uint64_t s_buf[BQ * CB];
-    __shared__ int s_cnt[BQ];
-    __shared__ uint64_t s_scr[WAVES][64 + KSEL + 1];
+    constexpr int BC = S::BC, NSUB = S::NSUB, RB = S::ROW_BYTES, RS = S::RS;
+    constexpr int NT = WAVES * 64;
+    constexpr int NQ = 32 * QB * WAVES;
+    constexpr int CHUNKS = BC * RB / 16;                        // 16-byte chunks per tile
+    constexpr int CPT = (CHUNKS + NT - 1) / NT;                 // chunks per thread
+    __shared__ __align__(16) uint8_t s_tile[2][BC * RS];
+    __shared__ __align__(16) float s_norm[2][BC];
+    __shared__ int32_t s_sexp[2][P == SG_PREC_FP8 ? BC : 1];
+    __shared__ uint64_t s_buf[NQ * CB];
+    __shared__ int s_cnt[NQ];
 
     const int tid = threadIdx.x;
     const int l = tid & 63;
     const int w = tid >> 6;
     const int h = l >> 5;
-    const int qloc = w * 32 + (l & 31);
-    const int64_t qbase = (int64_t)blockIdx.x * BQ + w * 32;   // first query of this wave
-    const int64_t qg = qbase + (l & 31);
+    const int ql = l & 31;
+    const int64_t qblk0 = (int64_t)blockIdx.x * NQ + w * 32 * QB;   // first query of this wave
 
-    if (tid < BQ) s_cnt[tid] = 0;
+    for (int t = tid; t < NQ; t += NT) s_cnt[t] = 0;
 
-    // resident query fragment, scaled to produce the ranking key
-    Frag<P, NSTEP> qf;
-    load_frag<P, NSTEP>(qf, ops + qg * S::ROW_BYTES + h * (S::ROW_BYTES / 2));
-    scale_query<P, NSTEP>(qf, qmul);
-    int q_scale = 127;
-    if constexpr (P == SG_PREC_FP8) q_scale = 127 + sexp[qg] + 1;
+    Frag<P, NSTEP> qf[QB];
+    int q_scale[QB];
+    float thr[QB];
+#pragma unroll
+    for (int b = 0; b < QB; ++b) {
+        const int64_t qg = qblk0 + b * 32 + ql;
+        load_frag<P, NSTEP>(qf[b], ops + qg * RB + h * (RB / 2));
+        scale_query<P, NSTEP>(qf[b], qmul);
+        q_scale[b] = 127;
+        if constexpr (P == SG_PREC_FP8) q_scale[b] = 127 + sexp[qg] + 1;
+        thr[b] = __builtin_inff();
+    }
 
-    float thr = __builtin_inff();
-    uint64_t* gstate = state + qg * KSEL;
-    __syncthreads();
-
-    for (int j0 = 0; j0 < n; j0 += BC) {
-        // stage the candidate tile (operand rows are padded, so no bounds checks)
-        {
-            const uint8_t* src = ops + (int64_t)j0 * S::ROW_BYTES;
-            constexpr int CHUNKS = BC * S::ROW_BYTES / 16;
-            constexpr int CPR = S::ROW_BYTES / 16;
-            for (int c = tid; c < CHUNKS; c += 256) {
-                int r = c / CPR, o = c % CPR;
-                intx4 v = *reinterpret_cast<const intx4*>(src + (int64_t)r * S::ROW_BYTES + o * 16);
-                *reinterpret_cast<intx4*>(s_tile + r * S::RS + o * 16) = v;
-            }
-            if (tid < BC) {
-                s_norm[tid] = ninit[j0 + tid];
-                if constexpr (P == SG_PREC_FP8) s_sexp[tid] = sexp[j0 + tid];
+    // tile staging: global -> registers (prefetch) -> LDS
+    intx4 pre[CPT];
+    float pre_norm = 0.f;
+    int32_t pre_sexp = 0;
+    auto prefetch = [&](int j0) {
+        const uint8_t* src = ops + (int64_t)j0 * RB;
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int c = tid + u * NT;
+            if (c < CHUNKS) pre[u] = *reinterpret_cast<const intx4*>(src + (int64_t)c * 16);
+        }
+        if (tid < BC) {
+            pre_norm = ninit[j0 + tid];
+            if constexpr (P == SG_PREC_FP8) pre_sexp = sexp[j0 + tid];
+        }
+    };
+    auto commit = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int c = tid + u * NT;
+            if (c < CHUNKS) {
+                const int r = c / (RB / 16), o = c % (RB / 16);
+                *reinterpret_cast<intx4*>(&s_tile[buf][r * RS + o * 16]) = pre[u];
             }
         }
-        __syncthreads();
+        if (tid < BC) {
+            s_norm[buf][tid] = pre_norm;
+            if constexpr (P == SG_PREC_FP8) s_sexp[buf][tid] = pre_sexp;
+        }
+    };
 
-#pragma unroll 1
-        for (int sub = 0; sub < BC / 32; ++sub) {
-            const int cbase = j0 + sub * 32;
-            floatx16 acc;
+    // insert the candidates of one subtile that beat the threshold; entries
+    // that find the buffer full are flagged in ovf and re-inserted after the
+    // merge that empties it
+    auto epilogue = [&](floatx16 (&acc)[QB], int cbase) {
 #pragma unroll
-            for (int i = 0; i < 16; ++i) acc[i] = s_norm[sub * 32 + out_row(i, l)];
-            int a_scale = 127;
-            if constexpr (P == SG_PREC_FP8) a_scale = 127 + s_sexp[sub * 32 + (l & 31)];
-            acc = mfma_tile<P, NSTEP>(s_tile + (sub * 32 + (l & 31)) * S::RS + h * (S::ROW_BYTES / 2),
-                                      qf, acc, a_scale, q_scale);
-            if (cbase == qbase) {            // exclude self by index
+        for (int b = 0; b < QB; ++b) {
+            if (cbase == qblk0 + b * 32) {          // self excluded by index
 #pragma unroll
                 for (int i = 0; i < 16; ++i)
-                    if (out_row(i, l) == (l & 31)) acc[i] = __builtin_inff();
+                    if (out_row(i, l) == ql) acc[b][i] = __builtin_inff();
             }
-            bool any = false;
+        }
+        bool any = false;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) any |= acc[i] < thr;
-            if (__builtin_amdgcn_ballot_w64(any)) {
+        for (int b = 0; b < QB; ++b)
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    if (acc[i] < thr) {
-                        int slot = atomicAdd(&s_cnt[qloc], 1);
-                        s_buf[qloc * CB + slot] = make_key(acc[i], cbase + out_row(i, l));
-                    }
+            for (int i = 0; i < 16; ++i) any |= acc[b][i] < thr[b];
+        if (!__builtin_amdgcn_ballot_w64(any)) return;
+        uint32_t ovf[QB];
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+            ovf[b] = 0;
+            const int qloc = (w * QB + b) * 32 + ql;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                if (acc[b][i] < thr[b]) {
+                    const int slot = atomicAdd(&s_cnt[qloc], 1);
+                    if (slot < CB)
+                        s_buf[qloc * CB + slot] = make_key(acc[b][i], cbase + out_row(i, l));
+                    else
+                        ovf[b] |= 1u << i;
                 }
+            }
+        }
+        bool anyovf = false;
+#pragma unroll
+        for (int b = 0; b < QB; ++b) anyovf |= ovf[b] != 0;
+        if (!__builtin_amdgcn_ballot_w64(anyovf)) return;
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+            // queries of this block with an overflow in either lane half
+            const uint64_t m = __builtin_amdgcn_ballot_w64(ovf[b] != 0);
+            uint32_t need = (uint32_t)m | (uint32_t)(m >> 32);
+            while (need) {
+                const int qi = __builtin_ctz(need);
+                need &= need - 1;
+                const int qloc = (w * QB + b) * 32 + qi;
+                const float t = merge_query<KSEL>(state + (qblk0 + b * 32 + qi) * KSEL,
+                                                  s_buf + qloc * CB, CB);
+                if (ql == qi) thr[b] = t;
+                if (l == 0) s_cnt[qloc] = 0;
                 asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-                uint64_t need = __builtin_amdgcn_ballot_w64(l < 32 && s_cnt[qloc] > CB - 32);
-                while (need) {
-                    int qi = __builtin_ctzll(need);
-                    need &= need - 1;
-                    float t = merge_query<KSEL>(state + (qbase + qi) * KSEL, s_buf + (w * 32 + qi) * CB,
-                                                &s_cnt[w * 32 + qi], s_scr[w]);
-                    if ((l & 31) == qi) thr = t;
+            }
+            const int qloc = (w * QB + b) * 32 + ql;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                if ((ovf[b] >> i & 1u) && acc[b][i] < thr[b]) {
+                    const int slot = atomicAdd(&s_cnt[qloc], 1);
+                    s_buf[qloc * CB + slot] = make_key(acc[b][i], cbase + out_row(i, l));
                 }
             }
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    };
+
+    auto compute = [&](floatx16 (&acc)[QB], int buf, int sub) {
+        floatx4 nv[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+            nv[g] = *reinterpret_cast<const floatx4*>(&s_norm[buf][sub * 32 + g * 8 + h * 4]);
+        int a_scale = 127;
+        if constexpr (P == SG_PREC_FP8) a_scale = 127 + s_sexp[buf][sub * 32 + ql];
+        const uint8_t* arow = &s_tile[buf][(sub * 32 + ql) * RS + h * (RB / 2)];
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[b][i] = nv[i >> 2][i & 3];
+        }
+        if constexpr (QB == 1) {
+            acc[0] = mfma_tile<P, NSTEP>(arow, qf[0], acc[0], a_scale, q_scale[0]);
+        } else {
+#pragma unroll
+            for (int b = 0; b < QB; ++b) acc[b] = mfma_tile<P, NSTEP>(arow, qf[b], acc[b], a_scale, q_scale[b]);
+        }
+    };
+
+    const int ntiles = (n + BC - 1) / BC;
+    prefetch(0);
+    commit(0);
+    __syncthreads();
+    if (ntiles > 1) prefetch(BC);
+    for (int t = 0; t < ntiles; ++t) {
+        const int buf = t & 1;
+        const int j0 = t * BC;
+        floatx16 accA[QB], accB[QB];
+        compute(accA, buf, 0);
+#pragma unroll
+        for (int sub = 0; sub < NSUB; ++sub) {
+            if (sub % 2 == 0) {
+                if (sub + 1 < NSUB) compute(accB, buf, sub + 1);
+                epilogue(accA, j0 + sub * 32);
+            } else {
+                if (sub + 1 < NSUB) compute(accA, buf, sub + 1);
+                epilogue(accB, j0 + sub * 32);
+            }
+        }
+        if (t + 1 < ntiles) {
+            commit(buf ^ 1);
+            if (t + 2 < ntiles) prefetch((t + 2) * BC);
         }
         __syncthreads();
     }
     // drain the buffers
-    {
-        uint64_t need = __builtin_amdgcn_ballot_w64(l < 32 && s_cnt[qloc] > 0);
+#pragma unroll
+    for (int b = 0; b < QB; ++b) {
+        const int qloc = (w * QB + b) * 32 + ql;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(l < 32 && s_cnt[qloc] > 0);
+        uint32_t need = (uint32_t)m;
         while (need) {
-            int qi = __builtin_ctzll(need);
+            const int qi = __builtin_ctz(need);
             need &= need - 1;
-            merge_query<KSEL>(state + (qbase + qi) * KSEL, s_buf + (w * 32 + qi) * CB,
-                              &s_cnt[w * 32 + qi], s_scr[w]);
+            const int ql2 = (w * QB + b) * 32 + qi;
+            merge_query<KSEL>(state + (qblk0 + b * 32 + qi) * KSEL, s_buf + ql2 * CB,
+                              __builtin_amdgcn_readfirstlane(s_cnt[ql2]));
         }
     }
-    (void)gstate;
     if (nbr) {
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        for (int qi = 0; qi < 32; ++qi) {
-            int64_t q = qbase + qi;
+        for (int qi = 0; qi < 32 * QB; ++qi) {
+            const int64_t q = qblk0 + qi;
             if (q >= n) break;
             const float qn = nout[q];
             for (int t = l; t < k_out; t += 64) {
-                uint64_t key = state[q * KSEL + t];
+                const uint64_t key = state[q * KSEL + t];
                 nbr[q * k_out + t] = key_id(key);
                 if (dist)
                     dist[q * k_out + t] = key == EMPTY_KEY ? __builtin_inff() : (key_dist(key) + qn) * osc;
@@ -647,10 +770,10 @@ typedef void (*topk_fn)(const uint8_t*, const float*, const float*, const int32_
 template <int P, int NSTEP>
 topk_fn pick_ksel(int ksel) {
     switch (ksel) {
-        case 32: return dist_topk_kernel<P, NSTEP, 32>;
-        case 64: return dist_topk_kernel<P, NSTEP, 64>;
-        case 128: return dist_topk_kernel<P, NSTEP, 128>;
-        default: return dist_topk_kernel<P, NSTEP, 256>;
+        case 32: return dist_topk_kernel<P, NSTEP, 32, TWAVES, TQB>;
+        case 64: return dist_topk_kernel<P, NSTEP, 64, TWAVES, TQB>;
+        case 128: return dist_topk_kernel<P, NSTEP, 128, TWAVES, TQB>;
+        default: return dist_topk_kernel<P, NSTEP, 256, TWAVES, TQB>;
     }
 }
 
@@ -805,7 +928,7 @@ extern "C" sg_status sg_knn_graph(const void* X, sg_dtype dtype, int64_t n, int3
         const float qmul = plain_ip ? -1.0f : -2.0f;
         const float osc = knn::norm_corrected_ip(metric, prec) ? 0.5f : 1.0f;
         profile_record(s, true);
-        fn<<<(unsigned)(L.n_pad / knn::BQ), 256, 0, s>>>(ops, ninit, nout, sexp, (int)n, qmul, osc, state,
+        fn<<<(unsigned)(L.n_pad / knn::BQ), knn::TWAVES * 64, 0, s>>>(ops, ninit, nout, sexp, (int)n, qmul, osc, state,
                                                           final_here ? nbr : nullptr,
                                                           final_here ? dist : nullptr, k);
         SG_LAUNCH_CHECK();
