@@ -136,6 +136,22 @@ sg_status sg_knn_graph(const void* X, sg_dtype dtype, int64_t n, int32_t d, int6
                        float* dist, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * sg_knn_rows -- exact (or re-ranked) kNN of listed rows against all rows
+ *
+ * The same computation as sg_knn_graph restricted to the query rows
+ * rows[0..nq) (device int64 row indices of X): row r of nbr / dist is the
+ * list of X row rows[r] over all n rows of X, itself excluded by index.  Used
+ * to judge a build on a sample of rows.  Listed rows outside [0, n) give
+ * empty lists.
+ * ---------------------------------------------------------------------- */
+sg_status sg_knn_rows_workspace_size(int64_t n, int32_t d, int64_t nq, int32_t k, sg_prec prec,
+                                     int32_t rerank, size_t* bytes);
+sg_status sg_knn_rows(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t ld,
+                      sg_metric metric, const int64_t* rows, int64_t nq, int32_t k, sg_prec prec,
+                      int32_t rerank, int32_t* nbr, float* dist, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* ------------------------------------------------------------------------
  * sg_prune -- rank-based edge prune + reverse-edge pass to out-degree R
  *
  * The graph-optimisation step of the CAGRA shard build the paper uses

@@ -58,6 +58,8 @@ _SIGS = {
                            i64, vp, sz, vp]),
     "sg_knn_graph_workspace_size": (i32, [i64, i32, i32, i32, i32, psz]),
     "sg_knn_graph": (i32, [vp, i32, i64, i32, i64, i32, i32, i32, i32, vp, vp, vp, sz, vp]),
+    "sg_knn_rows_workspace_size": (i32, [i64, i32, i64, i32, i32, i32, psz]),
+    "sg_knn_rows": (i32, [vp, i32, i64, i32, i64, i32, vp, i64, i32, i32, i32, vp, vp, vp, sz, vp]),
     "sg_prune_workspace_size": (i32, [i64, i32, i32, psz]),
     "sg_prune": (i32, [vp, i64, i32, i32, vp, vp, sz, vp]),
     "sg_merge_workspace_size": (i32, [i32, vp, i64, psz]),
@@ -156,6 +158,21 @@ def sg_knn_graph(X, k, metric="l2", prec="fp32", rerank=0, dist=True, stream=Non
         dd = torch.empty((n, k), dtype=torch.float32, device=X.device) if dist else None
     _check("sg_knn_graph", L.sg_knn_graph(_ptr(X), dt, n, d, ld, m, k, p, rerank, _ptr(nbr), _ptr(dd),
                                           _ptr(ws), ws.numel(), _stream(stream)))
+    return nbr, dd
+
+
+def sg_knn_rows(X, rows, k, metric="l2", prec="fp32", rerank=0, stream=None):
+    """kNN of the listed rows of X against all rows: (nbr int32 [nq,k], dist float32 [nq,k])."""
+    L = lib()
+    dt, n, d, ld = _rows(X)
+    r = torch.as_tensor(rows, dtype=torch.int64).to(X.device).contiguous()
+    nq = r.numel()
+    m, p = METRICS[metric], PRECS[prec]
+    ws = _ws.get(_size(L.sg_knn_rows_workspace_size, n, d, nq, k, p, rerank), X.device, "knn_rows")
+    nbr = torch.empty((nq, k), dtype=torch.int32, device=X.device)
+    dd = torch.empty((nq, k), dtype=torch.float32, device=X.device)
+    _check("sg_knn_rows", L.sg_knn_rows(_ptr(X), dt, n, d, ld, m, _ptr(r), nq, k, p, rerank, _ptr(nbr),
+                                        _ptr(dd), _ptr(ws), ws.numel(), _stream(stream)))
     return nbr, dd
 
 

@@ -135,20 +135,22 @@ __host__ __device__ inline bool norm_corrected_ip(int metric, int prec) {
     return metric == SG_IP && (prec == SG_PREC_BF16 || prec == SG_PREC_FP8);
 }
 
-// One wave per operand row.  Writes the converted row (zero padded to DP),
+// One wave per operand row (source row rowmap[row], or row itself when
+// rowmap is NULL).  Writes the converted row (zero padded to DP),
 // the accumulator start of the row as a candidate (ninit, +inf for padding
 // rows), its output offset as a query (nout) and, for FP8, the row's scale
 // exponent.
 __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_t n, int d, int64_t ld,
-                            int64_t n_pad, int DP, int prec, int metric, uint8_t* __restrict__ ops,
-                            float* __restrict__ ninit, float* __restrict__ nout,
-                            int32_t* __restrict__ sexp) {
+                            const int64_t* __restrict__ rowmap, int64_t n_src, int64_t n_pad, int DP,
+                            int prec, int metric, uint8_t* __restrict__ ops, float* __restrict__ ninit,
+                            float* __restrict__ nout, int32_t* __restrict__ sexp) {
     const int l = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (row >= n_pad) return;
     const int eb = elem_bytes(prec);
     uint8_t* out = ops + row * (int64_t)DP * eb;
-    if (row >= n) {
+    const int64_t src_row = row < n ? (rowmap ? rowmap[row] : row) : -1;
+    if (src_row < 0 || src_row >= n_src) {      // padding (or an out-of-range listed row)
         for (int t = l; t < DP; t += 64) {
             if (eb == 4) reinterpret_cast<float*>(out)[t] = 0.f;
             else if (eb == 2) reinterpret_cast<uint16_t*>(out)[t] = 0;
@@ -161,7 +163,7 @@ __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_t n, in
         }
         return;
     }
-    const int64_t base = row * ld;
+    const int64_t base = src_row * ld;
     int sx = 0;
     float inv = 1.0f;
     if (prec == SG_PREC_FP8) {
@@ -429,9 +431,10 @@ __device__ float merge_query(uint64_t* __restrict__ gstate, const uint64_t* buf,
 // subtile s so that both run at once.
 template <int P, int NSTEP, int KSEL, int WAVES, int QB>
 __global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_kernel(
-    const uint8_t* __restrict__ ops, const float* __restrict__ ninit, const float* __restrict__ nout,
-    const int32_t* __restrict__ sexp, int n, float qmul, float osc, uint64_t* __restrict__ state,
-    int32_t* __restrict__ nbr, float* __restrict__ dist, int k_out) {
+    const uint8_t* __restrict__ ops, const float* __restrict__ ninit, const int32_t* __restrict__ sexp,
+    int n, const uint8_t* __restrict__ qops, const int64_t* __restrict__ qid,
+    const float* __restrict__ qnout, const int32_t* __restrict__ qsexp, int nq, float qmul, float osc,
+    uint64_t* __restrict__ state, int32_t* __restrict__ nbr, float* __restrict__ dist, int k_out) {
     using S = Shape<P, NSTEP>;
     constexpr int BC = S::BC, NSUB = S::NSUB, RB = S::ROW_BYTES, RS = S::RS;
     constexpr int NT = WAVES * 64;
@@ -456,14 +459,16 @@ __global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_kernel(
     Frag<P, NSTEP> qf[QB];
     int q_scale[QB];
     float thr[QB];
+    int64_t qself[QB];    // candidate id equal to this lane's query (excluded); -1 for none
 #pragma unroll
     for (int b = 0; b < QB; ++b) {
         const int64_t qg = qblk0 + b * 32 + ql;
-        load_frag<P, NSTEP>(qf[b], ops + qg * RB + h * (RB / 2));
+        load_frag<P, NSTEP>(qf[b], qops + qg * RB + h * (RB / 2));
         scale_query<P, NSTEP>(qf[b], qmul);
         q_scale[b] = 127;
-        if constexpr (P == SG_PREC_FP8) q_scale[b] = 127 + sexp[qg] + 1;
+        if constexpr (P == SG_PREC_FP8) q_scale[b] = 127 + qsexp[qg] + 1;
         thr[b] = __builtin_inff();
+        qself[b] = qg < nq ? (qid ? qid[qg] : qg) : -1;
     }
 
     // tile staging: global -> registers (prefetch) -> LDS
@@ -503,10 +508,12 @@ __global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_kernel(
     auto epilogue = [&](floatx16 (&acc)[QB], int cbase) {
 #pragma unroll
         for (int b = 0; b < QB; ++b) {
-            if (cbase == qblk0 + b * 32) {          // self excluded by index
+            // self excluded by index
+            const bool mine = qself[b] >= cbase && qself[b] < cbase + 32;
+            if (__builtin_amdgcn_ballot_w64(mine)) {
 #pragma unroll
                 for (int i = 0; i < 16; ++i)
-                    if (out_row(i, l) == ql) acc[b][i] = __builtin_inff();
+                    if (cbase + out_row(i, l) == qself[b]) acc[b][i] = __builtin_inff();
             }
         }
         bool any = false;
@@ -628,8 +635,8 @@ __global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_kernel(
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         for (int qi = 0; qi < 32 * QB; ++qi) {
             const int64_t q = qblk0 + qi;
-            if (q >= n) break;
-            const float qn = nout[q];
+            if (q >= nq) break;
+            const float qn = qnout[q];
             for (int t = l; t < k_out; t += 64) {
                 const uint64_t key = state[q * KSEL + t];
                 nbr[q * k_out + t] = key_id(key);
@@ -685,7 +692,9 @@ __device__ inline void wave_sort_multi(uint64_t (&v)[PER]) {
 template <int PER>
 __global__ __launch_bounds__(256) void rerank_kernel(const void* __restrict__ X, int dtype, int64_t n,
                                                      int d, int64_t ld, int metric,
-                                                     const uint64_t* __restrict__ cand, int kstate,
+                                                     const int64_t* __restrict__ rowmap,
+                                                     int64_t n_src, const uint64_t* __restrict__ cand,
+                                                     int kstate,
                                                      int c, int k, int32_t* __restrict__ nbr,
                                                      float* __restrict__ dist) {
     extern __shared__ float s_q[];   // 4 waves x d
@@ -693,8 +702,11 @@ __global__ __launch_bounds__(256) void rerank_kernel(const void* __restrict__ X,
     const int w = threadIdx.x >> 6;
     const int64_t i = (int64_t)blockIdx.x * 4 + w;
     float* q = s_q + w * d;
-    if (i < n)
-        for (int t = l; t < d; t += 64) q[t] = load_elem(X, dtype, i * ld + t);
+    if (i < n) {
+        int64_t src = rowmap ? rowmap[i] : i;
+        if (src < 0 || src >= n_src) src = -1;
+        for (int t = l; t < d; t += 64) q[t] = src >= 0 ? load_elem(X, dtype, src * ld + t) : 0.f;
+    }
     __syncthreads();
     if (i >= n) return;
     uint64_t v[PER];
@@ -764,8 +776,9 @@ inline Layout layout(int64_t n, int d, int k, int prec, int rerank) {
     return L;
 }
 
-typedef void (*topk_fn)(const uint8_t*, const float*, const float*, const int32_t*, int, float, float,
-                        uint64_t*, int32_t*, float*, int);
+typedef void (*topk_fn)(const uint8_t*, const float*, const int32_t*, int, const uint8_t*,
+                        const int64_t*, const float*, const int32_t*, int, float, float, uint64_t*,
+                        int32_t*, float*, int);
 
 template <int P, int NSTEP>
 topk_fn pick_ksel(int ksel) {
@@ -892,6 +905,107 @@ extern "C" sg_status sg_knn_graph_workspace_size(int64_t n, int32_t d, int32_t k
     });
 }
 
+namespace sg {
+namespace knn {
+
+inline int64_t pad_rows(int64_t m) { return (m + PAD_ROWS - 1) / PAD_ROWS * PAD_ROWS; }
+
+// Workspace of one call: candidate operands + side arrays for all n rows,
+// and, for a row subset, the query operands + side arrays of its nq rows.
+inline size_t total_bytes(const Layout& L, int64_t nq, int prec) {
+    size_t t = L.total;
+    if (nq >= 0) {
+        const int64_t nqp = pad_rows(nq);
+        t += align_up((size_t)nqp * L.DP * elem_bytes(prec), 256) + 2 * align_up((size_t)nqp * 4, 256) +
+             align_up((size_t)nqp * 4, 256) + align_up((size_t)nqp * 8, 256);
+        // the state then covers the query rows only
+        t -= align_up(L.state_bytes, 256);
+        t += align_up((size_t)nqp * L.ksel * 8, 256);
+    }
+    return t;
+}
+
+// kNN of rows (nq >= 0: the listed rows; nq < 0: every row) against all n rows.
+void run(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int k, int prec,
+         int rerank, const int64_t* rows, int64_t nq, int32_t* nbr, float* dist, void* ws,
+         size_t ws_bytes, hipStream_t s) {
+    if (rerank == k) rerank = 0;
+    Layout L = layout_k(n, d, k, prec, rerank);
+    int used = 0;
+    topk_fn fn = pick_kernel(prec, padded_d(prec, d), L.ksel, &used);
+    if (!fn) {
+        set_error("sg_knn: d too large for the resident-query kernel of this precision");
+        throw Fail{SG_ERR_UNSUPPORTED};
+    }
+    const size_t need = total_bytes(L, rows ? nq : -1, prec);
+    if (ws_bytes < need || ws == nullptr) {
+        set_error("sg_knn: workspace too small (need " + std::to_string(need) + " bytes)");
+        throw Fail{SG_ERR_WORKSPACE};
+    }
+    const bool subset = rows != nullptr;
+    const int64_t nq_rows = subset ? nq : n;
+    const int64_t nq_pad = subset ? pad_rows(nq) : L.n_pad;
+    Carver cv(ws);
+    uint8_t* ops = cv.take<uint8_t>(L.ops_bytes);
+    float* ninit = cv.take<float>(L.n_pad);
+    float* nout = cv.take<float>(L.n_pad);
+    int32_t* sexp = prec == SG_PREC_FP8 ? cv.take<int32_t>(L.n_pad) : nullptr;
+    uint8_t* qops = ops;
+    float* qninit = ninit;
+    float* qnout = nout;
+    int32_t* qsexp = sexp;
+    const int64_t* qid = nullptr;
+    if (subset) {
+        qops = cv.take<uint8_t>((size_t)nq_pad * L.DP * elem_bytes(prec));
+        qninit = cv.take<float>(nq_pad);
+        qnout = cv.take<float>(nq_pad);
+        qsexp = cv.take<int32_t>(nq_pad);
+        int64_t* qid_w = cv.take<int64_t>(nq_pad);
+        fill<int64_t>(qid_w, -1, nq_pad, s);
+        SG_HIP(hipMemcpyAsync(qid_w, rows, nq * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+        qid = qid_w;
+    }
+    uint64_t* state = cv.take<uint64_t>((size_t)nq_pad * L.ksel);
+
+    prep_kernel<<<(unsigned)cdiv(L.n_pad, 4), 256, 0, s>>>(X, dtype, n, d, ld, nullptr, n, L.n_pad, L.DP,
+                                                            prec, metric, ops, ninit, nout, sexp);
+    SG_LAUNCH_CHECK();
+    if (subset) {
+        prep_kernel<<<(unsigned)cdiv(nq_pad, 4), 256, 0, s>>>(X, dtype, nq, d, ld, rows, n, nq_pad, L.DP,
+                                                               prec, metric, qops, qninit, qnout, qsexp);
+        SG_LAUNCH_CHECK();
+    }
+    fill<uint64_t>(state, EMPTY_KEY, nq_pad * L.ksel, s);
+    const bool final_here = rerank == 0;
+    const bool plain_ip = metric == SG_IP && !norm_corrected_ip(metric, prec);
+    const float qmul = plain_ip ? -1.0f : -2.0f;
+    const float osc = norm_corrected_ip(metric, prec) ? 0.5f : 1.0f;
+    profile_record(s, true);
+    fn<<<(unsigned)(nq_pad / BQ), TWAVES * 64, 0, s>>>(ops, ninit, sexp, (int)n, qops, qid, qnout, qsexp,
+                                                     (int)nq_rows, qmul, osc, state,
+                                                     final_here ? nbr : nullptr,
+                                                     final_here ? dist : nullptr, k);
+    SG_LAUNCH_CHECK();
+    profile_record(s, false);
+    if (!final_here) {
+        const size_t shm = (size_t)4 * d * sizeof(float);
+        const unsigned grid = (unsigned)cdiv(nq_rows, 4);
+        if (rerank <= 64)
+            rerank_kernel<1><<<grid, 256, shm, s>>>(X, dtype, nq_rows, d, ld, metric, rows, n, state, L.ksel,
+                                                    rerank, k, nbr, dist);
+        else if (rerank <= 128)
+            rerank_kernel<2><<<grid, 256, shm, s>>>(X, dtype, nq_rows, d, ld, metric, rows, n, state, L.ksel,
+                                                    rerank, k, nbr, dist);
+        else
+            rerank_kernel<4><<<grid, 256, shm, s>>>(X, dtype, nq_rows, d, ld, metric, rows, n, state, L.ksel,
+                                                    rerank, k, nbr, dist);
+        SG_LAUNCH_CHECK();
+    }
+}
+
+}  // namespace knn
+}  // namespace sg
+
 extern "C" sg_status sg_knn_graph(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t ld,
                                   sg_metric metric, int32_t k, sg_prec prec, int32_t rerank,
                                   int32_t* nbr, float* dist, void* ws, size_t ws_bytes, void* stream) {
@@ -899,53 +1013,32 @@ extern "C" sg_status sg_knn_graph(const void* X, sg_dtype dtype, int64_t n, int3
         knn::check_args(X, dtype, n, d, ld, metric, k, prec, rerank);
         SG_REQUIRE(nbr != nullptr || n == 0, "nbr is NULL");
         if (n == 0) return;
+        knn::run(X, dtype, n, d, ld, metric, k, prec, rerank, nullptr, -1, nbr, dist, ws, ws_bytes,
+                 as_stream(stream));
+    });
+}
+
+extern "C" sg_status sg_knn_rows_workspace_size(int64_t n, int32_t d, int64_t nq, int32_t k, sg_prec prec,
+                                                int32_t rerank, size_t* bytes) {
+    return guarded([&] {
+        SG_REQUIRE(bytes != nullptr, "bytes is NULL");
+        SG_REQUIRE(n >= 0 && nq >= 0 && d >= 1 && d <= 1024 && k >= 1 && k <= 256, "bad sizes");
         if (rerank == k) rerank = 0;
         knn::Layout L = knn::layout_k(n, d, k, prec, rerank);
-        int used = 0;
-        knn::topk_fn fn = knn::pick_kernel(prec, knn::padded_d(prec, d), L.ksel, &used);
-        if (!fn) {
-            set_error("sg_knn_graph: d too large for the resident-query kernel of this precision");
-            throw Fail{SG_ERR_UNSUPPORTED};
-        }
-        if (ws_bytes < L.total || ws == nullptr) {
-            set_error("sg_knn_graph: workspace too small (need " + std::to_string(L.total) + " bytes)");
-            throw Fail{SG_ERR_WORKSPACE};
-        }
-        hipStream_t s = as_stream(stream);
-        Carver cv(ws);
-        uint8_t* ops = cv.take<uint8_t>(L.ops_bytes);
-        float* ninit = cv.take<float>(L.n_pad);
-        float* nout = cv.take<float>(L.n_pad);
-        int32_t* sexp = prec == SG_PREC_FP8 ? cv.take<int32_t>(L.n_pad) : nullptr;
-        uint64_t* state = cv.take<uint64_t>((size_t)L.n_pad * L.ksel);
+        *bytes = (n == 0 || nq == 0) ? 0 : knn::total_bytes(L, nq, prec);
+    });
+}
 
-        knn::prep_kernel<<<(unsigned)cdiv(L.n_pad, 4), 256, 0, s>>>(X, dtype, n, d, ld, L.n_pad, L.DP,
-                                                                     prec, metric, ops, ninit, nout, sexp);
-        SG_LAUNCH_CHECK();
-        fill<uint64_t>(state, EMPTY_KEY, (int64_t)L.n_pad * L.ksel, s);
-        const bool final_here = rerank == 0;
-        const bool plain_ip = metric == SG_IP && !knn::norm_corrected_ip(metric, prec);
-        const float qmul = plain_ip ? -1.0f : -2.0f;
-        const float osc = knn::norm_corrected_ip(metric, prec) ? 0.5f : 1.0f;
-        profile_record(s, true);
-        fn<<<(unsigned)(L.n_pad / knn::BQ), knn::TWAVES * 64, 0, s>>>(ops, ninit, nout, sexp, (int)n, qmul, osc, state,
-                                                          final_here ? nbr : nullptr,
-                                                          final_here ? dist : nullptr, k);
-        SG_LAUNCH_CHECK();
-        profile_record(s, false);
-        if (!final_here) {
-            size_t shm = (size_t)4 * d * sizeof(float);
-            unsigned grid = (unsigned)cdiv(n, 4);
-            if (rerank <= 64)
-                knn::rerank_kernel<1><<<grid, 256, shm, s>>>(X, dtype, n, d, ld, metric, state, L.ksel,
-                                                             rerank, k, nbr, dist);
-            else if (rerank <= 128)
-                knn::rerank_kernel<2><<<grid, 256, shm, s>>>(X, dtype, n, d, ld, metric, state, L.ksel,
-                                                             rerank, k, nbr, dist);
-            else
-                knn::rerank_kernel<4><<<grid, 256, shm, s>>>(X, dtype, n, d, ld, metric, state, L.ksel,
-                                                             rerank, k, nbr, dist);
-            SG_LAUNCH_CHECK();
-        }
+extern "C" sg_status sg_knn_rows(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t ld,
+                                 sg_metric metric, const int64_t* rows, int64_t nq, int32_t k,
+                                 sg_prec prec, int32_t rerank, int32_t* nbr, float* dist, void* ws,
+                                 size_t ws_bytes, void* stream) {
+    return guarded([&] {
+        knn::check_args(X, dtype, n, d, ld, metric, k, prec, rerank);
+        SG_REQUIRE(nq >= 0 && nq < (1ll << 31), "nq out of range");
+        if (n == 0 || nq == 0) return;
+        SG_REQUIRE(rows != nullptr && nbr != nullptr, "NULL pointer");
+        knn::run(X, dtype, n, d, ld, metric, k, prec, rerank, rows, nq, nbr, dist, ws, ws_bytes,
+                 as_stream(stream));
     });
 }

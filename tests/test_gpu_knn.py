@@ -114,3 +114,22 @@ def test_knn_deterministic():
     a = sg.sg_knn_graph(Xg, 32, "l2", "fp32")
     b = sg.sg_knn_graph(Xg, 32, "l2", "fp32")
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "f16"])
+def test_knn_rows_u8_bit_exact(prec):
+    X = _u8(3000, 128, seed=77)
+    rows = np.random.default_rng(1).choice(3000, size=300, replace=False)
+    nbr, dist = sg.sg_knn_rows(torch.from_numpy(X).to(DEV), rows, 64, "l2", prec)
+    onbr, odist = oracle.knn(oracle.widen(X), 64, rows=rows)
+    np.testing.assert_array_equal(nbr.cpu().numpy(), onbr)
+    np.testing.assert_array_equal(dist.cpu().numpy(), odist.astype(np.float32))
+
+
+def test_knn_rows_rerank_and_full_agree():
+    X = synthdata.unit_rows(synthdata.mixture(2500, 96, 30, 0.15, seed=3))
+    Xg = torch.from_numpy(X).to(DEV)
+    rows = np.arange(0, 2500, 7)
+    full, _ = sg.sg_knn_graph(Xg, 32, "ip", "bf16", rerank=64)
+    sub, _ = sg.sg_knn_rows(Xg, rows, 32, "ip", "bf16", rerank=64)
+    np.testing.assert_array_equal(sub.cpu().numpy(), full.cpu().numpy()[rows])
