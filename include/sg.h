@@ -125,9 +125,10 @@ sg_status sg_partition(const void* X, sg_dtype dtype, int64_t n, int32_t d, int6
  *           are re-scored with the exact FP32 difference-form distance and
  *           the best k by (delta, id) kept.
  *  nbr    : out, n x k int32.   dist: out, n x k FP32, may be NULL.
- *  d      : 1..1024; the query tile of this kernel is register resident, which
- *           bounds d by precision: FP32 <= 128, FP16 / BF16 <= 256, FP8 <= 512
- *           (larger d returns SG_ERR_UNSUPPORTED).
+ *  d      : 1..1024 for FP32 and FP8, 1..768 for FP16 / BF16 (larger d returns
+ *           SG_ERR_UNSUPPORTED).  Queries are register resident up to FP32
+ *           d <= 128 and 16-bit / FP8 d <= 768 / 1024; wider FP32 rows use a
+ *           k-streamed kernel.
  * ---------------------------------------------------------------------- */
 sg_status sg_knn_graph_workspace_size(int64_t n, int32_t d, int32_t k, sg_prec prec,
                                       int32_t rerank, size_t* bytes);

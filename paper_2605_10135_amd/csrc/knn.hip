@@ -423,12 +423,129 @@ __device__ float merge_query(uint64_t* __restrict__ gstate, const uint64_t* buf,
     return key_dist(last);
 }
 
-// Fused distance tile + top-k.  WAVES waves per workgroup, QB blocks of 32
-// queries per wave (NQ = 32*QB*WAVES queries per workgroup).  Candidate
-// tiles (BC rows) are staged in LDS, double buffered, the next tile already
-// in flight in registers while the current one is computed.  Within a tile
-// the MFMAs of subtile s+1 are issued before the selection epilogue of
-// subtile s so that both run at once.
+// Per-wave selection state: the admission threshold of each of the wave's
+// 32*QB queries (lanes l and l+32 share query l%32 of each block), the id
+// excluded as the query itself, and the LDS buffers / counters and workspace
+// top-KSEL lists of those queries.
+template <int KSEL, int QB>
+struct Selector {
+    float thr[QB];
+    int64_t qself[QB];
+    uint64_t* state;   // state row of the wave's first query
+    uint64_t* buf;     // LDS buffers of the wave's queries (32*QB*CB keys)
+    int* cnt;          // LDS counters of the wave's queries
+
+    // Admit the candidates of one 32x32 subtile (rows cbase..cbase+31) that
+    // beat the thresholds.  Keys that find a buffer full are flagged, the
+    // buffer is merged into its list (lowering the threshold) and the flagged
+    // keys re-admitted against the new threshold.
+    __device__ void admit(floatx16 (&acc)[QB], int64_t cbase) {
+        const int l = lane_id();
+        const int ql = l & 31;
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+            const bool mine = qself[b] >= cbase && qself[b] < cbase + 32;
+            if (__builtin_amdgcn_ballot_w64(mine)) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    if (cbase + out_row(i, l) == qself[b]) acc[b][i] = __builtin_inff();
+            }
+        }
+        bool any = false;
+#pragma unroll
+        for (int b = 0; b < QB; ++b)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) any |= acc[b][i] < thr[b];
+        if (!__builtin_amdgcn_ballot_w64(any)) return;
+        uint32_t ovf[QB];
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+            ovf[b] = 0;
+            const int qq = b * 32 + ql;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                if (acc[b][i] < thr[b]) {
+                    const int slot = atomicAdd(&cnt[qq], 1);
+                    if (slot < CB)
+                        buf[qq * CB + slot] = make_key(acc[b][i], (int32_t)(cbase + out_row(i, l)));
+                    else
+                        ovf[b] |= 1u << i;
+                }
+            }
+        }
+        bool anyovf = false;
+#pragma unroll
+        for (int b = 0; b < QB; ++b) anyovf |= ovf[b] != 0;
+        if (!__builtin_amdgcn_ballot_w64(anyovf)) return;
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+            const uint64_t m = __builtin_amdgcn_ballot_w64(ovf[b] != 0);
+            uint32_t need = (uint32_t)m | (uint32_t)(m >> 32);
+            while (need) {
+                const int qi = __builtin_ctz(need);
+                need &= need - 1;
+                const int qq = b * 32 + qi;
+                const float t = merge_query<KSEL>(state + (int64_t)qq * KSEL, buf + qq * CB, CB);
+                if (ql == qi) thr[b] = t;
+                if (l == 0) cnt[qq] = 0;
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            }
+            const int qq = b * 32 + ql;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                if ((ovf[b] >> i & 1u) && acc[b][i] < thr[b]) {
+                    const int slot = atomicAdd(&cnt[qq], 1);
+                    buf[qq * CB + slot] = make_key(acc[b][i], (int32_t)(cbase + out_row(i, l)));
+                }
+            }
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    }
+
+    // Merge every non-empty buffer (end of the candidate stream).
+    __device__ void drain() {
+        const int l = lane_id();
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+            const int qq = b * 32 + (l & 31);
+            const uint64_t m = __builtin_amdgcn_ballot_w64(l < 32 && cnt[qq] > 0);
+            uint32_t need = (uint32_t)m;
+            while (need) {
+                const int qi = __builtin_ctz(need);
+                need &= need - 1;
+                const int q2 = b * 32 + qi;
+                merge_query<KSEL>(state + (int64_t)q2 * KSEL, buf + q2 * CB,
+                                  __builtin_amdgcn_readfirstlane(cnt[q2]));
+            }
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+};
+
+// Final lists of the wave's queries: ids and output distances.
+__device__ inline void write_lists(const uint64_t* __restrict__ state, int ksel, int64_t q0, int nqw,
+                                   int64_t nq, const float* __restrict__ qnout, float osc,
+                                   int32_t* __restrict__ nbr, float* __restrict__ dist, int k_out) {
+    const int l = lane_id();
+    for (int qi = 0; qi < nqw; ++qi) {
+        const int64_t q = q0 + qi;
+        if (q >= nq) break;
+        const float qn = qnout[q];
+        for (int t = l; t < k_out; t += 64) {
+            const uint64_t key = state[q * ksel + t];
+            nbr[q * k_out + t] = key_id(key);
+            if (dist) dist[q * k_out + t] = key == EMPTY_KEY ? __builtin_inff() : (key_dist(key) + qn) * osc;
+        }
+    }
+}
+
+// Fused distance tile + top-k with register-resident queries.  WAVES waves
+// per workgroup, QB blocks of 32 queries per wave (NQ = 32*QB*WAVES queries
+// per workgroup).  Candidate tiles (BC rows) are staged in LDS, double
+// buffered, the next tile already in flight in registers while the current
+// one is computed.  Within a tile the MFMAs of subtile s+1 are issued before
+// the selection epilogue of subtile s so that both run at once.
 template <int P, int NSTEP, int KSEL, int WAVES, int QB>
 __global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_kernel(
     const uint8_t* __restrict__ ops, const float* __restrict__ ninit, const int32_t* __restrict__ sexp,
@@ -458,8 +575,10 @@ __global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_kernel(
 
     Frag<P, NSTEP> qf[QB];
     int q_scale[QB];
-    float thr[QB];
-    int64_t qself[QB];    // candidate id equal to this lane's query (excluded); -1 for none
+    Selector<KSEL, QB> sel;
+    sel.state = state + qblk0 * KSEL;
+    sel.buf = s_buf + w * 32 * QB * CB;
+    sel.cnt = s_cnt + w * 32 * QB;
 #pragma unroll
     for (int b = 0; b < QB; ++b) {
         const int64_t qg = qblk0 + b * 32 + ql;
@@ -467,8 +586,8 @@ __global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_kernel(
         scale_query<P, NSTEP>(qf[b], qmul);
         q_scale[b] = 127;
         if constexpr (P == SG_PREC_FP8) q_scale[b] = 127 + qsexp[qg] + 1;
-        thr[b] = __builtin_inff();
-        qself[b] = qg < nq ? (qid ? qid[qg] : qg) : -1;
+        sel.thr[b] = __builtin_inff();
+        sel.qself[b] = qg < nq ? (qid ? qid[qg] : qg) : -1;
     }
 
     // tile staging: global -> registers (prefetch) -> LDS
@@ -501,75 +620,6 @@ __global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_kernel(
             if constexpr (P == SG_PREC_FP8) s_sexp[buf][tid] = pre_sexp;
         }
     };
-
-    // insert the candidates of one subtile that beat the threshold; entries
-    // that find the buffer full are flagged in ovf and re-inserted after the
-    // merge that empties it
-    auto epilogue = [&](floatx16 (&acc)[QB], int cbase) {
-#pragma unroll
-        for (int b = 0; b < QB; ++b) {
-            // self excluded by index
-            const bool mine = qself[b] >= cbase && qself[b] < cbase + 32;
-            if (__builtin_amdgcn_ballot_w64(mine)) {
-#pragma unroll
-                for (int i = 0; i < 16; ++i)
-                    if (cbase + out_row(i, l) == qself[b]) acc[b][i] = __builtin_inff();
-            }
-        }
-        bool any = false;
-#pragma unroll
-        for (int b = 0; b < QB; ++b)
-#pragma unroll
-            for (int i = 0; i < 16; ++i) any |= acc[b][i] < thr[b];
-        if (!__builtin_amdgcn_ballot_w64(any)) return;
-        uint32_t ovf[QB];
-#pragma unroll
-        for (int b = 0; b < QB; ++b) {
-            ovf[b] = 0;
-            const int qloc = (w * QB + b) * 32 + ql;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                if (acc[b][i] < thr[b]) {
-                    const int slot = atomicAdd(&s_cnt[qloc], 1);
-                    if (slot < CB)
-                        s_buf[qloc * CB + slot] = make_key(acc[b][i], cbase + out_row(i, l));
-                    else
-                        ovf[b] |= 1u << i;
-                }
-            }
-        }
-        bool anyovf = false;
-#pragma unroll
-        for (int b = 0; b < QB; ++b) anyovf |= ovf[b] != 0;
-        if (!__builtin_amdgcn_ballot_w64(anyovf)) return;
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-#pragma unroll
-        for (int b = 0; b < QB; ++b) {
-            // queries of this block with an overflow in either lane half
-            const uint64_t m = __builtin_amdgcn_ballot_w64(ovf[b] != 0);
-            uint32_t need = (uint32_t)m | (uint32_t)(m >> 32);
-            while (need) {
-                const int qi = __builtin_ctz(need);
-                need &= need - 1;
-                const int qloc = (w * QB + b) * 32 + qi;
-                const float t = merge_query<KSEL>(state + (qblk0 + b * 32 + qi) * KSEL,
-                                                  s_buf + qloc * CB, CB);
-                if (ql == qi) thr[b] = t;
-                if (l == 0) s_cnt[qloc] = 0;
-                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-            }
-            const int qloc = (w * QB + b) * 32 + ql;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                if ((ovf[b] >> i & 1u) && acc[b][i] < thr[b]) {
-                    const int slot = atomicAdd(&s_cnt[qloc], 1);
-                    s_buf[qloc * CB + slot] = make_key(acc[b][i], cbase + out_row(i, l));
-                }
-            }
-        }
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    };
-
     auto compute = [&](floatx16 (&acc)[QB], int buf, int sub) {
         floatx4 nv[4];
 #pragma unroll
@@ -583,12 +633,8 @@ __global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_kernel(
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[b][i] = nv[i >> 2][i & 3];
         }
-        if constexpr (QB == 1) {
-            acc[0] = mfma_tile<P, NSTEP>(arow, qf[0], acc[0], a_scale, q_scale[0]);
-        } else {
 #pragma unroll
-            for (int b = 0; b < QB; ++b) acc[b] = mfma_tile<P, NSTEP>(arow, qf[b], acc[b], a_scale, q_scale[b]);
-        }
+        for (int b = 0; b < QB; ++b) acc[b] = mfma_tile<P, NSTEP>(arow, qf[b], acc[b], a_scale, q_scale[b]);
     };
 
     const int ntiles = (n + BC - 1) / BC;
@@ -605,10 +651,10 @@ __global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_kernel(
         for (int sub = 0; sub < NSUB; ++sub) {
             if (sub % 2 == 0) {
                 if (sub + 1 < NSUB) compute(accB, buf, sub + 1);
-                epilogue(accA, j0 + sub * 32);
+                sel.admit(accA, j0 + sub * 32);
             } else {
                 if (sub + 1 < NSUB) compute(accA, buf, sub + 1);
-                epilogue(accB, j0 + sub * 32);
+                sel.admit(accB, j0 + sub * 32);
             }
         }
         if (t + 1 < ntiles) {
@@ -617,34 +663,133 @@ __global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_kernel(
         }
         __syncthreads();
     }
-    // drain the buffers
-#pragma unroll
-    for (int b = 0; b < QB; ++b) {
-        const int qloc = (w * QB + b) * 32 + ql;
-        const uint64_t m = __builtin_amdgcn_ballot_w64(l < 32 && s_cnt[qloc] > 0);
-        uint32_t need = (uint32_t)m;
-        while (need) {
-            const int qi = __builtin_ctz(need);
-            need &= need - 1;
-            const int ql2 = (w * QB + b) * 32 + qi;
-            merge_query<KSEL>(state + (qblk0 + b * 32 + qi) * KSEL, s_buf + ql2 * CB,
-                              __builtin_amdgcn_readfirstlane(s_cnt[ql2]));
-        }
+    sel.drain();
+    if (nbr) write_lists(state, KSEL, qblk0, 32 * QB, nq, qnout, osc, nbr, dist, k_out);
+}
+
+// Fused distance tile + top-k for FP32 rows too wide for register-resident
+// queries: a 128 x 128 (queries x candidates) workgroup tile accumulated over
+// k in chunks of 32, both operands staged through LDS (double buffered, the
+// next chunk loading into registers during the current chunk's MFMAs); the
+// selection runs on the four 32x32 subtiles of each wave once a candidate
+// tile's k-loop is complete.
+constexpr int KS_WAVES = 4;
+constexpr int KS_NQ = 128;
+constexpr int KS_BC = 128;
+constexpr int KS_DC = 32;
+constexpr int KS_RS = KS_DC + 4;    // LDS row stride (floats)
+
+template <int KSEL>
+__global__ __launch_bounds__(KS_WAVES * 64, 1) void dist_topk_kstream_kernel(
+    const float* __restrict__ ops, int DP, const float* __restrict__ ninit, int n,
+    const float* __restrict__ qops, const int64_t* __restrict__ qid, const float* __restrict__ qnout,
+    int nq, float qmul, float osc, uint64_t* __restrict__ state, int32_t* __restrict__ nbr,
+    float* __restrict__ dist, int k_out) {
+    constexpr int NT = KS_WAVES * 64;
+    constexpr int CPR = KS_DC / 4;                       // 16-byte chunks per row per k-chunk
+    constexpr int CPT = (KS_NQ + KS_BC) * CPR / NT;      // per thread per k-chunk
+    __shared__ __align__(16) float s_q[2][KS_NQ * KS_RS];
+    __shared__ __align__(16) float s_c[2][KS_BC * KS_RS];
+    __shared__ __align__(16) float s_norm[KS_BC];
+    __shared__ uint64_t s_buf[KS_NQ * CB];
+    __shared__ int s_cnt[KS_NQ];
+
+    const int tid = threadIdx.x;
+    const int l = tid & 63;
+    const int w = tid >> 6;
+    const int h = l >> 5;
+    const int ql = l & 31;
+    const int64_t qb0 = (int64_t)blockIdx.x * KS_NQ;
+    const int64_t qblk0 = qb0 + w * 32;
+    for (int t = tid; t < KS_NQ; t += NT) s_cnt[t] = 0;
+
+    Selector<KSEL, 1> sel;
+    sel.state = state + qblk0 * KSEL;
+    sel.buf = s_buf + w * 32 * CB;
+    sel.cnt = s_cnt + w * 32;
+    {
+        const int64_t qg = qblk0 + ql;
+        sel.thr[0] = __builtin_inff();
+        sel.qself[0] = qg < nq ? (qid ? qid[qg] : qg) : -1;
     }
-    if (nbr) {
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        for (int qi = 0; qi < 32 * QB; ++qi) {
-            const int64_t q = qblk0 + qi;
-            if (q >= nq) break;
-            const float qn = qnout[q];
-            for (int t = l; t < k_out; t += 64) {
-                const uint64_t key = state[q * KSEL + t];
-                nbr[q * k_out + t] = key_id(key);
-                if (dist)
-                    dist[q * k_out + t] = key == EMPTY_KEY ? __builtin_inff() : (key_dist(key) + qn) * osc;
+
+    const int nch = DP / KS_DC;
+    const int ntiles = (n + KS_BC - 1) / KS_BC;
+    const int64_t total = (int64_t)ntiles * nch;
+    intx4 pre[CPT];
+    float pre_norm = 0.f;
+    auto prefetch = [&](int64_t g) {
+        const int t = (int)(g / nch), kc = (int)(g % nch);
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int c = tid + u * NT;
+            const int r = c / CPR, o = c % CPR;
+            const float* src = r < KS_NQ ? qops + (qb0 + r) * DP
+                                         : ops + ((int64_t)t * KS_BC + (r - KS_NQ)) * DP;
+            pre[u] = *reinterpret_cast<const intx4*>(src + kc * KS_DC + o * 4);
+        }
+        if (kc == 0 && tid < KS_BC) pre_norm = ninit[(int64_t)t * KS_BC + tid];
+    };
+    auto commit = [&](int64_t g, int buf) {
+        const int kc = (int)(g % nch);
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int c = tid + u * NT;
+            const int r = c / CPR, o = c % CPR;
+            float* dst = r < KS_NQ ? &s_q[buf][r * KS_RS + o * 4] : &s_c[buf][(r - KS_NQ) * KS_RS + o * 4];
+            *reinterpret_cast<intx4*>(dst) = pre[u];
+        }
+        if (kc == 0 && tid < KS_BC) s_norm[tid] = pre_norm;
+    };
+
+    prefetch(0);
+    commit(0, 0);
+    __syncthreads();
+    if (total > 1) prefetch(1);
+    floatx16 acc[4];
+    for (int64_t g = 0; g < total; ++g) {
+        const int buf = (int)(g & 1);
+        const int t = (int)(g / nch), kc = (int)(g % nch);
+        if (kc == 0) {
+#pragma unroll
+            for (int sub = 0; sub < 4; ++sub)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) acc[sub][i] = s_norm[sub * 32 + out_row(i, l)];
+        }
+        // B fragment: this lane's query, the lane half's 16 k values of the chunk
+        float bq[KS_DC / 2];
+#pragma unroll
+        for (int v = 0; v < KS_DC / 8; ++v) {
+            floatx4 x = *reinterpret_cast<const floatx4*>(&s_q[buf][(w * 32 + ql) * KS_RS + h * (KS_DC / 2) + v * 4]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) bq[v * 4 + e] = x[e] * qmul;
+        }
+#pragma unroll
+        for (int sub = 0; sub < 4; ++sub) {
+            const float* arow = &s_c[buf][(sub * 32 + ql) * KS_RS + h * (KS_DC / 2)];
+#pragma unroll
+            for (int v = 0; v < KS_DC / 8; ++v) {
+                floatx4 a = *reinterpret_cast<const floatx4*>(arow + v * 4);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    acc[sub] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[e], bq[v * 4 + e], acc[sub], 0, 0, 0);
             }
         }
+        if (kc == nch - 1) {
+#pragma unroll
+            for (int sub = 0; sub < 4; ++sub) {
+                floatx16 one[1] = {acc[sub]};
+                sel.admit(one, (int64_t)t * KS_BC + sub * 32);
+            }
+        }
+        if (g + 1 < total) {
+            commit(g + 1, buf ^ 1);
+            if (g + 2 < total) prefetch(g + 2);
+        }
+        __syncthreads();
     }
+    sel.drain();
+    if (nbr) write_lists(state, KSEL, qblk0, 32, nq, qnout, osc, nbr, dist, k_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -779,93 +924,102 @@ inline Layout layout(int64_t n, int d, int k, int prec, int rerank) {
 typedef void (*topk_fn)(const uint8_t*, const float*, const int32_t*, int, const uint8_t*,
                         const int64_t*, const float*, const int32_t*, int, float, float, uint64_t*,
                         int32_t*, float*, int);
+typedef void (*kstream_fn)(const float*, int, const float*, int, const float*, const int64_t*,
+                           const float*, int, float, float, uint64_t*, int32_t*, float*, int);
 
-template <int P, int NSTEP>
+// A distance kernel and its launch geometry.
+struct Kern {
+    topk_fn fn = nullptr;         // resident-query kernel, or
+    kstream_fn ks = nullptr;      // k-streamed FP32 kernel
+    int DP = 0;                   // padded operand row length it expects
+    int nq_block = 0;             // queries per workgroup
+    int threads = 0;
+};
+
+template <int P, int NSTEP, int W>
 topk_fn pick_ksel(int ksel) {
     switch (ksel) {
-        case 32: return dist_topk_kernel<P, NSTEP, 32, TWAVES, TQB>;
-        case 64: return dist_topk_kernel<P, NSTEP, 64, TWAVES, TQB>;
-        case 128: return dist_topk_kernel<P, NSTEP, 128, TWAVES, TQB>;
-        default: return dist_topk_kernel<P, NSTEP, 256, TWAVES, TQB>;
+        case 32: return dist_topk_kernel<P, NSTEP, 32, W, 1>;
+        case 64: return dist_topk_kernel<P, NSTEP, 64, W, 1>;
+        case 128: return dist_topk_kernel<P, NSTEP, 128, W, 1>;
+        default: return dist_topk_kernel<P, NSTEP, 256, W, 1>;
     }
 }
 
-// Resident-query kernels are instantiated for the padded half-row lengths
-// below; a smaller d pads up to the next one.
-topk_fn pick_kernel(int prec, int DP, int ksel, int* DP_used) {
-    int need = nstep_for(prec, DP);
+template <int P, int NSTEP, int W>
+Kern resident(int ksel) {
+    Kern k;
+    k.fn = pick_ksel<P, NSTEP, W>(ksel);
+    k.DP = 2 * NSTEP * Tr<P>::VEC;
+    k.nq_block = 32 * W;
+    k.threads = 64 * W;
+    return k;
+}
+
+// Resident-query kernels are instantiated for the half-row lengths below
+// (8 waves while the query fragment fits 2 waves per SIMD, 4 waves beyond);
+// a smaller d pads up to the next one.  FP32 rows wider than 128 use the
+// k-streamed kernel.
+Kern pick_kernel(int prec, int d, int ksel) {
+    const int need = nstep_for(prec, padded_d(prec, d));
     switch (prec) {
         case SG_PREC_FP32: {
-            static const int steps[] = {16, 32, 48, 64};
-            for (int s : steps)
-                if (need <= s) {
-                    *DP_used = 2 * s;
-                    switch (s) {
-                        case 16: return pick_ksel<SG_PREC_FP32, 16>(ksel);
-                        case 32: return pick_ksel<SG_PREC_FP32, 32>(ksel);
-                        case 48: return pick_ksel<SG_PREC_FP32, 48>(ksel);
-                        default: return pick_ksel<SG_PREC_FP32, 64>(ksel);
-                    }
-                }
-            return nullptr;
+            if (need <= 16) return resident<SG_PREC_FP32, 16, TWAVES>(ksel);
+            if (need <= 32) return resident<SG_PREC_FP32, 32, TWAVES>(ksel);
+            if (need <= 48) return resident<SG_PREC_FP32, 48, TWAVES>(ksel);
+            if (need <= 64) return resident<SG_PREC_FP32, 64, TWAVES>(ksel);
+            Kern k;
+            switch (ksel) {
+                case 32: k.ks = dist_topk_kstream_kernel<32>; break;
+                case 64: k.ks = dist_topk_kstream_kernel<64>; break;
+                case 128: k.ks = dist_topk_kstream_kernel<128>; break;
+                default: k.ks = dist_topk_kstream_kernel<256>; break;
+            }
+            k.DP = (d + KS_DC - 1) / KS_DC * KS_DC;
+            k.nq_block = KS_NQ;
+            k.threads = KS_WAVES * 64;
+            return k;
         }
-        case SG_PREC_F16:
+        case SG_PREC_F16: {
+            if (need <= 2) return resident<SG_PREC_F16, 2, TWAVES>(ksel);
+            if (need <= 4) return resident<SG_PREC_F16, 4, TWAVES>(ksel);
+            if (need <= 6) return resident<SG_PREC_F16, 6, TWAVES>(ksel);
+            if (need <= 8) return resident<SG_PREC_F16, 8, TWAVES>(ksel);
+            if (need <= 12) return resident<SG_PREC_F16, 12, TWAVES>(ksel);
+            if (need <= 16) return resident<SG_PREC_F16, 16, TWAVES>(ksel);
+            if (need <= 24) return resident<SG_PREC_F16, 24, 4>(ksel);
+            if (need <= 32) return resident<SG_PREC_F16, 32, 4>(ksel);
+            if (need <= 48) return resident<SG_PREC_F16, 48, 4>(ksel);
+            return Kern();
+        }
         case SG_PREC_BF16: {
-            static const int steps[] = {2, 4, 6, 8, 12, 16};
-            for (int s : steps)
-                if (need <= s) {
-                    *DP_used = 2 * s * 8;
-                    if (prec == SG_PREC_F16) {
-                        switch (s) {
-                            case 2: return pick_ksel<SG_PREC_F16, 2>(ksel);
-                            case 4: return pick_ksel<SG_PREC_F16, 4>(ksel);
-                            case 6: return pick_ksel<SG_PREC_F16, 6>(ksel);
-                            case 8: return pick_ksel<SG_PREC_F16, 8>(ksel);
-                            case 12: return pick_ksel<SG_PREC_F16, 12>(ksel);
-                            default: return pick_ksel<SG_PREC_F16, 16>(ksel);
-                        }
-                    } else {
-                        switch (s) {
-                            case 2: return pick_ksel<SG_PREC_BF16, 2>(ksel);
-                            case 4: return pick_ksel<SG_PREC_BF16, 4>(ksel);
-                            case 6: return pick_ksel<SG_PREC_BF16, 6>(ksel);
-                            case 8: return pick_ksel<SG_PREC_BF16, 8>(ksel);
-                            case 12: return pick_ksel<SG_PREC_BF16, 12>(ksel);
-                            default: return pick_ksel<SG_PREC_BF16, 16>(ksel);
-                        }
-                    }
-                }
-            return nullptr;
+            if (need <= 2) return resident<SG_PREC_BF16, 2, TWAVES>(ksel);
+            if (need <= 4) return resident<SG_PREC_BF16, 4, TWAVES>(ksel);
+            if (need <= 6) return resident<SG_PREC_BF16, 6, TWAVES>(ksel);
+            if (need <= 8) return resident<SG_PREC_BF16, 8, TWAVES>(ksel);
+            if (need <= 12) return resident<SG_PREC_BF16, 12, TWAVES>(ksel);
+            if (need <= 16) return resident<SG_PREC_BF16, 16, TWAVES>(ksel);
+            if (need <= 24) return resident<SG_PREC_BF16, 24, 4>(ksel);
+            if (need <= 32) return resident<SG_PREC_BF16, 32, 4>(ksel);
+            if (need <= 48) return resident<SG_PREC_BF16, 48, 4>(ksel);
+            return Kern();
         }
         default: {
-            static const int steps[] = {1, 2, 4, 8};
-            for (int s : steps)
-                if (need <= s) {
-                    *DP_used = 2 * s * 32;
-                    switch (s) {
-                        case 1: return pick_ksel<SG_PREC_FP8, 1>(ksel);
-                        case 2: return pick_ksel<SG_PREC_FP8, 2>(ksel);
-                        case 4: return pick_ksel<SG_PREC_FP8, 4>(ksel);
-                        default: return pick_ksel<SG_PREC_FP8, 8>(ksel);
-                    }
-                }
-            return nullptr;
+            if (need <= 1) return resident<SG_PREC_FP8, 1, TWAVES>(ksel);
+            if (need <= 2) return resident<SG_PREC_FP8, 2, TWAVES>(ksel);
+            if (need <= 4) return resident<SG_PREC_FP8, 4, TWAVES>(ksel);
+            if (need <= 8) return resident<SG_PREC_FP8, 8, 4>(ksel);
+            if (need <= 16) return resident<SG_PREC_FP8, 16, 4>(ksel);
+            return Kern();
         }
     }
-}
-
-// padded row length actually used by the kernel for (prec, d)
-inline int kernel_dp(int prec, int d, int ksel) {
-    int used = 0;
-    pick_kernel(prec, padded_d(prec, d), ksel, &used);
-    return used;
 }
 
 inline Layout layout_k(int64_t n, int d, int k, int prec, int rerank) {
     Layout L = layout(n, d, k, prec, rerank);
-    int used = kernel_dp(prec, d, L.ksel);
-    if (used > 0) {
-        L.DP = used;
+    Kern kk = pick_kernel(prec, d, L.ksel);
+    if (kk.DP > 0) {
+        L.DP = kk.DP;
         L.ops_bytes = (size_t)L.n_pad * L.DP * elem_bytes(prec);
         L.total = align_up(L.ops_bytes, 256) + align_up(L.norms_bytes, 256) +
                   align_up(L.sexp_bytes, 256) + align_up(L.state_bytes, 256) + 1024;
@@ -931,10 +1085,9 @@ void run(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int
          size_t ws_bytes, hipStream_t s) {
     if (rerank == k) rerank = 0;
     Layout L = layout_k(n, d, k, prec, rerank);
-    int used = 0;
-    topk_fn fn = pick_kernel(prec, padded_d(prec, d), L.ksel, &used);
-    if (!fn) {
-        set_error("sg_knn: d too large for the resident-query kernel of this precision");
+    const Kern kern = pick_kernel(prec, d, L.ksel);
+    if (!kern.fn && !kern.ks) {
+        set_error("sg_knn: no distance kernel for this precision at d = " + std::to_string(d));
         throw Fail{SG_ERR_UNSUPPORTED};
     }
     const size_t need = total_bytes(L, rows ? nq : -1, prec);
@@ -981,10 +1134,16 @@ void run(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int
     const float qmul = plain_ip ? -1.0f : -2.0f;
     const float osc = norm_corrected_ip(metric, prec) ? 0.5f : 1.0f;
     profile_record(s, true);
-    fn<<<(unsigned)(nq_pad / BQ), TWAVES * 64, 0, s>>>(ops, ninit, sexp, (int)n, qops, qid, qnout, qsexp,
-                                                     (int)nq_rows, qmul, osc, state,
-                                                     final_here ? nbr : nullptr,
-                                                     final_here ? dist : nullptr, k);
+    const unsigned grid = (unsigned)(nq_pad / kern.nq_block);
+    if (kern.fn)
+        kern.fn<<<grid, kern.threads, 0, s>>>(ops, ninit, sexp, (int)n, qops, qid, qnout, qsexp,
+                                              (int)nq_rows, qmul, osc, state, final_here ? nbr : nullptr,
+                                              final_here ? dist : nullptr, k);
+    else
+        kern.ks<<<grid, kern.threads, 0, s>>>(reinterpret_cast<const float*>(ops), L.DP, ninit, (int)n,
+                                              reinterpret_cast<const float*>(qops), qid, qnout,
+                                              (int)nq_rows, qmul, osc, state, final_here ? nbr : nullptr,
+                                              final_here ? dist : nullptr, k);
     SG_LAUNCH_CHECK();
     profile_record(s, false);
     if (!final_here) {

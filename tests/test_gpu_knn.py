@@ -133,3 +133,37 @@ def test_knn_rows_rerank_and_full_agree():
     full, _ = sg.sg_knn_graph(Xg, 32, "ip", "bf16", rerank=64)
     sub, _ = sg.sg_knn_rows(Xg, rows, 32, "ip", "bf16", rerank=64)
     np.testing.assert_array_equal(sub.cpu().numpy(), full.cpu().numpy()[rows])
+
+
+@pytest.mark.parametrize("n,d,K", [(700, 960, 64), (1030, 200, 32), (300, 129, 16)])
+def test_knn_wide_fp32_kstream_exact(n, d, K):
+    # small integers: every FP32 product and partial sum is exact at d = 960
+    X = _u8(n, d, seed=d, levels=16).astype(np.float32)
+    nbr, dist = sg.sg_knn_graph(torch.from_numpy(X).to(DEV), K, "l2", "fp32")
+    onbr, odist = oracle.knn(oracle.widen(X), K)
+    np.testing.assert_array_equal(nbr.cpu().numpy(), onbr)
+    np.testing.assert_array_equal(dist.cpu().numpy(), odist.astype(np.float32))
+
+
+@pytest.mark.parametrize("d", [768, 300])
+def test_knn_wide_f16_four_wave_exact(d):
+    X = _u8(900, d, seed=d + 1, levels=12).astype(np.float16)
+    nbr, dist = sg.sg_knn_graph(torch.from_numpy(X).to(DEV), 64, "ip", "f16")
+    onbr, odist = oracle.knn(oracle.widen(X), 64, oracle.IP)
+    np.testing.assert_array_equal(nbr.cpu().numpy(), onbr)
+    np.testing.assert_array_equal(dist.cpu().numpy(), odist.astype(np.float32))
+
+
+def test_knn_rows_wide_fp32_exact():
+    X = _u8(1500, 960, seed=5, levels=16).astype(np.float32)
+    rows = np.arange(3, 1500, 11)
+    nbr, _ = sg.sg_knn_rows(torch.from_numpy(X).to(DEV), rows, 64, "l2", "fp32")
+    onbr, _ = oracle.knn(oracle.widen(X), 64, rows=rows)
+    np.testing.assert_array_equal(nbr.cpu().numpy(), onbr)
+
+
+def test_knn_fp8_wide_rerank_recall():
+    X = synthdata.l1_nonneg(2000, d=512, seed=9, n_comp=20)
+    nbr, _ = sg.sg_knn_graph(torch.from_numpy(X).to(DEV), 32, "l2", "fp8", rerank=128)
+    onbr, _ = oracle.knn(oracle.widen(X), 32)
+    assert recall(nbr.cpu().numpy(), onbr) >= 0.95
