@@ -153,6 +153,19 @@ sg_status sg_knn_rows(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64
                       void* stream);
 
 /* ------------------------------------------------------------------------
+ * sg_rerank -- exact re-rank of given candidate lists
+ *
+ * For each row i of X: the ids cand[i][0..c) (SG_NONE, out-of-range ids,
+ * repeats and i itself skipped) are re-scored with the FP32 difference-form
+ * distance (L2: sum_t (x_it - x_jt)^2 in ascending t; IP: -sum_t x_it x_jt)
+ * and the best k by (delta, id) kept, padded with SG_NONE / +inf.  Used by
+ * the learned form: candidates proposed on projected rows are re-ranked on
+ * the original rows.  k <= c <= 256; d <= 4096.  No workspace.
+ * ---------------------------------------------------------------------- */
+sg_status sg_rerank(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t ld, sg_metric metric,
+                    const int32_t* cand, int32_t c, int32_t k, int32_t* nbr, float* dist, void* stream);
+
+/* ------------------------------------------------------------------------
  * sg_prune -- rank-based edge prune + reverse-edge pass to out-degree R
  *
  * The graph-optimisation step of the CAGRA shard build the paper uses
@@ -213,6 +226,48 @@ sg_status sg_search(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t
                     sg_metric metric, const int32_t* graph, int32_t max_degree, const void* Q,
                     int64_t nq, int64_t ldq, int32_t topk, int32_t L, int64_t entry,
                     int32_t* out_ids, float* out_dist, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Learned candidate proposer (a small MLP trained on the GPU)
+ *
+ *   z = (x - mu) / sigma,  h1 = W1 z + b1,  a1 = GELU(h1) (erf form),
+ *   h2 = W2 a1 + b2,  f = h2 / ||h2||          W1: H x D, W2: E x H (row-major)
+ *
+ * Rows are FP32 (n x D, stride ld).  Layer products use BF16-rounded operands
+ * with FP32 accumulation; masters, biases, Adam moments and outputs are FP32.
+ * sg_mlp_stats: mu = per-dimension mean, sigma = one global standard
+ *   deviation, over the listed rows (ws: >= 2048 bytes).
+ * sg_mlp_loss_grad: one forward + backward on B anchors and B positives
+ *   (device row lists): in-batch softmax cross-entropy of the logits
+ *   f(a_i).f(p_j)/T, target j = i; writes the mean loss (device float) and
+ *   the gradients of W1, b1, W2, b2.
+ * sg_mlp_train: `steps` Adam steps (bias corrected); step t uses anchors /
+ *   positives [t*B, (t+1)*B) of the given device lists (the sampling is the
+ *   caller's, seeded); adam_m / adam_v hold H*D + H + E*H + E floats each, in
+ *   the order W1, b1, W2, b2, zero before the first step; losses (nullable)
+ *   receives one loss per step.  use_graph != 0 captures one step in a
+ *   hipGraph and replays it.
+ * sg_mlp_project: f for every row into F (n x E).
+ * ---------------------------------------------------------------------- */
+sg_status sg_mlp_workspace_size(int32_t B, int32_t D, int32_t H, int32_t E, size_t* bytes);
+sg_status sg_mlp_stats(const float* X, int64_t n, int32_t D, int64_t ld, const int64_t* rows,
+                       int64_t nrows, float* mu, float* sigma, void* ws, size_t ws_bytes, void* stream);
+sg_status sg_mlp_loss_grad(const float* X, int64_t n, int32_t D, int64_t ld, const int64_t* anchors,
+                           const int64_t* positives, int32_t B, int32_t H, int32_t E, const float* W1,
+                           const float* b1, const float* W2, const float* b2, const float* mu,
+                           const float* sigma, float T, float* loss, float* gW1, float* gb1,
+                           float* gW2, float* gb2, void* ws, size_t ws_bytes, void* stream);
+sg_status sg_mlp_train(const float* X, int64_t n, int32_t D, int64_t ld, const int64_t* anchors,
+                       const int64_t* positives, int32_t B, int32_t steps, int32_t H, int32_t E,
+                       float* W1, float* b1, float* W2, float* b2, float* adam_m, float* adam_v,
+                       const float* mu, const float* sigma, float T, float lr, float beta1,
+                       float beta2, float eps, float* losses, int32_t use_graph, void* ws,
+                       size_t ws_bytes, void* stream);
+sg_status sg_mlp_project(const float* X, int64_t n, int32_t D, int64_t ld, int32_t H, int32_t E,
+                         const float* W1, const float* b1, const float* W2, const float* b2,
+                         const float* mu, const float* sigma, float* F, void* ws, size_t ws_bytes,
+                         void* stream);
+sg_status sg_mlp_project_workspace_size(int32_t D, int32_t H, int32_t E, size_t* bytes);
 
 /* ------------------------------------------------------------------------
  * Profiling of the distance kernel (host-side, per process)

@@ -554,8 +554,8 @@ int orc_rerank(const double* X, int64_t n, int d, int metric, const int32_t* can
             int m = 0;
             for (int e = 0; e < c; ++e) {
                 int32_t j = cand[i * c + e];
-                if (j == ORC_NONE) continue;
-                if (j < 0 || j >= n || j == i) {
+                if (j == ORC_NONE || j == i) continue;   /* self excluded by index */
+                if (j < 0 || j >= n) {
                     bad = 1;
                     continue;
                 }

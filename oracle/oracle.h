@@ -110,8 +110,9 @@ int orc_search(const double* X, int64_t n, int d, int metric, const int32_t* gra
                int max_degree, const double* Q, int64_t nq, int topk, int L,
                int64_t entry, int32_t* out_ids, double* out_dist);
 
-/* Re-rank: each row's c candidate ids (ORC_NONE skipped) re-scored with the
- * exact FP64 delta; the first K by (delta, id) are kept. */
+/* Re-rank: each row's c candidate ids (ORC_NONE, repeats and the row itself
+ * skipped) re-scored with the exact FP64 delta; the first K by (delta, id)
+ * are kept. */
 int orc_rerank(const double* X, int64_t n, int d, int metric, const int32_t* cand,
                int c, int K, int32_t* nbr, double* dist);
 

@@ -65,6 +65,15 @@ _SIGS = {
     "sg_merge_workspace_size": (i32, [i32, vp, i64, psz]),
     "sg_merge": (i32, [i32, vp, vp, vp, i32, i64, i32, vp, vp, vp, sz, vp]),
     "sg_search_workspace_size": (i32, [i64, i32, i64, psz]),
+    "sg_rerank": (i32, [vp, i32, i64, i32, i64, i32, vp, i32, i32, vp, vp, vp]),
+    "sg_mlp_workspace_size": (i32, [i32, i32, i32, i32, psz]),
+    "sg_mlp_project_workspace_size": (i32, [i32, i32, i32, psz]),
+    "sg_mlp_stats": (i32, [vp, i64, i32, i64, vp, i64, vp, vp, vp, sz, vp]),
+    "sg_mlp_loss_grad": (i32, [vp, i64, i32, i64, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, f32, vp,
+                               vp, vp, vp, vp, vp, sz, vp]),
+    "sg_mlp_train": (i32, [vp, i64, i32, i64, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp,
+                           f32, f32, f32, f32, f32, vp, i32, vp, sz, vp]),
+    "sg_mlp_project": (i32, [vp, i64, i32, i64, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
     "sg_profile_begin": (i32, []),
     "sg_profile_end": (i32, [C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "sg_search": (i32, [vp, i32, i64, i32, i64, i32, vp, i32, vp, i64, i64, i32, i32, i64, vp, vp,
@@ -253,3 +262,93 @@ def sg_profile_end():
     ms, n = C.c_double(0.0), C.c_int64(0)
     _check("sg_profile_end", lib().sg_profile_end(C.byref(ms), C.byref(n)))
     return ms.value, n.value
+
+
+def sg_rerank(X, cand, k, metric="l2", stream=None):
+    """Exact FP32 re-rank of candidate lists cand [n, c]: (nbr [n,k], dist [n,k])."""
+    L = lib()
+    dt, n, d, ld = _rows(X)
+    _dev_tensor(cand, "cand")
+    cand = cand.to(torch.int32).contiguous()
+    c = cand.shape[1]
+    nbr = torch.empty((n, k), dtype=torch.int32, device=X.device)
+    dd = torch.empty((n, k), dtype=torch.float32, device=X.device)
+    _check("sg_rerank", L.sg_rerank(_ptr(X), dt, n, d, ld, METRICS[metric], _ptr(cand), c, k, _ptr(nbr),
+                                    _ptr(dd), _stream(stream)))
+    return nbr, dd
+
+
+class MLP:
+    """Device tensors of the learned proposer (FP32 masters + Adam moments)."""
+
+    def __init__(self, W1, b1, W2, b2, mu, sigma):
+        self.W1, self.b1, self.W2, self.b2 = (t.float().contiguous() for t in (W1, b1, W2, b2))
+        self.mu = mu.float().contiguous()
+        self.sigma = sigma.float().reshape(1).contiguous()
+        self.H, self.D = self.W1.shape
+        self.E = self.W2.shape[0]
+        n = self.W1.numel() + self.b1.numel() + self.W2.numel() + self.b2.numel()
+        self.m = torch.zeros(n, dtype=torch.float32, device=self.W1.device)
+        self.v = torch.zeros(n, dtype=torch.float32, device=self.W1.device)
+
+
+def sg_mlp_stats(X, rows, stream=None):
+    """(mu [D], sigma [1]) of the listed rows of X (FP32)."""
+    L = lib()
+    _dev_tensor(X, "X")
+    n, D = X.shape
+    r = torch.as_tensor(rows, dtype=torch.int64).to(X.device).contiguous()
+    mu = torch.empty(D, dtype=torch.float32, device=X.device)
+    sigma = torch.empty(1, dtype=torch.float32, device=X.device)
+    ws = _ws.get(4096, X.device, "mlp_stats")
+    _check("sg_mlp_stats", L.sg_mlp_stats(_ptr(X), n, D, X.stride(0), _ptr(r), r.numel(), _ptr(mu), _ptr(sigma),
+                                          _ptr(ws), ws.numel(), _stream(stream)))
+    return mu, sigma
+
+
+def sg_mlp_loss_grad(X, net, anchors, positives, T, stream=None):
+    """(loss scalar tensor, gW1, gb1, gW2, gb2) for one batch."""
+    L = lib()
+    n, D = X.shape
+    a = torch.as_tensor(anchors, dtype=torch.int64).to(X.device).contiguous()
+    p = torch.as_tensor(positives, dtype=torch.int64).to(X.device).contiguous()
+    B = a.numel()
+    ws = _ws.get(_size(L.sg_mlp_workspace_size, B, D, net.H, net.E), X.device, "mlp")
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    g = [torch.empty_like(t) for t in (net.W1, net.b1, net.W2, net.b2)]
+    _check("sg_mlp_loss_grad", L.sg_mlp_loss_grad(
+        _ptr(X), n, D, X.stride(0), _ptr(a), _ptr(p), B, net.H, net.E, _ptr(net.W1), _ptr(net.b1),
+        _ptr(net.W2), _ptr(net.b2), _ptr(net.mu), _ptr(net.sigma), float(T), _ptr(loss), _ptr(g[0]),
+        _ptr(g[1]), _ptr(g[2]), _ptr(g[3]), _ptr(ws), ws.numel(), _stream(stream)))
+    return (loss, *g)
+
+
+def sg_mlp_train(X, net, anchors, positives, B, steps, T=0.05, lr=1e-3, betas=(0.9, 0.999), eps=1e-8,
+                 use_graph=True, stream=None):
+    """Run `steps` Adam steps in place on net; returns the per-step losses."""
+    L = lib()
+    n, D = X.shape
+    a = torch.as_tensor(anchors, dtype=torch.int64).to(X.device).contiguous()
+    p = torch.as_tensor(positives, dtype=torch.int64).to(X.device).contiguous()
+    if a.numel() < B * steps or p.numel() < B * steps:
+        raise ValueError("need B*steps anchors and positives")
+    ws = _ws.get(_size(L.sg_mlp_workspace_size, B, D, net.H, net.E), X.device, "mlp")
+    losses = torch.empty(steps, dtype=torch.float32, device=X.device)
+    _check("sg_mlp_train", L.sg_mlp_train(
+        _ptr(X), n, D, X.stride(0), _ptr(a), _ptr(p), B, steps, net.H, net.E, _ptr(net.W1), _ptr(net.b1),
+        _ptr(net.W2), _ptr(net.b2), _ptr(net.m), _ptr(net.v), _ptr(net.mu), _ptr(net.sigma), float(T),
+        float(lr), float(betas[0]), float(betas[1]), float(eps), _ptr(losses), 1 if use_graph else 0,
+        _ptr(ws), ws.numel(), _stream(stream)))
+    return losses
+
+
+def sg_mlp_project(X, net, stream=None):
+    """Unit-norm projections F [n, E] of every row of X."""
+    L = lib()
+    n, D = X.shape
+    ws = _ws.get(_size(L.sg_mlp_project_workspace_size, D, net.H, net.E), X.device, "mlp_proj")
+    F = torch.empty((n, net.E), dtype=torch.float32, device=X.device)
+    _check("sg_mlp_project", L.sg_mlp_project(
+        _ptr(X), n, D, X.stride(0), net.H, net.E, _ptr(net.W1), _ptr(net.b1), _ptr(net.W2), _ptr(net.b2),
+        _ptr(net.mu), _ptr(net.sigma), _ptr(F), _ptr(ws), ws.numel(), _stream(stream)))
+    return F

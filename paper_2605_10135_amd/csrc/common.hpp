@@ -181,6 +181,17 @@ void fill(T* p, T v, int64_t n, hipStream_t s) {
 // Event pair around a distance-kernel launch while sg_profile_begin is active.
 void profile_record(hipStream_t s, bool before);
 
+__global__ inline void iota_kernel(int64_t* __restrict__ p, int64_t start, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = start + i;
+}
+
+inline void fill_iota(int64_t* p, int64_t start, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    iota_kernel<<<(unsigned)std::min<int64_t>((n + 255) / 256, 4096), 256, 0, s>>>(p, start, n);
+    SG_LAUNCH_CHECK();
+}
+
 // Exclusive scan of int64 counts (n entries) into out (n+1 entries).
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t s);
 size_t exclusive_scan_tmp_bytes(int64_t n);

@@ -834,11 +834,14 @@ __device__ inline void wave_sort_multi(uint64_t (&v)[PER]) {
     }
 }
 
-template <int PER>
+__device__ inline int32_t cand_id(uint64_t key) { return key_id(key); }
+__device__ inline int32_t cand_id(int32_t id) { return id; }
+
+template <int PER, typename CT = uint64_t>
 __global__ __launch_bounds__(256) void rerank_kernel(const void* __restrict__ X, int dtype, int64_t n,
                                                      int d, int64_t ld, int metric,
                                                      const int64_t* __restrict__ rowmap,
-                                                     int64_t n_src, const uint64_t* __restrict__ cand,
+                                                     int64_t n_src, const CT* __restrict__ cand,
                                                      int kstate,
                                                      int c, int k, int32_t* __restrict__ nbr,
                                                      float* __restrict__ dist) {
@@ -858,9 +861,8 @@ __global__ __launch_bounds__(256) void rerank_kernel(const void* __restrict__ X,
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
         int e = p * 64 + l;
-        uint64_t key = e < c ? cand[i * kstate + e] : EMPTY_KEY;
-        int32_t j = key_id(key);
-        if (j < 0) {
+        int32_t j = e < c ? cand_id(cand[i * kstate + e]) : SG_NONE;
+        if (j < 0 || j >= n_src || j == (rowmap ? rowmap[i] : i)) {   // absent, out of range or self
             v[p] = EMPTY_KEY;
             continue;
         }
@@ -878,13 +880,31 @@ __global__ __launch_bounds__(256) void rerank_kernel(const void* __restrict__ X,
         v[p] = make_key(s, j);
     }
     wave_sort_multi<PER>(v);
+    // a repeated candidate id gives equal adjacent keys: keep the first copy
+    // (every lane runs every shuffle: element p*64+l-1 is lane l-1 of v[p],
+    // or lane 63 of v[p-1] for l == 0)
+    uint64_t prev[PER];
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
-        int e = p * 64 + l;
-        if (e < k) {
-            nbr[i * k + e] = key_id(v[p]);
-            if (dist) dist[i * k + e] = key_dist(v[p]);
+        const uint64_t a = shfl_u64(v[p], (l + 63) & 63);
+        const uint64_t b = shfl_u64(v[p > 0 ? p - 1 : 0], 63);
+        prev[p] = l > 0 ? a : (p > 0 ? b : ~v[0]);
+    }
+    int kept = 0;
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const bool keep = v[p] != EMPTY_KEY && v[p] != prev[p];
+        const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
+        const int pos = kept + __builtin_popcountll(m & ((1ull << l) - 1));
+        if (keep && pos < k) {
+            nbr[i * k + pos] = key_id(v[p]);
+            if (dist) dist[i * k + pos] = key_dist(v[p]);
         }
+        kept += __builtin_popcountll(m);
+    }
+    for (int e = kept + l; e < k; e += 64) {
+        nbr[i * k + e] = SG_NONE;
+        if (dist) dist[i * k + e] = __builtin_inff();
     }
 }
 
@@ -1199,5 +1219,32 @@ extern "C" sg_status sg_knn_rows(const void* X, sg_dtype dtype, int64_t n, int32
         SG_REQUIRE(rows != nullptr && nbr != nullptr, "NULL pointer");
         knn::run(X, dtype, n, d, ld, metric, k, prec, rerank, rows, nq, nbr, dist, ws, ws_bytes,
                  as_stream(stream));
+    });
+}
+
+extern "C" sg_status sg_rerank(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t ld, sg_metric metric,
+                               const int32_t* cand, int32_t c, int32_t k, int32_t* nbr, float* dist,
+                               void* stream) {
+    return guarded([&] {
+        SG_REQUIRE(n >= 0 && n < (1ll << 31), "n out of range");
+        SG_REQUIRE(d >= 1 && d <= 4096 && ld >= d, "bad d / ld");
+        SG_REQUIRE(c >= 1 && c <= 256 && k >= 1 && k <= c, "need 1 <= k <= c <= 256");
+        SG_REQUIRE(metric == SG_L2 || metric == SG_IP, "unknown metric");
+        SG_REQUIRE(dtype >= SG_F32 && dtype <= SG_U8, "unknown dtype");
+        if (n == 0) return;
+        SG_REQUIRE(X && cand && nbr, "NULL pointer");
+        hipStream_t s = as_stream(stream);
+        const size_t shm = (size_t)4 * d * sizeof(float);
+        const unsigned grid = (unsigned)cdiv(n, 4);
+        if (c <= 64)
+            knn::rerank_kernel<1, int32_t><<<grid, 256, shm, s>>>(X, dtype, n, d, ld, metric, nullptr, n, cand, c, c,
+                                                                  k, nbr, dist);
+        else if (c <= 128)
+            knn::rerank_kernel<2, int32_t><<<grid, 256, shm, s>>>(X, dtype, n, d, ld, metric, nullptr, n, cand, c, c,
+                                                                  k, nbr, dist);
+        else
+            knn::rerank_kernel<4, int32_t><<<grid, 256, shm, s>>>(X, dtype, n, d, ld, metric, nullptr, n, cand, c, c,
+                                                                  k, nbr, dist);
+        SG_LAUNCH_CHECK();
     });
 }

@@ -163,3 +163,10 @@ def test_pair_dist_line_and_knn_agree():
     assert oracle.pair_dist(X64, [2], [7], oracle.IP).tolist() == [-14.0]
     nbr, dist = oracle.knn(X64, 5)
     np.testing.assert_array_equal(oracle.pair_dist(X64, np.repeat(np.arange(n)[:, None], 5, 1), nbr), dist)
+
+
+def test_rerank_skips_self_and_repeats():
+    X = np.arange(12, dtype=np.float32).reshape(4, 3)
+    cand = np.array([[0, 1, 1, 2], [1, 0, 3, -1], [3, 3, 2, 0], [2, 3, 1, 1]], np.int32)
+    nbr, _ = oracle.rerank(oracle.widen(X), cand, 3)
+    assert nbr.tolist() == [[1, 2, -1], [0, 3, -1], [3, 0, -1], [2, 1, -1]]
