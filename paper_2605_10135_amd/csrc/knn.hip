@@ -540,45 +540,53 @@ __device__ inline void write_lists(const uint64_t* __restrict__ state, int ksel,
     }
 }
 
-// Fused distance tile + top-k with register-resident queries.  WAVES waves
-// per workgroup, QB blocks of 32 queries per wave (NQ = 32*QB*WAVES queries
-// per workgroup).  Candidate tiles (BC rows) are staged in LDS, double
-// buffered, the next tile already in flight in registers while the current
-// one is computed.  Within a tile the MFMAs of subtile s+1 are issued before
-// the selection epilogue of subtile s so that both run at once.
+// LDS of the register-resident kernel.
+template <int P, int NSTEP, int WAVES, int QB>
+struct TopkSmem {
+    using S = Shape<P, NSTEP>;
+    static constexpr int NQ = 32 * QB * WAVES;
+    __align__(16) uint8_t tile[2][S::BC * S::RS];
+    __align__(16) float norm[2][S::BC];
+    int32_t sexp[2][P == SG_PREC_FP8 ? S::BC : 1];
+    uint64_t buf[NQ * CB];
+    int cnt[NQ];
+};
+
+// One block of NQ = 32*QB*WAVES queries (query rows qb*NQ.. of qops) against
+// all n candidate rows of ops: the fused distance tile + top-k with
+// register-resident queries.  Candidate tiles (BC rows) are staged in LDS,
+// double buffered, the next tile already in flight in registers while the
+// current one is computed.  Within a tile the MFMAs of subtile s+1 are
+// issued before the selection epilogue of subtile s so that both run at once.
 template <int P, int NSTEP, int KSEL, int WAVES, int QB>
-__global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_kernel(
-    const uint8_t* __restrict__ ops, const float* __restrict__ ninit, const int32_t* __restrict__ sexp,
-    int n, const uint8_t* __restrict__ qops, const int64_t* __restrict__ qid,
-    const float* __restrict__ qnout, const int32_t* __restrict__ qsexp, int nq, float qmul, float osc,
-    uint64_t* __restrict__ state, int32_t* __restrict__ nbr, float* __restrict__ dist, int k_out) {
+__device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB>& sm, int64_t qb, const uint8_t* __restrict__ ops,
+                           const float* __restrict__ ninit, const int32_t* __restrict__ sexp, int n,
+                           const uint8_t* __restrict__ qops, const int64_t* __restrict__ qid,
+                           const float* __restrict__ qnout, const int32_t* __restrict__ qsexp, int nq,
+                           float qmul, float osc, uint64_t* __restrict__ state, int32_t* __restrict__ nbr,
+                           float* __restrict__ dist, int k_out) {
     using S = Shape<P, NSTEP>;
     constexpr int BC = S::BC, NSUB = S::NSUB, RB = S::ROW_BYTES, RS = S::RS;
     constexpr int NT = WAVES * 64;
     constexpr int NQ = 32 * QB * WAVES;
     constexpr int CHUNKS = BC * RB / 16;                        // 16-byte chunks per tile
     constexpr int CPT = (CHUNKS + NT - 1) / NT;                 // chunks per thread
-    __shared__ __align__(16) uint8_t s_tile[2][BC * RS];
-    __shared__ __align__(16) float s_norm[2][BC];
-    __shared__ int32_t s_sexp[2][P == SG_PREC_FP8 ? BC : 1];
-    __shared__ uint64_t s_buf[NQ * CB];
-    __shared__ int s_cnt[NQ];
 
     const int tid = threadIdx.x;
     const int l = tid & 63;
     const int w = tid >> 6;
     const int h = l >> 5;
     const int ql = l & 31;
-    const int64_t qblk0 = (int64_t)blockIdx.x * NQ + w * 32 * QB;   // first query of this wave
+    const int64_t qblk0 = qb * NQ + w * 32 * QB;   // first query of this wave
 
-    for (int t = tid; t < NQ; t += NT) s_cnt[t] = 0;
+    for (int t = tid; t < NQ; t += NT) sm.cnt[t] = 0;
 
     Frag<P, NSTEP> qf[QB];
     int q_scale[QB];
     Selector<KSEL, QB> sel;
     sel.state = state + qblk0 * KSEL;
-    sel.buf = s_buf + w * 32 * QB * CB;
-    sel.cnt = s_cnt + w * 32 * QB;
+    sel.buf = sm.buf + w * 32 * QB * CB;
+    sel.cnt = sm.cnt + w * 32 * QB;
 #pragma unroll
     for (int b = 0; b < QB; ++b) {
         const int64_t qg = qblk0 + b * 32 + ql;
@@ -612,22 +620,22 @@ __global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_kernel(
             const int c = tid + u * NT;
             if (c < CHUNKS) {
                 const int r = c / (RB / 16), o = c % (RB / 16);
-                *reinterpret_cast<intx4*>(&s_tile[buf][r * RS + o * 16]) = pre[u];
+                *reinterpret_cast<intx4*>(&sm.tile[buf][r * RS + o * 16]) = pre[u];
             }
         }
         if (tid < BC) {
-            s_norm[buf][tid] = pre_norm;
-            if constexpr (P == SG_PREC_FP8) s_sexp[buf][tid] = pre_sexp;
+            sm.norm[buf][tid] = pre_norm;
+            if constexpr (P == SG_PREC_FP8) sm.sexp[buf][tid] = pre_sexp;
         }
     };
     auto compute = [&](floatx16 (&acc)[QB], int buf, int sub) {
         floatx4 nv[4];
 #pragma unroll
         for (int g = 0; g < 4; ++g)
-            nv[g] = *reinterpret_cast<const floatx4*>(&s_norm[buf][sub * 32 + g * 8 + h * 4]);
+            nv[g] = *reinterpret_cast<const floatx4*>(&sm.norm[buf][sub * 32 + g * 8 + h * 4]);
         int a_scale = 127;
-        if constexpr (P == SG_PREC_FP8) a_scale = 127 + s_sexp[buf][sub * 32 + ql];
-        const uint8_t* arow = &s_tile[buf][(sub * 32 + ql) * RS + h * (RB / 2)];
+        if constexpr (P == SG_PREC_FP8) a_scale = 127 + sm.sexp[buf][sub * 32 + ql];
+        const uint8_t* arow = &sm.tile[buf][(sub * 32 + ql) * RS + h * (RB / 2)];
 #pragma unroll
         for (int b = 0; b < QB; ++b) {
 #pragma unroll
@@ -665,6 +673,53 @@ __global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_kernel(
     }
     sel.drain();
     if (nbr) write_lists(state, KSEL, qblk0, 32 * QB, nq, qnout, osc, nbr, dist, k_out);
+    __syncthreads();   // LDS is reused by the next block of a persistent workgroup
+}
+
+// One query block per workgroup (blockIdx.x).
+template <int P, int NSTEP, int KSEL, int WAVES, int QB>
+__global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_kernel(
+    const uint8_t* __restrict__ ops, const float* __restrict__ ninit, const int32_t* __restrict__ sexp,
+    int n, const uint8_t* __restrict__ qops, const int64_t* __restrict__ qid,
+    const float* __restrict__ qnout, const int32_t* __restrict__ qsexp, int nq, float qmul, float osc,
+    uint64_t* __restrict__ state, int32_t* __restrict__ nbr, float* __restrict__ dist, int k_out) {
+    __shared__ TopkSmem<P, NSTEP, WAVES, QB> sm;
+    topk_block<P, NSTEP, KSEL, WAVES, QB>(sm, blockIdx.x, ops, ninit, sexp, n, qops, qid, qnout, qsexp, nq, qmul,
+                                          osc, state, nbr, dist, k_out);
+}
+
+// Many shards in one launch: a persistent grid pulls (shard, query block)
+// items from a counter in the order of the work list (largest shards first)
+// and runs each as above.  Shard s occupies operand / state rows
+// [row0[s], row0[s] + ceil(n[s]/NQ)*NQ) and output rows [out0[s], out0[s] + n[s]);
+// candidate ids are shard-local.  Every workgroup leaves once the counter
+// passes the last item.
+template <int P, int NSTEP, int KSEL, int WAVES, int QB>
+__global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_persistent_kernel(
+    const uint8_t* __restrict__ ops, const float* __restrict__ ninit, const float* __restrict__ nout,
+    const int32_t* __restrict__ sexp, const int64_t* __restrict__ row0, const int32_t* __restrict__ nrows,
+    const int64_t* __restrict__ out0, const int32_t* __restrict__ items, int nitems,
+    unsigned int* __restrict__ counter, float qmul, float osc, uint64_t* __restrict__ state,
+    int32_t* __restrict__ nbr, float* __restrict__ dist, int k_out) {
+    __shared__ TopkSmem<P, NSTEP, WAVES, QB> sm;
+    __shared__ int s_item;
+    using S = Shape<P, NSTEP>;
+    constexpr int RB = S::ROW_BYTES;
+    while (true) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= nitems) break;
+        const int sh = items[2 * it], qb = items[2 * it + 1];
+        const int64_t r0 = row0[sh];
+        const int ns = nrows[sh];
+        const uint8_t* o = ops + r0 * RB;
+        topk_block<P, NSTEP, KSEL, WAVES, QB>(sm, qb, o, ninit + r0, sexp ? sexp + r0 : nullptr, ns, o, nullptr,
+                                              nout + r0, sexp ? sexp + r0 : nullptr, ns, qmul, osc,
+                                              state + r0 * KSEL, nbr + out0[sh] * k_out,
+                                              dist ? dist + out0[sh] * k_out : nullptr, k_out);
+    }
 }
 
 // Fused distance tile + top-k for FP32 rows too wide for register-resident
