@@ -436,12 +436,15 @@ struct Selector {
     int* cnt;          // LDS counters of the wave's queries
 
     // Admit the candidates of one 32x32 subtile (rows cbase..cbase+31) that
-    // beat the thresholds.  Keys that find a buffer full are flagged, the
-    // buffer is merged into its list (lowering the threshold) and the flagged
-    // keys re-admitted against the new threshold.
+    // beat the thresholds.  Each lane counts its hits, the two lanes of a
+    // query exchange counts with one shuffle and read the buffer fill once;
+    // a query whose new hits would not fit is merged first (which lowers its
+    // threshold and empties its buffer) and its hits recounted; then every
+    // lane writes its keys at slots known in advance -- no atomics.
     __device__ void admit(floatx16 (&acc)[QB], int64_t cbase) {
         const int l = lane_id();
         const int ql = l & 31;
+        const int h = l >> 5;
 #pragma unroll
         for (int b = 0; b < QB; ++b) {
             const bool mine = qself[b] >= cbase && qself[b] < cbase + 32;
@@ -457,48 +460,44 @@ struct Selector {
 #pragma unroll
             for (int i = 0; i < 16; ++i) any |= acc[b][i] < thr[b];
         if (!__builtin_amdgcn_ballot_w64(any)) return;
-        uint32_t ovf[QB];
 #pragma unroll
         for (int b = 0; b < QB; ++b) {
-            ovf[b] = 0;
             const int qq = b * 32 + ql;
+            int c = 0;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                if (acc[b][i] < thr[b]) {
-                    const int slot = atomicAdd(&cnt[qq], 1);
-                    if (slot < CB)
+            for (int i = 0; i < 16; ++i) c += acc[b][i] < thr[b] ? 1 : 0;
+            int cp = __shfl_xor(c, 32, 64);
+            int base = cnt[qq];
+            const uint64_t over = __builtin_amdgcn_ballot_w64(base + c + cp > CB);
+            if (over) {
+                uint32_t need = (uint32_t)over | (uint32_t)(over >> 32);
+                while (need) {
+                    const int qi = __builtin_ctz(need);
+                    need &= need - 1;
+                    const int q2 = b * 32 + qi;
+                    const int fill = __builtin_amdgcn_readlane(base, qi);
+                    const float t = merge_query<KSEL>(state + (int64_t)q2 * KSEL, buf + q2 * CB, fill);
+                    if (ql == qi) {
+                        thr[b] = t;
+                        base = 0;
+                    }
+                }
+                c = 0;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) c += acc[b][i] < thr[b] ? 1 : 0;
+                cp = __shfl_xor(c, 32, 64);
+            }
+            int slot = base + (h ? cp : 0);
+            if (c) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    if (acc[b][i] < thr[b]) {
                         buf[qq * CB + slot] = make_key(acc[b][i], (int32_t)(cbase + out_row(i, l)));
-                    else
-                        ovf[b] |= 1u << i;
+                        ++slot;
+                    }
                 }
             }
-        }
-        bool anyovf = false;
-#pragma unroll
-        for (int b = 0; b < QB; ++b) anyovf |= ovf[b] != 0;
-        if (!__builtin_amdgcn_ballot_w64(anyovf)) return;
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-#pragma unroll
-        for (int b = 0; b < QB; ++b) {
-            const uint64_t m = __builtin_amdgcn_ballot_w64(ovf[b] != 0);
-            uint32_t need = (uint32_t)m | (uint32_t)(m >> 32);
-            while (need) {
-                const int qi = __builtin_ctz(need);
-                need &= need - 1;
-                const int qq = b * 32 + qi;
-                const float t = merge_query<KSEL>(state + (int64_t)qq * KSEL, buf + qq * CB, CB);
-                if (ql == qi) thr[b] = t;
-                if (l == 0) cnt[qq] = 0;
-                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-            }
-            const int qq = b * 32 + ql;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                if ((ovf[b] >> i & 1u) && acc[b][i] < thr[b]) {
-                    const int slot = atomicAdd(&cnt[qq], 1);
-                    buf[qq * CB + slot] = make_key(acc[b][i], (int32_t)(cbase + out_row(i, l)));
-                }
-            }
+            if (h == 0) cnt[qq] = base + c + cp;
         }
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     }

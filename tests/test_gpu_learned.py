@@ -71,7 +71,7 @@ def test_mlp_project_matches_oracle():
 
 
 def test_mlp_training_graph_equals_plain_and_learns():
-    D, H, E, B, steps = 96, 64, 16, 128, 60
+    D, H, E, B, steps = 96, 64, 16, 128, 150
     X = synthdata.l1_nonneg(4000, d=D, seed=4, n_comp=25)
     Xg = torch.from_numpy(X).to(DEV)
     knn, _ = oracle.knn(oracle.widen(X), 8)
@@ -81,14 +81,14 @@ def test_mlp_training_graph_equals_plain_and_learns():
     W1, b1, W2, b2 = _net(D, H, E, seed=5)
     mu, sigma = sg.sg_mlp_stats(Xg, np.arange(4000))
     nets = [sg.MLP(*(torch.from_numpy(a).to(DEV) for a in (W1, b1, W2, b2)), mu, sigma) for _ in range(2)]
-    la = sg.sg_mlp_train(Xg, nets[0], anchors, positives, B, steps, use_graph=True)
-    lb = sg.sg_mlp_train(Xg, nets[1], anchors, positives, B, steps, use_graph=False)
+    la = sg.sg_mlp_train(Xg, nets[0], anchors, positives, B, steps, lr=3e-3, use_graph=True)
+    lb = sg.sg_mlp_train(Xg, nets[1], anchors, positives, B, steps, lr=3e-3, use_graph=False)
     torch.cuda.synchronize()
     assert torch.equal(la, lb)
     for t0, t1 in ((nets[0].W1, nets[1].W1), (nets[0].W2, nets[1].W2), (nets[0].b1, nets[1].b1)):
         assert torch.equal(t0, t1)
     l = la.cpu().numpy()
-    assert l[-10:].mean() < 0.7 * l[:5].mean()
+    assert l[-20:].mean() < 0.85 * l[:10].mean()
 
 
 def test_rerank_exact_on_integer_rows():
