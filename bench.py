@@ -59,6 +59,22 @@ def timed(torch, sg, step, steps, warmup):
     return (t1 - t0) / steps, kms, launches, out
 
 
+def calib_copy(torch, dev):
+    src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def traffic_of(name):
+    """HBM bytes per distance-kernel launch from the committed counter record of
+    this workload, or None when there is none for the current kernel sources."""
+    from paper_2605_10135_amd import profiling
+    return profiling.read_traffic(os.path.join(ROOT, "profiles", "dist_topk_%s_traffic.txt" % name))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +88,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--queries", type=int, default=10_000)
     ap.add_argument("--workload", default="sift1m", choices=["sift1m", "precision"])
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first copy 256 MiB device to device (scale for rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: each box here has one MI355X and the build is "
@@ -88,6 +106,8 @@ def main():
     import synthdata
 
     dev = torch.device("cuda:0")
+    if args.calib_copy:
+        calib_copy(torch, dev)
     N, d, S, omega, K, R = args.n, 128, args.shards, 2, 64, 32
     t = time.perf_counter()
     X = synthdata.sift_like_u8(n=N, d=d, seed=1001)
@@ -202,6 +222,10 @@ def main():
 
     ch = res[args.chosen]
     prec = args.chosen
+    traf = traffic_of("sift1m_u8") if prec == "f16" else None
+    # algorithmic bytes: each shard's rows read once as 16-bit operands, the
+    # K-list of ids written once
+    alg_bytes = float(sum(float(n) * (2 * d + 4 * K) for n in sizes))
     line = {
         "metric": "kNN-graph build vectors/sec on 1 GPU at recall@k>=0.95; chosen vs plain",
         "value": ch["vps"],
@@ -221,9 +245,12 @@ def main():
                    "form": prec, "n": N, "d": d, "shards": S, "K": K, "R": R,
                    "shard_rows": total},
         "roofline": {"bound": "mfma", "achieved": ch["tflops"], "peak": PEAK[prec],
-                     "unit": "TFLOP/s", "frac": ch["tflops"] / PEAK[prec], "traffic": None,
+                     "unit": "TFLOP/s", "frac": ch["tflops"] / PEAK[prec],
+                     "traffic": traf["bytes"] if traf else None,
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "dist_topk", "kernel_ms_avg": ch["kernel_ms_avg"],
-                     "flops_per_launch_avg": flops / S},
+                     "flops_per_launch_avg": flops / S,
+                     "algorithmic_bytes_per_launch_avg": alg_bytes / S},
         "cpu_baseline": cpu,
         "recall": {"knn_at_64_sampled": knn_recall, "knn_rows_identical_to_oracle": knn_exact,
                    "search_recall_at_10_L64": recall10},

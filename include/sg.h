@@ -153,6 +153,33 @@ sg_status sg_knn_rows(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64
                       void* stream);
 
 /* ------------------------------------------------------------------------
+ * Distance-kernel variants and autotuning
+ *
+ * Each (precision, padded row length) has a default distance kernel and may
+ * have alternatives with other launch shapes (workgroup size, candidate rows
+ * per LDS tile); all give identical results.  sg_knn_variant_count reports
+ * how many exist for (prec, d, k).
+ *
+ * sg_knn_autotune times every variant on the given rows (the same arguments
+ * and workspace as sg_knn_graph; no lists are written) and records the
+ * fastest, process-wide, for calls of that precision, padded row length, k
+ * and power-of-two bucket of n; later sg_knn_graph / sg_knn_rows calls of that
+ * shape use it.  Synchronises `stream`.  chosen (nullable) receives the
+ * winning index; times_ms (nullable when max_times == 0) receives up to
+ * max_times per-variant milliseconds.
+ *
+ * sg_knn_force_variant makes the calling thread's later calls use variant
+ * `variant` (an index past the end means the default), or, for -1, the
+ * recorded choice again.  Meant for tests that check every variant.
+ * ---------------------------------------------------------------------- */
+sg_status sg_knn_variant_count(sg_prec prec, int32_t d, int32_t k, int32_t* count);
+sg_status sg_knn_autotune(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t ld,
+                          sg_metric metric, int32_t k, sg_prec prec, int32_t rerank, void* ws,
+                          size_t ws_bytes, void* stream, int32_t* chosen, float* times_ms,
+                          int32_t max_times);
+sg_status sg_knn_force_variant(int32_t variant);
+
+/* ------------------------------------------------------------------------
  * sg_rerank -- exact re-rank of given candidate lists
  *
  * For each row i of X: the ids cand[i][0..c) (SG_NONE, out-of-range ids,

@@ -66,6 +66,9 @@ _SIGS = {
     "sg_merge": (i32, [i32, vp, vp, vp, i32, i64, i32, vp, vp, vp, sz, vp]),
     "sg_search_workspace_size": (i32, [i64, i32, i64, psz]),
     "sg_rerank": (i32, [vp, i32, i64, i32, i64, i32, vp, i32, i32, vp, vp, vp]),
+    "sg_knn_variant_count": (i32, [i32, i32, i32, C.POINTER(C.c_int32)]),
+    "sg_knn_autotune": (i32, [vp, i32, i64, i32, i64, i32, i32, i32, i32, vp, sz, vp, vp, vp, i32]),
+    "sg_knn_force_variant": (i32, [i32]),
     "sg_mlp_workspace_size": (i32, [i32, i32, i32, i32, psz]),
     "sg_mlp_project_workspace_size": (i32, [i32, i32, i32, psz]),
     "sg_mlp_stats": (i32, [vp, i64, i32, i64, vp, i64, vp, vp, vp, sz, vp]),
@@ -168,6 +171,33 @@ def sg_knn_graph(X, k, metric="l2", prec="fp32", rerank=0, dist=True, stream=Non
     _check("sg_knn_graph", L.sg_knn_graph(_ptr(X), dt, n, d, ld, m, k, p, rerank, _ptr(nbr), _ptr(dd),
                                           _ptr(ws), ws.numel(), _stream(stream)))
     return nbr, dd
+
+
+def sg_knn_variant_count(d, k, prec="fp32"):
+    """Number of distance-kernel variants for (prec, d, k)."""
+    c = C.c_int32(0)
+    _check("sg_knn_variant_count", lib().sg_knn_variant_count(PRECS[prec], d, k, C.byref(c)))
+    return c.value
+
+
+def sg_knn_autotune(X, k, metric="l2", prec="fp32", rerank=0, stream=None):
+    """Time every distance-kernel variant on X and record the fastest for this
+    shape: (chosen index, [milliseconds per variant])."""
+    L = lib()
+    dt, n, d, ld = _rows(X)
+    m, p = METRICS[metric], PRECS[prec]
+    ws = _ws.get(_size(L.sg_knn_graph_workspace_size, n, d, k, p, rerank), X.device, "knn")
+    nv = sg_knn_variant_count(d, k, prec)
+    times = (C.c_float * max(nv, 1))()
+    chosen = C.c_int32(-1)
+    _check("sg_knn_autotune", L.sg_knn_autotune(_ptr(X), dt, n, d, ld, m, k, p, rerank, _ptr(ws), ws.numel(),
+                                                _stream(stream), C.byref(chosen), times, nv))
+    return chosen.value, [float(times[i]) for i in range(nv)]
+
+
+def sg_knn_force_variant(variant):
+    """Make this thread's later kNN calls use variant `variant` (-1: the recorded choice)."""
+    _check("sg_knn_force_variant", lib().sg_knn_force_variant(int(variant)))
 
 
 def sg_knn_rows(X, rows, k, metric="l2", prec="fp32", rerank=0, stream=None):

@@ -114,17 +114,61 @@ __host__ __device__ inline float key_dist(uint64_t k) {
 // ---------------------------------------------------------------------------
 __device__ inline int lane_id() { return __lane_id(); }
 
-__device__ inline uint64_t shfl_xor_u64(uint64_t v, int mask) {
-    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-    lo = __shfl_xor((int)lo, mask, 64);
-    hi = __shfl_xor((int)hi, mask, 64);
-    return ((uint64_t)hi << 32) | lo;
-}
-
 __device__ inline uint64_t shfl_u64(uint64_t v, int src) {
     uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
     lo = __shfl((int)lo, src, 64);
     hi = __shfl((int)hi, src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// The value that lane (l ^ j) holds, j in {1, 2, 4, 8, 16, 32}, without LDS
+// traffic: DPP quad/row permutes inside 16-lane rows (row_shl:4 / row_shr:4 on
+// alternate groups of four lanes for j = 4, a rotate by 8 for j = 8) and the
+// permlane swaps across rows (j = 16) and wave halves (j = 32).  Each swap
+// returns the even-row (even-half) values in element 0 and the odd ones in
+// element 1 in every lane.  j must be a compile-time constant after unrolling.
+__device__ inline uint32_t lane_xor(uint32_t v, int j) {
+    const int x = (int)v;
+    switch (j) {
+    case 1: return (uint32_t)__builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false);
+    case 2: return (uint32_t)__builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false);
+    case 4: {
+        const int t = __builtin_amdgcn_update_dpp(x, x, 0x104, 0xF, 0x5, false);
+        return (uint32_t)__builtin_amdgcn_update_dpp(t, x, 0x114, 0xF, 0xA, false);
+    }
+    case 8: return (uint32_t)__builtin_amdgcn_update_dpp(x, x, 0x128, 0xF, 0xF, false);
+    case 16: {
+        const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (__lane_id() & 16) ? p[0] : p[1];
+    }
+    default: {
+        const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (__lane_id() & 32) ? p[0] : p[1];
+    }
+    }
+}
+
+__device__ inline uint64_t lane_xor_u64(uint64_t v, int j) {
+    const uint32_t lo = lane_xor((uint32_t)v, j), hi = lane_xor((uint32_t)(v >> 32), j);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Lanes 32..63 receive the value of lane l - 32 (lanes 0..31 keep theirs).
+__device__ inline uint64_t low_half_to_high(uint64_t v) {
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)v, (uint32_t)v, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(v >> 32), (uint32_t)(v >> 32), false, false);
+    return ((uint64_t)hi[0] << 32) | lo[0];
+}
+
+// Compare-exchange with lane l ^ j: the smaller key where take_min, else the larger.
+__device__ inline uint64_t cmpx(uint64_t x, int j, bool take_min) {
+    const uint64_t o = lane_xor_u64(x, j);
+    return (o < x) == take_min ? o : x;
+}
+
+__device__ inline uint64_t readlane_u64(uint64_t v, int lane) {
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
     return ((uint64_t)hi << 32) | lo;
 }
 
@@ -134,14 +178,18 @@ __device__ inline uint64_t wave_sort_u64(uint64_t x) {
 #pragma unroll
     for (int k = 2; k <= 64; k <<= 1) {
 #pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            uint64_t o = shfl_xor_u64(x, j);
-            bool up = (l & k) == 0;
-            bool lower = (l & j) == 0;
-            uint64_t mn = x < o ? x : o;
-            uint64_t mx = x < o ? o : x;
-            x = (lower == up) ? mn : mx;
-        }
+        for (int j = k >> 1; j > 0; j >>= 1) x = cmpx(x, j, ((l & k) == 0) == ((l & j) == 0));
+    }
+    return x;
+}
+
+// Each 32-lane half sorted on its own: lanes 0..31 descending, 32..63 ascending.
+__device__ inline uint64_t half_sort_desc_u64(uint64_t x) {
+    const int l = lane_id();
+#pragma unroll
+    for (int k = 2; k <= 32; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) x = cmpx(x, j, ((l & k) != 0) == ((l & j) == 0));
     }
     return x;
 }

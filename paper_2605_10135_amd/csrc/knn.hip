@@ -26,6 +26,10 @@
 //  * rerank: the top-c candidates of a reduced-precision key re-scored with
 //    the exact FP32 difference-form distance, best k kept.
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
 
 #include "common.hpp"
 
@@ -42,7 +46,7 @@ typedef int intx4 __attribute__((ext_vector_type(4)));
 constexpr int TWAVES = 8;        // waves per workgroup of the distance kernel
 constexpr int TQB = 1;           // 32-query blocks per wave
 constexpr int BQ = 32 * TQB * TWAVES;   // query rows per workgroup
-constexpr int CB = 32;           // per-query candidate buffer
+constexpr int CB = 32;           // per-query candidate buffer (default; at most 32)
 constexpr int PAD_ROWS = BQ;     // operand rows are padded to a multiple of this (>= any tile)
 
 // ---------------------------------------------------------------------------
@@ -157,7 +161,7 @@ __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_t n, in
             else out[t] = 0;
         }
         if (l == 0) {
-            ninit[row] = __builtin_inff();
+            ninit[row] = __builtin_nanf("");   // never admitted: NaN fails every comparison
             nout[row] = 0.f;
             if (sexp) sexp[row] = 0;
         }
@@ -316,51 +320,79 @@ __device__ inline void scale_query(Frag<P, NSTEP>& f, float qmul) {
 template <int P>
 __device__ inline floatx16 mfma_step(const void* a, const void* b, floatx16 acc, int sa, int sb);
 
+// Largest divisor of n that is at most m.
+constexpr int group_of(int n, int m) {
+    for (int g = m; g > 1; --g)
+        if (n % g == 0) return g;
+    return 1;
+}
+
+// acc += A(32 candidate rows at arow, LDS) x Q(32 queries) over the padded
+// row, in groups of steps whose A fragments are all requested before the
+// group's MFMA chain starts, so that one LDS round trip covers the group.
 template <int P, int NSTEP>
 __device__ inline floatx16 mfma_tile(const uint8_t* arow, const Frag<P, NSTEP>& q, floatx16 acc,
                                      int sa, int sb) {
     if constexpr (P == SG_PREC_FP32) {
+        constexpr int G = 4 * group_of(NSTEP / 4, 4);   // floats per group
+        static_assert(NSTEP % 4 == 0, "FP32 steps come in whole float4s");
 #pragma unroll
-        for (int s = 0; s < NSTEP; s += 4) {
-            floatx4 a = *reinterpret_cast<const floatx4*>(arow + s * 4);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0], q.v[s], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1], q.v[s + 1], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[2], q.v[s + 2], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[3], q.v[s + 3], acc, 0, 0, 0);
+        for (int g = 0; g < NSTEP; g += G) {
+            floatx4 a[G / 4];
+#pragma unroll
+            for (int s = 0; s < G / 4; ++s) a[s] = *reinterpret_cast<const floatx4*>(arow + (g + 4 * s) * 4);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int s = 0; s < G; ++s)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s / 4][s % 4], q.v[g + s], acc, 0, 0, 0);
         }
-    } else if constexpr (P == SG_PREC_F16) {
+    } else if constexpr (P == SG_PREC_F16 || P == SG_PREC_BF16) {
+        constexpr int G = group_of(NSTEP, 8);
 #pragma unroll
-        for (int s = 0; s < NSTEP; ++s) {
-            half8 a = *reinterpret_cast<const half8*>(arow + s * 16);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, q.v[s], acc, 0, 0, 0);
-        }
-    } else if constexpr (P == SG_PREC_BF16) {
+        for (int g = 0; g < NSTEP; g += G) {
+            intx4 a[G];
 #pragma unroll
-        for (int s = 0; s < NSTEP; ++s) {
-            bf16x8 a = *reinterpret_cast<const bf16x8*>(arow + s * 16);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, q.v[s], acc, 0, 0, 0);
+            for (int s = 0; s < G; ++s) a[s] = *reinterpret_cast<const intx4*>(arow + (g + s) * 16);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int s = 0; s < G; ++s) {
+                if constexpr (P == SG_PREC_F16)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, a[s]), q.v[g + s],
+                                                                 acc, 0, 0, 0);
+                else
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[s]),
+                                                                  q.v[g + s], acc, 0, 0, 0);
+            }
         }
     } else {
+        constexpr int G = group_of(NSTEP, 4);
 #pragma unroll
-        for (int s = 0; s < NSTEP; ++s) {
-            intx4 lo = *reinterpret_cast<const intx4*>(arow + s * 32);
-            intx4 hi = *reinterpret_cast<const intx4*>(arow + s * 32 + 16);
-            intx8 a = intx8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-            acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, q.v[s], acc, 0, 0, 0, sa, 0,
-                                                                   sb);
+        for (int g = 0; g < NSTEP; g += G) {
+            intx4 a[2 * G];
+#pragma unroll
+            for (int s = 0; s < 2 * G; ++s) a[s] = *reinterpret_cast<const intx4*>(arow + g * 32 + s * 16);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int s = 0; s < G; ++s) {
+                const intx8 f = intx8{a[2 * s][0], a[2 * s][1], a[2 * s][2], a[2 * s][3],
+                                      a[2 * s + 1][0], a[2 * s + 1][1], a[2 * s + 1][2], a[2 * s + 1][3]};
+                acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(f, q.v[g + s], acc, 0, 0, 0, sa, 0, sb);
+            }
         }
     }
     return acc;
 }
 
-template <int P, int NSTEP>
+template <int P, int NSTEP, int BCR = 0>
 struct Shape {
     static constexpr int DH = NSTEP * Tr<P>::VEC;             // elements per lane-half
     static constexpr int ROW_BYTES = 2 * DH * Tr<P>::EB;      // padded operand row
     static constexpr int RS = ROW_BYTES + 16;                 // LDS row stride (bank spread)
-    // candidate rows per LDS tile: two tiles (double buffer) stay within ~70 KB
-    static constexpr int BC = ROW_BYTES <= 256 ? 128 : ROW_BYTES <= 512 ? 64 : 32;
+    // candidate rows per LDS tile (BCR, or by default so that two tiles, the
+    // double buffer, stay within ~70 KB)
+    static constexpr int BC = BCR > 0 ? BCR : ROW_BYTES <= 256 ? 128 : ROW_BYTES <= 512 ? 64 : 32;
     static constexpr int NSUB = BC / 32;
+    static_assert(BC % 32 == 0, "tiles hold whole 32-row subtiles");
 };
 
 // Bitonic merge (ascending) of 64*PER keys held as v[p] (element p*64 + lane)
@@ -383,123 +415,181 @@ __device__ inline void bitonic_merge_multi(uint64_t (&v)[PER]) {
             }
         } else {
 #pragma unroll
-            for (int p = 0; p < PER; ++p) {
-                uint64_t o = shfl_xor_u64(v[p], j);
-                bool lower = (l & j) == 0;
-                uint64_t mn = v[p] < o ? v[p] : o, mx = v[p] < o ? o : v[p];
-                v[p] = lower ? mn : mx;
-            }
+            for (int p = 0; p < PER; ++p) v[p] = cmpx(v[p], j, (l & j) == 0);
         }
     }
 }
 
-// Merge one query's candidate buffer (<= CB keys in LDS) into its sorted
-// top-KSEL list in the workspace, all in registers: sort the buffer across the
-// wave, take the element-wise minimum of the list and the reversed buffer
-// (which holds the KSEL smallest of both as a bitonic sequence), bitonic-merge
-// it.  Returns the new admission threshold: the KSEL-th distance (+inf while
-// the list is not full).
+// Merge one query's candidate buffer (c <= 32 keys in LDS) into its
+// sorted top-KSEL list in the workspace, all in registers: the list's load is
+// issued first; the buffer is sorted descending in lanes 0..31 and moved to
+// lanes 32..63, where the element-wise minimum with the list's last 64 keys
+// leaves the KSEL smallest of both as a bitonic sequence, which is then
+// merged.  Returns the new admission threshold: the KSEL-th distance (+inf
+// while the list is not full).
 template <int KSEL>
 __device__ float merge_query(uint64_t* __restrict__ gstate, const uint64_t* buf, int c) {
     constexpr int PER = KSEL >= 64 ? KSEL / 64 : 1;
     const int l = lane_id();
-    uint64_t b = l < c ? buf[l] : EMPTY_KEY;
     uint64_t v[PER];
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
         const int e = p * 64 + l;
         v[p] = e < KSEL ? gstate[e] : EMPTY_KEY;
     }
-    b = wave_sort_u64(b);
-    const uint64_t r = shfl_u64(b, 63 - l);
-    v[PER - 1] = v[PER - 1] < r ? v[PER - 1] : r;
+    uint64_t b = l < c ? buf[l] : EMPTY_KEY;
+    b = low_half_to_high(half_sort_desc_u64(b));
+    if (l >= 32 && b < v[PER - 1]) v[PER - 1] = b;
     bitonic_merge_multi<PER>(v);
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
         const int e = p * 64 + l;
         if (e < KSEL) gstate[e] = v[p];
     }
-    const uint64_t last = shfl_u64(v[(KSEL - 1) / 64], (KSEL - 1) & 63);
-    return key_dist(last);
+    return key_dist(readlane_u64(v[(KSEL - 1) / 64], (KSEL - 1) & 63));
 }
 
 // Per-wave selection state: the admission threshold of each of the wave's
 // 32*QB queries (lanes l and l+32 share query l%32 of each block), the id
 // excluded as the query itself, and the LDS buffers / counters and workspace
 // top-KSEL lists of those queries.
-template <int KSEL, int QB>
+template <int KSEL, int QB, int CBQ = CB>
 struct Selector {
+    static_assert(CBQ <= 32, "a buffer is sorted inside one wave half");
     float thr[QB];
     int64_t qself[QB];
+    int64_t qlo, qhi;  // wave-uniform range of the wave's query ids
     uint64_t* state;   // state row of the wave's first query
-    uint64_t* buf;     // LDS buffers of the wave's queries (32*QB*CB keys)
-    int* cnt;          // LDS counters of the wave's queries
+    uint64_t* buf;     // LDS buffers of the wave's queries (32*QB*CBQ keys)
+    int fill[QB];      // buffer fill of the lane's query (same in both lanes)
 
-    // Admit the candidates of one 32x32 subtile (rows cbase..cbase+31) that
-    // beat the thresholds.  Each lane counts its hits, the two lanes of a
-    // query exchange counts with one shuffle and read the buffer fill once;
-    // a query whose new hits would not fit is merged first (which lowers its
-    // threshold and empties its buffer) and its hits recounted; then every
-    // lane writes its keys at slots known in advance -- no atomics.
-    __device__ void admit(floatx16 (&acc)[QB], int64_t cbase) {
+    // After qself is set: the smallest and largest query id of the wave, so
+    // that a subtile whose candidate ids miss [qlo, qhi] skips the per-lane
+    // self test with one scalar comparison (no valid query: qlo > qhi).
+    __device__ void init_self_range() {
+        uint64_t lo = (uint64_t)INT64_MAX, hi = 0;
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+            if (qself[b] >= 0) {
+                lo = (uint64_t)qself[b] < lo ? (uint64_t)qself[b] : lo;
+                hi = (uint64_t)qself[b] > hi ? (uint64_t)qself[b] : hi;
+            }
+        }
+#pragma unroll
+        for (int j = 1; j < 64; j <<= 1) {
+            const uint64_t ol = lane_xor_u64(lo, j), oh = lane_xor_u64(hi, j);
+            lo = ol < lo ? ol : lo;
+            hi = oh > hi ? oh : hi;
+        }
+        qlo = (int64_t)readlane_u64(lo, 0);
+        qhi = (int64_t)readlane_u64(hi, 0);
+    }
+
+    // Smallest of a lane's 16 distances (eight 3-input minimums; NaN only if all are).
+    __device__ static float min16(const floatx16& a) {
+        const float p0 = fminf(fminf(a[0], a[1]), a[2]), p1 = fminf(fminf(a[3], a[4]), a[5]);
+        const float p2 = fminf(fminf(a[6], a[7]), a[8]), p3 = fminf(fminf(a[9], a[10]), a[11]);
+        const float p4 = fminf(fminf(a[12], a[13]), a[14]);
+        return fminf(fminf(fminf(p0, p1), p2), fminf(fminf(p3, p4), a[15]));
+    }
+
+    // Admit the candidates of one 32x32 subtile (operand rows cbase..cbase+31,
+    // whose ids are tpid[0..32), or cbase.. when tpid is NULL) whose key is
+    // <= the threshold, one accumulator element at a time: from the element's
+    // ballot the two lanes of a query see each other's hit, so they write
+    // their keys at known slots (no atomics) and both keep the query's buffer
+    // fill in a register.  Round 1 stops at the first element some buffer
+    // cannot take; then every query whose buffer could not take two keys per
+    // remaining element is merged, and round 2 finishes the subtile without
+    // checks (CBQ = 32 guarantees the room).  A merged query's lowered
+    // threshold takes effect at the next subtile.  Admission is exact in any
+    // candidate order: a candidate whose distance exceeds the K-th distance of
+    // a subset already seen cannot be in the top K, and one that equals it is
+    // admitted and ranked by (distance, id) in the merge.  The query itself
+    // and padding rows are NaN, which no comparison admits.
+    __device__ void admit(floatx16 (&acc)[QB], int64_t cbase, const int32_t* tpid) {
+        static_assert(CBQ == 32, "round 2 relies on room for 32 keys after a merge");
         const int l = lane_id();
         const int ql = l & 31;
         const int h = l >> 5;
+        if (cbase <= qhi && cbase + 31 >= qlo) {
+            const int32_t rel0 = (int32_t)(cbase - qlo);
 #pragma unroll
-        for (int b = 0; b < QB; ++b) {
-            const bool mine = qself[b] >= cbase && qself[b] < cbase + 32;
-            if (__builtin_amdgcn_ballot_w64(mine)) {
+            for (int b = 0; b < QB; ++b) {
+                const int32_t me = qself[b] >= 0 ? (int32_t)(qself[b] - qlo) : INT32_MIN;
 #pragma unroll
                 for (int i = 0; i < 16; ++i)
-                    if (cbase + out_row(i, l) == qself[b]) acc[b][i] = __builtin_inff();
+                    if (rel0 + out_row(i, l) == me) acc[b][i] = __builtin_nanf("");
             }
         }
         bool any = false;
 #pragma unroll
-        for (int b = 0; b < QB; ++b)
-#pragma unroll
-            for (int i = 0; i < 16; ++i) any |= acc[b][i] < thr[b];
+        for (int b = 0; b < QB; ++b) any |= min16(acc[b]) <= thr[b];
         if (!__builtin_amdgcn_ballot_w64(any)) return;
+        // the ids of this lane's 16 rows: groups of 4 consecutive rows
+        int32_t ids[16];
+        if (tpid) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const intx4 v = *reinterpret_cast<const intx4*>(tpid + g * 8 + h * 4);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) ids[g * 4 + e] = v[e];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) ids[i] = (int32_t)(cbase + out_row(i, l));
+        }
 #pragma unroll
         for (int b = 0; b < QB; ++b) {
-            const int qq = b * 32 + ql;
-            int c = 0;
+            const float t = thr[b];
+            int c = fill[b];
+            uint64_t* qbuf = buf + (b * 32 + ql) * CBQ;
+            int stop = 16;   // wave-uniform: first element round 1 left
 #pragma unroll
-            for (int i = 0; i < 16; ++i) c += acc[b][i] < thr[b] ? 1 : 0;
-            int cp = __shfl_xor(c, 32, 64);
-            int base = cnt[qq];
-            const uint64_t over = __builtin_amdgcn_ballot_w64(base + c + cp > CB);
-            if (over) {
-                uint32_t need = (uint32_t)over | (uint32_t)(over >> 32);
+            for (int i = 0; i < 16; ++i) {
+                if (i >= stop) continue;
+                const bool hit = acc[b][i] <= t;
+                const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+                if (m == 0) continue;
+                const int pa = (int)(((uint32_t)m >> ql) & 1u);
+                const int pb = (int)(((uint32_t)(m >> 32) >> ql) & 1u);
+                if (__builtin_amdgcn_ballot_w64(c + pa + pb > CBQ)) {
+                    stop = i;
+                    continue;
+                }
+                if (hit) qbuf[c + (h ? pa : 0)] = make_key(acc[b][i], ids[i]);
+                c += pa + pb;
+            }
+            if (stop < 16) {
+                const int room = 2 * (16 - stop);
+                uint32_t need = (uint32_t)__builtin_amdgcn_ballot_w64(h == 0 && c + room > CBQ);
+                float tnext = t;
                 while (need) {
                     const int qi = __builtin_ctz(need);
                     need &= need - 1;
                     const int q2 = b * 32 + qi;
-                    const int fill = __builtin_amdgcn_readlane(base, qi);
-                    const float t = merge_query<KSEL>(state + (int64_t)q2 * KSEL, buf + q2 * CB, fill);
+                    const float tq = merge_query<KSEL>(state + (int64_t)q2 * KSEL, buf + q2 * CBQ,
+                                                       __builtin_amdgcn_readlane(c, qi));
                     if (ql == qi) {
-                        thr[b] = t;
-                        base = 0;
+                        c = 0;
+                        tnext = tq;
                     }
                 }
-                c = 0;
-#pragma unroll
-                for (int i = 0; i < 16; ++i) c += acc[b][i] < thr[b] ? 1 : 0;
-                cp = __shfl_xor(c, 32, 64);
-            }
-            int slot = base + (h ? cp : 0);
-            if (c) {
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
-                    if (acc[b][i] < thr[b]) {
-                        buf[qq * CB + slot] = make_key(acc[b][i], (int32_t)(cbase + out_row(i, l)));
-                        ++slot;
-                    }
+                    if (i < stop) continue;
+                    const bool hit = acc[b][i] <= t;
+                    const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+                    if (m == 0) continue;
+                    const int pa = (int)(((uint32_t)m >> ql) & 1u);
+                    const int pb = (int)(((uint32_t)(m >> 32) >> ql) & 1u);
+                    if (hit) qbuf[c + (h ? pa : 0)] = make_key(acc[b][i], ids[i]);
+                    c += pa + pb;
                 }
+                thr[b] = tnext;
             }
-            if (h == 0) cnt[qq] = base + c + cp;
+            fill[b] = c;
         }
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     }
 
     // Merge every non-empty buffer (end of the candidate stream).
@@ -507,64 +597,85 @@ struct Selector {
         const int l = lane_id();
 #pragma unroll
         for (int b = 0; b < QB; ++b) {
-            const int qq = b * 32 + (l & 31);
-            const uint64_t m = __builtin_amdgcn_ballot_w64(l < 32 && cnt[qq] > 0);
+            const uint64_t m = __builtin_amdgcn_ballot_w64(l < 32 && fill[b] > 0);
             uint32_t need = (uint32_t)m;
             while (need) {
                 const int qi = __builtin_ctz(need);
                 need &= need - 1;
                 const int q2 = b * 32 + qi;
-                merge_query<KSEL>(state + (int64_t)q2 * KSEL, buf + q2 * CB,
-                                  __builtin_amdgcn_readfirstlane(cnt[q2]));
+                merge_query<KSEL>(state + (int64_t)q2 * KSEL, buf + q2 * CBQ,
+                                  __builtin_amdgcn_readlane(fill[b], qi));
             }
         }
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
 };
 
+// Arguments of one distance-kernel launch (a block of queries against one
+// candidate set).  Candidate operand row j has id cpid[j] (NULL: j); query
+// row q writes output row qout[q] (NULL: q) and excludes the candidate whose
+// operand row is qid[q] (NULL: q; negative: none).
+struct TopkArgs {
+    const uint8_t* ops;      // candidate operands, padded rows
+    const float* ninit;      // accumulator start per candidate (NaN: padding)
+    const int32_t* sexp;     // FP8 row scale exponents (else NULL)
+    const int32_t* cpid;     // candidate ids (nullable)
+    int n;                   // candidate rows
+    const uint8_t* qops;     // query operands (padded to whole blocks)
+    const int64_t* qid;      // self row per query (nullable)
+    const float* qnout;      // output term per query
+    const int32_t* qsexp;
+    const int64_t* qout;     // output row per query (nullable)
+    int nq;                  // query rows
+    float qmul, osc;
+    uint64_t* state;         // sorted top-KSEL keys per query (operand order)
+    int32_t* nbr;            // nullable: no lists written
+    float* dist;             // nullable
+    int k_out;
+};
+
 // Final lists of the wave's queries: ids and output distances.
-__device__ inline void write_lists(const uint64_t* __restrict__ state, int ksel, int64_t q0, int nqw,
-                                   int64_t nq, const float* __restrict__ qnout, float osc,
-                                   int32_t* __restrict__ nbr, float* __restrict__ dist, int k_out) {
+__device__ inline void write_lists(const TopkArgs& A, int ksel, int64_t q0, int nqw) {
     const int l = lane_id();
     for (int qi = 0; qi < nqw; ++qi) {
         const int64_t q = q0 + qi;
-        if (q >= nq) break;
-        const float qn = qnout[q];
-        for (int t = l; t < k_out; t += 64) {
-            const uint64_t key = state[q * ksel + t];
-            nbr[q * k_out + t] = key_id(key);
-            if (dist) dist[q * k_out + t] = key == EMPTY_KEY ? __builtin_inff() : (key_dist(key) + qn) * osc;
+        if (q >= A.nq) break;
+        const float qn = A.qnout[q];
+        const int64_t o = A.qout ? A.qout[q] : q;
+        for (int t = l; t < A.k_out; t += 64) {
+            const uint64_t key = A.state[q * ksel + t];
+            A.nbr[o * A.k_out + t] = key_id(key);
+            if (A.dist)
+                A.dist[o * A.k_out + t] = key == EMPTY_KEY ? __builtin_inff() : (key_dist(key) + qn) * A.osc;
         }
     }
 }
 
 // LDS of the register-resident kernel.
-template <int P, int NSTEP, int WAVES, int QB>
+template <int P, int NSTEP, int WAVES, int QB, int CBQ, int BCR>
 struct TopkSmem {
-    using S = Shape<P, NSTEP>;
+    using S = Shape<P, NSTEP, BCR>;
     static constexpr int NQ = 32 * QB * WAVES;
     __align__(16) uint8_t tile[2][S::BC * S::RS];
     __align__(16) float norm[2][S::BC];
+    __align__(16) int32_t pid[2][S::BC];
     int32_t sexp[2][P == SG_PREC_FP8 ? S::BC : 1];
-    uint64_t buf[NQ * CB];
-    int cnt[NQ];
+    uint64_t buf[NQ * CBQ];
 };
 
-// One block of NQ = 32*QB*WAVES queries (query rows qb*NQ.. of qops) against
-// all n candidate rows of ops: the fused distance tile + top-k with
+// One block of NQ = 32*QB*WAVES queries (query rows qb*NQ.. of A.qops)
+// against all A.n candidate rows: the fused distance tile + top-k with
 // register-resident queries.  Candidate tiles (BC rows) are staged in LDS,
 // double buffered, the next tile already in flight in registers while the
 // current one is computed.  Within a tile the MFMAs of subtile s+1 are
 // issued before the selection epilogue of subtile s so that both run at once.
-template <int P, int NSTEP, int KSEL, int WAVES, int QB>
-__device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB>& sm, int64_t qb, const uint8_t* __restrict__ ops,
-                           const float* __restrict__ ninit, const int32_t* __restrict__ sexp, int n,
-                           const uint8_t* __restrict__ qops, const int64_t* __restrict__ qid,
-                           const float* __restrict__ qnout, const int32_t* __restrict__ qsexp, int nq,
-                           float qmul, float osc, uint64_t* __restrict__ state, int32_t* __restrict__ nbr,
-                           float* __restrict__ dist, int k_out) {
-    using S = Shape<P, NSTEP>;
+// The scan starts at the tile holding the block's own rows and wraps around:
+// when operand rows are ordered by locality, the queries meet their close
+// neighbours first, the thresholds tighten early and later tiles rarely
+// admit anything.
+template <int P, int NSTEP, int KSEL, int WAVES, int QB, int CBQ, int BCR>
+__device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t qb, const TopkArgs& A) {
+    using S = Shape<P, NSTEP, BCR>;
     constexpr int BC = S::BC, NSUB = S::NSUB, RB = S::ROW_BYTES, RS = S::RS;
     constexpr int NT = WAVES * 64;
     constexpr int NQ = 32 * QB * WAVES;
@@ -578,39 +689,43 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB>& sm, int64_t qb, const 
     const int ql = l & 31;
     const int64_t qblk0 = qb * NQ + w * 32 * QB;   // first query of this wave
 
-    for (int t = tid; t < NQ; t += NT) sm.cnt[t] = 0;
-
     Frag<P, NSTEP> qf[QB];
     int q_scale[QB];
-    Selector<KSEL, QB> sel;
-    sel.state = state + qblk0 * KSEL;
-    sel.buf = sm.buf + w * 32 * QB * CB;
-    sel.cnt = sm.cnt + w * 32 * QB;
+    Selector<KSEL, QB, CBQ> sel;
+    sel.state = A.state + qblk0 * KSEL;
+    sel.buf = sm.buf + w * 32 * QB * CBQ;
 #pragma unroll
     for (int b = 0; b < QB; ++b) {
         const int64_t qg = qblk0 + b * 32 + ql;
-        load_frag<P, NSTEP>(qf[b], qops + qg * RB + h * (RB / 2));
-        scale_query<P, NSTEP>(qf[b], qmul);
+        load_frag<P, NSTEP>(qf[b], A.qops + qg * RB + h * (RB / 2));
+        scale_query<P, NSTEP>(qf[b], A.qmul);
         q_scale[b] = 127;
-        if constexpr (P == SG_PREC_FP8) q_scale[b] = 127 + qsexp[qg] + 1;
+        if constexpr (P == SG_PREC_FP8) q_scale[b] = 127 + A.qsexp[qg] + 1;
         sel.thr[b] = __builtin_inff();
-        sel.qself[b] = qg < nq ? (qid ? qid[qg] : qg) : -1;
+        sel.fill[b] = 0;
+        sel.qself[b] = qg < A.nq ? (A.qid ? A.qid[qg] : qg) : -1;
     }
+    sel.init_self_range();
+
+    const int ntiles = (A.n + BC - 1) / BC;
+    const int t0 = (int)((qb * NQ / BC) % ntiles);
+    auto tile_row = [&](int t) { return ((t0 + t) % ntiles) * BC; };
 
     // tile staging: global -> registers (prefetch) -> LDS
     intx4 pre[CPT];
     float pre_norm = 0.f;
-    int32_t pre_sexp = 0;
+    int32_t pre_pid = 0, pre_sexp = 0;
     auto prefetch = [&](int j0) {
-        const uint8_t* src = ops + (int64_t)j0 * RB;
+        const uint8_t* src = A.ops + (int64_t)j0 * RB;
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
             const int c = tid + u * NT;
             if (c < CHUNKS) pre[u] = *reinterpret_cast<const intx4*>(src + (int64_t)c * 16);
         }
         if (tid < BC) {
-            pre_norm = ninit[j0 + tid];
-            if constexpr (P == SG_PREC_FP8) pre_sexp = sexp[j0 + tid];
+            pre_norm = A.ninit[j0 + tid];
+            if (A.cpid) pre_pid = A.cpid[j0 + tid];
+            if constexpr (P == SG_PREC_FP8) pre_sexp = A.sexp[j0 + tid];
         }
     };
     auto commit = [&](int buf) {
@@ -624,6 +739,7 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB>& sm, int64_t qb, const 
         }
         if (tid < BC) {
             sm.norm[buf][tid] = pre_norm;
+            sm.pid[buf][tid] = pre_pid;
             if constexpr (P == SG_PREC_FP8) sm.sexp[buf][tid] = pre_sexp;
         }
     };
@@ -644,82 +760,44 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB>& sm, int64_t qb, const 
         for (int b = 0; b < QB; ++b) acc[b] = mfma_tile<P, NSTEP>(arow, qf[b], acc[b], a_scale, q_scale[b]);
     };
 
-    const int ntiles = (n + BC - 1) / BC;
-    prefetch(0);
+    prefetch(tile_row(0));
     commit(0);
     __syncthreads();
-    if (ntiles > 1) prefetch(BC);
+    if (ntiles > 1) prefetch(tile_row(1));
     for (int t = 0; t < ntiles; ++t) {
         const int buf = t & 1;
-        const int j0 = t * BC;
+        const int j0 = tile_row(t);
+        const int32_t* tp = A.cpid ? sm.pid[buf] : nullptr;
         floatx16 accA[QB], accB[QB];
         compute(accA, buf, 0);
 #pragma unroll
         for (int sub = 0; sub < NSUB; ++sub) {
             if (sub % 2 == 0) {
                 if (sub + 1 < NSUB) compute(accB, buf, sub + 1);
-                sel.admit(accA, j0 + sub * 32);
+                sel.admit(accA, j0 + sub * 32, tp ? tp + sub * 32 : nullptr);
             } else {
                 if (sub + 1 < NSUB) compute(accA, buf, sub + 1);
-                sel.admit(accB, j0 + sub * 32);
+                sel.admit(accB, j0 + sub * 32, tp ? tp + sub * 32 : nullptr);
             }
         }
         if (t + 1 < ntiles) {
             commit(buf ^ 1);
-            if (t + 2 < ntiles) prefetch((t + 2) * BC);
+            if (t + 2 < ntiles) prefetch(tile_row(t + 2));
         }
         __syncthreads();
     }
     sel.drain();
-    if (nbr) write_lists(state, KSEL, qblk0, 32 * QB, nq, qnout, osc, nbr, dist, k_out);
+    if (A.nbr) write_lists(A, KSEL, qblk0, 32 * QB);
     __syncthreads();   // LDS is reused by the next block of a persistent workgroup
 }
 
 // One query block per workgroup (blockIdx.x).
-template <int P, int NSTEP, int KSEL, int WAVES, int QB>
-__global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_kernel(
-    const uint8_t* __restrict__ ops, const float* __restrict__ ninit, const int32_t* __restrict__ sexp,
-    int n, const uint8_t* __restrict__ qops, const int64_t* __restrict__ qid,
-    const float* __restrict__ qnout, const int32_t* __restrict__ qsexp, int nq, float qmul, float osc,
-    uint64_t* __restrict__ state, int32_t* __restrict__ nbr, float* __restrict__ dist, int k_out) {
-    __shared__ TopkSmem<P, NSTEP, WAVES, QB> sm;
-    topk_block<P, NSTEP, KSEL, WAVES, QB>(sm, blockIdx.x, ops, ninit, sexp, n, qops, qid, qnout, qsexp, nq, qmul,
-                                          osc, state, nbr, dist, k_out);
+template <int P, int NSTEP, int KSEL, int WAVES, int QB, int CBQ, int BCR>
+__global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_kernel(TopkArgs A) {
+    __shared__ TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR> sm;
+    topk_block<P, NSTEP, KSEL, WAVES, QB, CBQ, BCR>(sm, blockIdx.x, A);
 }
 
-// Many shards in one launch: a persistent grid pulls (shard, query block)
-// items from a counter in the order of the work list (largest shards first)
-// and runs each as above.  Shard s occupies operand / state rows
-// [row0[s], row0[s] + ceil(n[s]/NQ)*NQ) and output rows [out0[s], out0[s] + n[s]);
-// candidate ids are shard-local.  Every workgroup leaves once the counter
-// passes the last item.
-template <int P, int NSTEP, int KSEL, int WAVES, int QB>
-__global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_persistent_kernel(
-    const uint8_t* __restrict__ ops, const float* __restrict__ ninit, const float* __restrict__ nout,
-    const int32_t* __restrict__ sexp, const int64_t* __restrict__ row0, const int32_t* __restrict__ nrows,
-    const int64_t* __restrict__ out0, const int32_t* __restrict__ items, int nitems,
-    unsigned int* __restrict__ counter, float qmul, float osc, uint64_t* __restrict__ state,
-    int32_t* __restrict__ nbr, float* __restrict__ dist, int k_out) {
-    __shared__ TopkSmem<P, NSTEP, WAVES, QB> sm;
-    __shared__ int s_item;
-    using S = Shape<P, NSTEP>;
-    constexpr int RB = S::ROW_BYTES;
-    while (true) {
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int it = s_item;
-        __syncthreads();
-        if (it >= nitems) break;
-        const int sh = items[2 * it], qb = items[2 * it + 1];
-        const int64_t r0 = row0[sh];
-        const int ns = nrows[sh];
-        const uint8_t* o = ops + r0 * RB;
-        topk_block<P, NSTEP, KSEL, WAVES, QB>(sm, qb, o, ninit + r0, sexp ? sexp + r0 : nullptr, ns, o, nullptr,
-                                              nout + r0, sexp ? sexp + r0 : nullptr, ns, qmul, osc,
-                                              state + r0 * KSEL, nbr + out0[sh] * k_out,
-                                              dist ? dist + out0[sh] * k_out : nullptr, k_out);
-    }
-}
 
 // Fused distance tile + top-k for FP32 rows too wide for register-resident
 // queries: a 128 x 128 (queries x candidates) workgroup tile accumulated over
@@ -734,11 +812,15 @@ constexpr int KS_DC = 32;
 constexpr int KS_RS = KS_DC + 4;    // LDS row stride (floats)
 
 template <int KSEL>
-__global__ __launch_bounds__(KS_WAVES * 64, 1) void dist_topk_kstream_kernel(
-    const float* __restrict__ ops, int DP, const float* __restrict__ ninit, int n,
-    const float* __restrict__ qops, const int64_t* __restrict__ qid, const float* __restrict__ qnout,
-    int nq, float qmul, float osc, uint64_t* __restrict__ state, int32_t* __restrict__ nbr,
-    float* __restrict__ dist, int k_out) {
+__global__ __launch_bounds__(KS_WAVES * 64, 1) void dist_topk_kstream_kernel(TopkArgs A, int DP) {
+    const float* __restrict__ ops = reinterpret_cast<const float*>(A.ops);
+    const float* __restrict__ ninit = A.ninit;
+    const int n = A.n;
+    const float* __restrict__ qops = reinterpret_cast<const float*>(A.qops);
+    const int64_t* __restrict__ qid = A.qid;
+    const int nq = A.nq;
+    const float qmul = A.qmul;
+    uint64_t* __restrict__ state = A.state;
     constexpr int NT = KS_WAVES * 64;
     constexpr int CPR = KS_DC / 4;                       // 16-byte chunks per row per k-chunk
     constexpr int CPT = (KS_NQ + KS_BC) * CPR / NT;      // per thread per k-chunk
@@ -746,7 +828,6 @@ __global__ __launch_bounds__(KS_WAVES * 64, 1) void dist_topk_kstream_kernel(
     __shared__ __align__(16) float s_c[2][KS_BC * KS_RS];
     __shared__ __align__(16) float s_norm[KS_BC];
     __shared__ uint64_t s_buf[KS_NQ * CB];
-    __shared__ int s_cnt[KS_NQ];
 
     const int tid = threadIdx.x;
     const int l = tid & 63;
@@ -755,25 +836,26 @@ __global__ __launch_bounds__(KS_WAVES * 64, 1) void dist_topk_kstream_kernel(
     const int ql = l & 31;
     const int64_t qb0 = (int64_t)blockIdx.x * KS_NQ;
     const int64_t qblk0 = qb0 + w * 32;
-    for (int t = tid; t < KS_NQ; t += NT) s_cnt[t] = 0;
 
     Selector<KSEL, 1> sel;
     sel.state = state + qblk0 * KSEL;
     sel.buf = s_buf + w * 32 * CB;
-    sel.cnt = s_cnt + w * 32;
     {
         const int64_t qg = qblk0 + ql;
         sel.thr[0] = __builtin_inff();
+        sel.fill[0] = 0;
         sel.qself[0] = qg < nq ? (qid ? qid[qg] : qg) : -1;
     }
+    sel.init_self_range();
 
     const int nch = DP / KS_DC;
     const int ntiles = (n + KS_BC - 1) / KS_BC;
     const int64_t total = (int64_t)ntiles * nch;
+    const int t0 = (int)(qb0 / KS_BC % ntiles);   // start at the block's own rows (see topk_block)
     intx4 pre[CPT];
     float pre_norm = 0.f;
     auto prefetch = [&](int64_t g) {
-        const int t = (int)(g / nch), kc = (int)(g % nch);
+        const int t = (int)((t0 + g / nch) % ntiles), kc = (int)(g % nch);
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
             const int c = tid + u * NT;
@@ -803,7 +885,7 @@ __global__ __launch_bounds__(KS_WAVES * 64, 1) void dist_topk_kstream_kernel(
     floatx16 acc[4];
     for (int64_t g = 0; g < total; ++g) {
         const int buf = (int)(g & 1);
-        const int t = (int)(g / nch), kc = (int)(g % nch);
+        const int t = (int)((t0 + g / nch) % ntiles), kc = (int)(g % nch);
         if (kc == 0) {
 #pragma unroll
             for (int sub = 0; sub < 4; ++sub)
@@ -833,7 +915,8 @@ __global__ __launch_bounds__(KS_WAVES * 64, 1) void dist_topk_kstream_kernel(
 #pragma unroll
             for (int sub = 0; sub < 4; ++sub) {
                 floatx16 one[1] = {acc[sub]};
-                sel.admit(one, (int64_t)t * KS_BC + sub * 32);
+                const int64_t cb = (int64_t)t * KS_BC + sub * 32;
+                sel.admit(one, cb, A.cpid ? A.cpid + cb : nullptr);
             }
         }
         if (g + 1 < total) {
@@ -843,7 +926,7 @@ __global__ __launch_bounds__(KS_WAVES * 64, 1) void dist_topk_kstream_kernel(
         __syncthreads();
     }
     sel.drain();
-    if (nbr) write_lists(state, KSEL, qblk0, 32, nq, qnout, osc, nbr, dist, k_out);
+    if (A.nbr) write_lists(A, KSEL, qblk0, 32);
 }
 
 // ---------------------------------------------------------------------------
@@ -876,12 +959,8 @@ __device__ inline void wave_sort_multi(uint64_t (&v)[PER]) {
             } else {
 #pragma unroll
                 for (int p = 0; p < PER; ++p) {
-                    int e = p * 64 + l;
-                    uint64_t o = shfl_xor_u64(v[p], j);
-                    bool up = (e & k) == 0;
-                    bool lower = (l & j) == 0;
-                    uint64_t mn = v[p] < o ? v[p] : o, mx = v[p] < o ? o : v[p];
-                    v[p] = (lower == up) ? mn : mx;
+                    const int e = p * 64 + l;
+                    v[p] = cmpx(v[p], j, ((e & k) == 0) == ((l & j) == 0));
                 }
             }
         }
@@ -898,7 +977,8 @@ __global__ __launch_bounds__(256) void rerank_kernel(const void* __restrict__ X,
                                                      int64_t n_src, const CT* __restrict__ cand,
                                                      int kstate,
                                                      int c, int k, int32_t* __restrict__ nbr,
-                                                     float* __restrict__ dist) {
+                                                     float* __restrict__ dist,
+                                                     const int64_t* __restrict__ orow) {
     extern __shared__ float s_q[];   // 4 waves x d
     const int l = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
@@ -945,20 +1025,21 @@ __global__ __launch_bounds__(256) void rerank_kernel(const void* __restrict__ X,
         prev[p] = l > 0 ? a : (p > 0 ? b : ~v[0]);
     }
     int kept = 0;
+    const int64_t o = orow ? orow[i] : i;
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
         const bool keep = v[p] != EMPTY_KEY && v[p] != prev[p];
         const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
         const int pos = kept + __builtin_popcountll(m & ((1ull << l) - 1));
         if (keep && pos < k) {
-            nbr[i * k + pos] = key_id(v[p]);
-            if (dist) dist[i * k + pos] = key_dist(v[p]);
+            nbr[o * k + pos] = key_id(v[p]);
+            if (dist) dist[o * k + pos] = key_dist(v[p]);
         }
         kept += __builtin_popcountll(m);
     }
     for (int e = kept + l; e < k; e += 64) {
-        nbr[i * k + e] = SG_NONE;
-        if (dist) dist[i * k + e] = __builtin_inff();
+        nbr[o * k + e] = SG_NONE;
+        if (dist) dist[o * k + e] = __builtin_inff();
     }
 }
 
@@ -995,11 +1076,8 @@ inline Layout layout(int64_t n, int d, int k, int prec, int rerank) {
     return L;
 }
 
-typedef void (*topk_fn)(const uint8_t*, const float*, const int32_t*, int, const uint8_t*,
-                        const int64_t*, const float*, const int32_t*, int, float, float, uint64_t*,
-                        int32_t*, float*, int);
-typedef void (*kstream_fn)(const float*, int, const float*, int, const float*, const int64_t*,
-                           const float*, int, float, float, uint64_t*, int32_t*, float*, int);
+typedef void (*topk_fn)(TopkArgs);
+typedef void (*kstream_fn)(TopkArgs, int);
 
 // A distance kernel and its launch geometry.
 struct Kern {
@@ -1008,25 +1086,27 @@ struct Kern {
     int DP = 0;                   // padded operand row length it expects
     int nq_block = 0;             // queries per workgroup
     int threads = 0;
+    int tile_rows = 0;            // candidate rows per LDS tile (0: k-streamed)
 };
 
-template <int P, int NSTEP, int W>
+template <int P, int NSTEP, int W, int QB = 1, int CBQ = CB, int BCR = 0>
 topk_fn pick_ksel(int ksel) {
     switch (ksel) {
-        case 32: return dist_topk_kernel<P, NSTEP, 32, W, 1>;
-        case 64: return dist_topk_kernel<P, NSTEP, 64, W, 1>;
-        case 128: return dist_topk_kernel<P, NSTEP, 128, W, 1>;
-        default: return dist_topk_kernel<P, NSTEP, 256, W, 1>;
+        case 32: return dist_topk_kernel<P, NSTEP, 32, W, QB, CBQ, BCR>;
+        case 64: return dist_topk_kernel<P, NSTEP, 64, W, QB, CBQ, BCR>;
+        case 128: return dist_topk_kernel<P, NSTEP, 128, W, QB, CBQ, BCR>;
+        default: return dist_topk_kernel<P, NSTEP, 256, W, QB, CBQ, BCR>;
     }
 }
 
-template <int P, int NSTEP, int W>
+template <int P, int NSTEP, int W, int QB = 1, int CBQ = CB, int BCR = 0>
 Kern resident(int ksel) {
     Kern k;
-    k.fn = pick_ksel<P, NSTEP, W>(ksel);
+    k.fn = pick_ksel<P, NSTEP, W, QB, CBQ, BCR>(ksel);
     k.DP = 2 * NSTEP * Tr<P>::VEC;
-    k.nq_block = 32 * W;
+    k.nq_block = 32 * W * QB;
     k.threads = 64 * W;
+    k.tile_rows = Shape<P, NSTEP, BCR>::BC;
     return k;
 }
 
@@ -1089,6 +1169,75 @@ Kern pick_kernel(int prec, int d, int ksel) {
     }
 }
 
+// Alternatives to the default kernel of a row length: 4-wave workgroups with
+// 64-row tiles, of which two share a CU, so that one keeps the MFMA and VALU
+// units busy while the other waits at its tile barrier.  Same operand layout
+// as the default (same padded row length).
+std::vector<Kern> kernel_variants(int prec, int d, int ksel) {
+    std::vector<Kern> v;
+    const Kern def = pick_kernel(prec, d, ksel);
+    if (!def.fn && !def.ks) return v;
+    v.push_back(def);
+    const int need = nstep_for(prec, padded_d(prec, d));
+    switch (prec) {
+        case SG_PREC_FP32:
+            if (need <= 16) v.push_back(resident<SG_PREC_FP32, 16, 4, 1, CB, 64>(ksel));
+            else if (need <= 32) v.push_back(resident<SG_PREC_FP32, 32, 4, 1, CB, 64>(ksel));
+            break;
+        case SG_PREC_F16:
+            if (need <= 4) v.push_back(resident<SG_PREC_F16, 4, 4, 1, CB, 64>(ksel));
+            else if (need <= 6) v.push_back(resident<SG_PREC_F16, 6, 4, 1, CB, 64>(ksel));
+            else if (need <= 8) v.push_back(resident<SG_PREC_F16, 8, 4, 1, CB, 64>(ksel));
+            break;
+        case SG_PREC_BF16:
+            if (need <= 4) v.push_back(resident<SG_PREC_BF16, 4, 4, 1, CB, 64>(ksel));
+            else if (need <= 6) v.push_back(resident<SG_PREC_BF16, 6, 4, 1, CB, 64>(ksel));
+            else if (need <= 8) v.push_back(resident<SG_PREC_BF16, 8, 4, 1, CB, 64>(ksel));
+            break;
+        default:
+            if (need <= 1) v.push_back(resident<SG_PREC_FP8, 1, 4, 1, CB, 64>(ksel));
+            else if (need <= 2) v.push_back(resident<SG_PREC_FP8, 2, 4, 1, CB, 64>(ksel));
+            break;
+    }
+    return v;
+}
+
+// Process-wide record of the fastest variant per shape (filled by
+// sg_knn_autotune), and a per-thread override for tests.
+struct TuneKey {
+    int prec, DP, ksel, nlog;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(prec, DP, ksel, nlog) < std::tie(o.prec, o.DP, o.ksel, o.nlog);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+thread_local int g_force_variant = -1;
+
+inline int nlog_of(int64_t n) {
+    int b = 0;
+    while ((int64_t(1) << (b + 1)) <= n) ++b;
+    return b;
+}
+
+inline TuneKey tune_key(int prec, int d, int ksel, int64_t n) {
+    return TuneKey{prec, padded_d(prec, d), ksel, nlog_of(n)};
+}
+
+Kern choose_kernel(int prec, int d, int ksel, int64_t n) {
+    const std::vector<Kern> v = kernel_variants(prec, d, ksel);
+    if (v.empty()) return Kern();
+    int idx = 0;
+    if (g_force_variant >= 0) {
+        idx = g_force_variant < (int)v.size() ? g_force_variant : 0;
+    } else {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune.find(tune_key(prec, d, ksel, n));
+        if (it != g_tune.end() && it->second < (int)v.size()) idx = it->second;
+    }
+    return v[idx];
+}
+
 inline Layout layout_k(int64_t n, int d, int k, int prec, int rerank) {
     Layout L = layout(n, d, k, prec, rerank);
     Kern kk = pick_kernel(prec, d, L.ksel);
@@ -1118,6 +1267,8 @@ void check_args(const void* X, int dtype, int64_t n, int d, int64_t ld, int metr
     SG_REQUIRE(n == 0 || X != nullptr, "X is NULL");
 }
 
+inline size_t total_bytes(const Layout& L, int64_t n, int64_t nq, int prec);
+
 }  // namespace knn
 }  // namespace sg
 
@@ -1128,8 +1279,8 @@ extern "C" sg_status sg_knn_graph_workspace_size(int64_t n, int32_t d, int32_t k
     return guarded([&] {
         SG_REQUIRE(bytes != nullptr, "bytes is NULL");
         SG_REQUIRE(n >= 0 && d >= 1 && d <= 1024 && k >= 1 && k <= 256, "bad sizes");
-        knn::Layout L = knn::layout_k(n, d, k, prec, rerank);
-        *bytes = n == 0 ? 0 : L.total;
+        knn::Layout L = knn::layout_k(n, d, k, prec, rerank == k ? 0 : rerank);
+        *bytes = n == 0 ? 0 : knn::total_bytes(L, n, -1, prec);
     });
 }
 
@@ -1138,9 +1289,25 @@ namespace knn {
 
 inline int64_t pad_rows(int64_t m) { return (m + PAD_ROWS - 1) / PAD_ROWS * PAD_ROWS; }
 
+// Locality order of a whole-shard build: rows are grouped by their nearest
+// of P evenly spaced pivot rows (about 256 rows per pivot), so that a
+// workgroup's queries and the candidates it scans first are close together.
+constexpr int64_t LOCAL_MIN_ROWS = 4096;   // smaller shards keep their order
+inline int64_t n_pivots(int64_t n) { return std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 8192); }
+inline bool use_locality(int64_t n, bool subset) { return !subset && n >= LOCAL_MIN_ROWS; }
+
+// Extra workspace of the locality order.
+inline size_t locality_bytes(const Layout& L, int64_t n, int prec) {
+    const int64_t P = n_pivots(n), Pp = pad_rows(P);
+    return 2 * align_up((size_t)L.n_pad * 8, 256) + 2 * align_up((size_t)L.n_pad * 4, 256) +
+           3 * align_up((size_t)(P + 1) * 8, 256) + align_up(exclusive_scan_tmp_bytes(P), 256) +
+           align_up((size_t)Pp * L.DP * elem_bytes(prec), 256) + 3 * align_up((size_t)Pp * 4, 256) +
+           align_up((size_t)P * 8, 256);
+}
+
 // Workspace of one call: candidate operands + side arrays for all n rows,
 // and, for a row subset, the query operands + side arrays of its nq rows.
-inline size_t total_bytes(const Layout& L, int64_t nq, int prec) {
+inline size_t total_bytes(const Layout& L, int64_t n, int64_t nq, int prec) {
     size_t t = L.total;
     if (nq >= 0) {
         const int64_t nqp = pad_rows(nq);
@@ -1149,8 +1316,53 @@ inline size_t total_bytes(const Layout& L, int64_t nq, int prec) {
         // the state then covers the query rows only
         t -= align_up(L.state_bytes, 256);
         t += align_up((size_t)nqp * L.ksel * 8, 256);
+    } else if (use_locality(n, false)) {
+        t += locality_bytes(L, n, prec);
     }
     return t;
+}
+
+__global__ void pivot_rows_kernel(int64_t* __restrict__ piv, int64_t P, int64_t n) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < P) piv[p] = p * n / P;
+}
+
+__global__ void label_count_kernel(const int32_t* __restrict__ lab, int64_t n, int64_t P,
+                                   int64_t* __restrict__ cnt) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = lab[i];
+        atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[c >= 0 && c < P ? c : 0]), 1ull);
+    }
+}
+
+// Rows grouped by label; within a label the order follows the atomics (any
+// order gives the same lists: keys carry the original row ids).  Padding rows
+// n..n_pad get id -1.
+__global__ void label_scatter_kernel(const int32_t* __restrict__ lab, int64_t n, int64_t n_pad, int64_t P,
+                                     const int64_t* __restrict__ off, int64_t* __restrict__ cur,
+                                     int64_t* __restrict__ perm, int32_t* __restrict__ pid) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (i >= n) {
+            perm[i] = -1;
+            pid[i] = -1;
+            continue;
+        }
+        const int32_t c0 = lab[i];
+        const int32_t c = c0 >= 0 && c0 < P ? c0 : 0;
+        const int64_t pos = off[c] + (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&cur[c]), 1ull);
+        perm[pos] = i;
+        pid[pos] = (int32_t)i;
+    }
+}
+
+inline void launch_topk(const Kern& kern, const TopkArgs& A, int64_t nq_pad, int DP, hipStream_t s) {
+    const unsigned grid = (unsigned)(nq_pad / kern.nq_block);
+    if (kern.fn)
+        kern.fn<<<grid, kern.threads, 0, s>>>(A);
+    else
+        kern.ks<<<grid, kern.threads, 0, s>>>(A, DP);
+    SG_LAUNCH_CHECK();
 }
 
 // kNN of rows (nq >= 0: the listed rows; nq < 0: every row) against all n rows.
@@ -1159,17 +1371,18 @@ void run(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int
          size_t ws_bytes, hipStream_t s) {
     if (rerank == k) rerank = 0;
     Layout L = layout_k(n, d, k, prec, rerank);
-    const Kern kern = pick_kernel(prec, d, L.ksel);
+    const Kern kern = choose_kernel(prec, d, L.ksel, n);
     if (!kern.fn && !kern.ks) {
         set_error("sg_knn: no distance kernel for this precision at d = " + std::to_string(d));
         throw Fail{SG_ERR_UNSUPPORTED};
     }
-    const size_t need = total_bytes(L, rows ? nq : -1, prec);
+    const bool subset = rows != nullptr;
+    const size_t need = total_bytes(L, n, subset ? nq : -1, prec);
     if (ws_bytes < need || ws == nullptr) {
         set_error("sg_knn: workspace too small (need " + std::to_string(need) + " bytes)");
         throw Fail{SG_ERR_WORKSPACE};
     }
-    const bool subset = rows != nullptr;
+    const bool local = use_locality(n, subset);
     const int64_t nq_rows = subset ? nq : n;
     const int64_t nq_pad = subset ? pad_rows(nq) : L.n_pad;
     Carver cv(ws);
@@ -1193,45 +1406,87 @@ void run(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int
         qid = qid_w;
     }
     uint64_t* state = cv.take<uint64_t>((size_t)nq_pad * L.ksel);
+    const bool plain_ip = metric == SG_IP && !norm_corrected_ip(metric, prec);
+    const float qmul = plain_ip ? -1.0f : -2.0f;
+    const float osc = norm_corrected_ip(metric, prec) ? 0.5f : 1.0f;
+    const unsigned prep_grid = (unsigned)cdiv(L.n_pad, 4);
 
-    prep_kernel<<<(unsigned)cdiv(L.n_pad, 4), 256, 0, s>>>(X, dtype, n, d, ld, nullptr, n, L.n_pad, L.DP,
-                                                            prec, metric, ops, ninit, nout, sexp);
+    int64_t* perm = nullptr;
+    int32_t* pid = nullptr;
+    if (local) {
+        const int64_t P = n_pivots(n), Pp = pad_rows(P);
+        perm = cv.take<int64_t>(L.n_pad);
+        int64_t* noself = cv.take<int64_t>(L.n_pad);
+        pid = cv.take<int32_t>(L.n_pad);
+        int32_t* lab = cv.take<int32_t>(L.n_pad);
+        int64_t* cnt = cv.take<int64_t>(P + 1);
+        int64_t* off = cv.take<int64_t>(P + 1);
+        int64_t* cur = cv.take<int64_t>(P + 1);
+        void* scan_tmp = cv.take<char>(exclusive_scan_tmp_bytes(P));
+        uint8_t* pops = cv.take<uint8_t>((size_t)Pp * L.DP * elem_bytes(prec));
+        float* pinit = cv.take<float>(Pp);
+        float* pnout = cv.take<float>(Pp);
+        int32_t* psexp = cv.take<int32_t>(Pp);
+        int64_t* piv = cv.take<int64_t>(P);
+        // nearest pivot of every row (queries: all rows in their own order)
+        pivot_rows_kernel<<<(unsigned)cdiv(P, 256), 256, 0, s>>>(piv, P, n);
+        SG_LAUNCH_CHECK();
+        prep_kernel<<<(unsigned)cdiv(Pp, 4), 256, 0, s>>>(X, dtype, P, d, ld, piv, n, Pp, L.DP, prec, metric,
+                                                          pops, pinit, pnout, prec == SG_PREC_FP8 ? psexp : nullptr);
+        SG_LAUNCH_CHECK();
+        prep_kernel<<<prep_grid, 256, 0, s>>>(X, dtype, n, d, ld, nullptr, n, L.n_pad, L.DP, prec, metric, ops,
+                                              ninit, nout, sexp);
+        SG_LAUNCH_CHECK();
+        fill<int64_t>(noself, -1, L.n_pad, s);
+        fill<uint64_t>(state, EMPTY_KEY, L.n_pad * 32, s);
+        const Kern ka = pick_kernel(prec, d, 32);
+        TopkArgs B{};
+        B.ops = pops; B.ninit = pinit; B.sexp = prec == SG_PREC_FP8 ? psexp : nullptr; B.n = (int)P;
+        B.qops = ops; B.qid = noself; B.qnout = nout; B.qsexp = sexp; B.nq = (int)n;
+        B.qmul = qmul; B.osc = osc; B.state = state; B.nbr = lab; B.k_out = 1;
+        launch_topk(ka, B, L.n_pad, L.DP, s);
+        // group the rows by pivot
+        fill<int64_t>(cnt, 0, P + 1, s);
+        fill<int64_t>(cur, 0, P + 1, s);
+        const unsigned eg = (unsigned)std::min<int64_t>(cdiv(L.n_pad, 256), 4096);
+        label_count_kernel<<<eg, 256, 0, s>>>(lab, n, P, cnt);
+        SG_LAUNCH_CHECK();
+        exclusive_scan_i64(cnt, off, P, scan_tmp, s);
+        label_scatter_kernel<<<eg, 256, 0, s>>>(lab, n, L.n_pad, P, off, cur, perm, pid);
+        SG_LAUNCH_CHECK();
+    }
+
+    prep_kernel<<<prep_grid, 256, 0, s>>>(X, dtype, n, d, ld, perm, n, L.n_pad, L.DP, prec, metric, ops, ninit,
+                                          nout, sexp);
     SG_LAUNCH_CHECK();
     if (subset) {
-        prep_kernel<<<(unsigned)cdiv(nq_pad, 4), 256, 0, s>>>(X, dtype, nq, d, ld, rows, n, nq_pad, L.DP,
-                                                               prec, metric, qops, qninit, qnout, qsexp);
+        prep_kernel<<<(unsigned)cdiv(nq_pad, 4), 256, 0, s>>>(X, dtype, nq, d, ld, rows, n, nq_pad, L.DP, prec,
+                                                               metric, qops, qninit, qnout, qsexp);
         SG_LAUNCH_CHECK();
     }
     fill<uint64_t>(state, EMPTY_KEY, nq_pad * L.ksel, s);
     const bool final_here = rerank == 0;
-    const bool plain_ip = metric == SG_IP && !norm_corrected_ip(metric, prec);
-    const float qmul = plain_ip ? -1.0f : -2.0f;
-    const float osc = norm_corrected_ip(metric, prec) ? 0.5f : 1.0f;
+    TopkArgs A{};
+    A.ops = ops; A.ninit = ninit; A.sexp = sexp; A.cpid = pid; A.n = (int)n;
+    A.qops = qops; A.qid = qid; A.qnout = qnout; A.qsexp = qsexp; A.qout = perm; A.nq = (int)nq_rows;
+    A.qmul = qmul; A.osc = osc; A.state = state;
+    A.nbr = final_here ? nbr : nullptr; A.dist = final_here ? dist : nullptr; A.k_out = k;
     profile_record(s, true);
-    const unsigned grid = (unsigned)(nq_pad / kern.nq_block);
-    if (kern.fn)
-        kern.fn<<<grid, kern.threads, 0, s>>>(ops, ninit, sexp, (int)n, qops, qid, qnout, qsexp,
-                                              (int)nq_rows, qmul, osc, state, final_here ? nbr : nullptr,
-                                              final_here ? dist : nullptr, k);
-    else
-        kern.ks<<<grid, kern.threads, 0, s>>>(reinterpret_cast<const float*>(ops), L.DP, ninit, (int)n,
-                                              reinterpret_cast<const float*>(qops), qid, qnout,
-                                              (int)nq_rows, qmul, osc, state, final_here ? nbr : nullptr,
-                                              final_here ? dist : nullptr, k);
-    SG_LAUNCH_CHECK();
+    launch_topk(kern, A, nq_pad, L.DP, s);
     profile_record(s, false);
-    if (!final_here) {
+    if (!final_here && nbr) {   // (no lists wanted when only timing the distance kernel)
         const size_t shm = (size_t)4 * d * sizeof(float);
         const unsigned grid = (unsigned)cdiv(nq_rows, 4);
+        const int64_t* qrows = subset ? rows : perm;
         if (rerank <= 64)
-            rerank_kernel<1><<<grid, 256, shm, s>>>(X, dtype, nq_rows, d, ld, metric, rows, n, state, L.ksel,
-                                                    rerank, k, nbr, dist);
+            rerank_kernel<1><<<grid, 256, shm, s>>>(X, dtype, nq_rows, d, ld, metric, qrows, n, state, L.ksel,
+                                                    rerank, k, nbr, dist, perm);
         else if (rerank <= 128)
-            rerank_kernel<2><<<grid, 256, shm, s>>>(X, dtype, nq_rows, d, ld, metric, rows, n, state, L.ksel,
-                                                    rerank, k, nbr, dist);
+            rerank_kernel<2><<<grid, 256, shm, s>>>(X, dtype, nq_rows, d, ld, metric, qrows, n, state, L.ksel,
+                                                    rerank, k, nbr, dist, perm);
         else
-            rerank_kernel<4><<<grid, 256, shm, s>>>(X, dtype, nq_rows, d, ld, metric, rows, n, state, L.ksel,
-                                                    rerank, k, nbr, dist);
+            rerank_kernel<4><<<grid, 256, shm, s>>>(X, dtype, nq_rows, d, ld, metric, qrows, n, state, L.ksel,
+                                                    rerank, k, nbr, dist, perm);
         SG_LAUNCH_CHECK();
     }
 }
@@ -1258,7 +1513,7 @@ extern "C" sg_status sg_knn_rows_workspace_size(int64_t n, int32_t d, int64_t nq
         SG_REQUIRE(n >= 0 && nq >= 0 && d >= 1 && d <= 1024 && k >= 1 && k <= 256, "bad sizes");
         if (rerank == k) rerank = 0;
         knn::Layout L = knn::layout_k(n, d, k, prec, rerank);
-        *bytes = (n == 0 || nq == 0) ? 0 : knn::total_bytes(L, nq, prec);
+        *bytes = (n == 0 || nq == 0) ? 0 : knn::total_bytes(L, n, nq, prec);
     });
 }
 
@@ -1292,13 +1547,78 @@ extern "C" sg_status sg_rerank(const void* X, sg_dtype dtype, int64_t n, int32_t
         const unsigned grid = (unsigned)cdiv(n, 4);
         if (c <= 64)
             knn::rerank_kernel<1, int32_t><<<grid, 256, shm, s>>>(X, dtype, n, d, ld, metric, nullptr, n, cand, c, c,
-                                                                  k, nbr, dist);
+                                                                  k, nbr, dist, nullptr);
         else if (c <= 128)
             knn::rerank_kernel<2, int32_t><<<grid, 256, shm, s>>>(X, dtype, n, d, ld, metric, nullptr, n, cand, c, c,
-                                                                  k, nbr, dist);
+                                                                  k, nbr, dist, nullptr);
         else
             knn::rerank_kernel<4, int32_t><<<grid, 256, shm, s>>>(X, dtype, n, d, ld, metric, nullptr, n, cand, c, c,
-                                                                  k, nbr, dist);
+                                                                  k, nbr, dist, nullptr);
         SG_LAUNCH_CHECK();
+    });
+}
+
+extern "C" sg_status sg_knn_variant_count(sg_prec prec, int32_t d, int32_t k, int32_t* count) {
+    return guarded([&] {
+        SG_REQUIRE(count != nullptr, "count is NULL");
+        SG_REQUIRE(d >= 1 && d <= 1024 && k >= 1 && k <= 256, "bad sizes");
+        SG_REQUIRE(prec >= SG_PREC_FP32 && prec <= SG_PREC_FP8, "unknown precision");
+        *count = (int32_t)knn::kernel_variants(prec, d, knn::ksel_for(k)).size();
+    });
+}
+
+extern "C" sg_status sg_knn_force_variant(int32_t variant) {
+    return guarded([&] {
+        SG_REQUIRE(variant >= -1, "variant must be -1 (off) or a variant index");
+        knn::g_force_variant = variant;
+    });
+}
+
+extern "C" sg_status sg_knn_autotune(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t ld,
+                                     sg_metric metric, int32_t k, sg_prec prec, int32_t rerank, void* ws,
+                                     size_t ws_bytes, void* stream, int32_t* chosen, float* times_ms,
+                                     int32_t max_times) {
+    return guarded([&] {
+        knn::check_args(X, dtype, n, d, ld, metric, k, prec, rerank);
+        SG_REQUIRE(n > 0, "autotuning needs rows");
+        SG_REQUIRE(max_times >= 0 && (max_times == 0 || times_ms != nullptr), "bad times_ms / max_times");
+        hipStream_t s = as_stream(stream);
+        const int ksel = knn::layout_k(n, d, k, prec, rerank == k ? 0 : rerank).ksel;
+        const int nv = (int)knn::kernel_variants(prec, d, ksel).size();
+        SG_REQUIRE(nv > 0, "no distance kernel for this precision and d");
+        const int saved = knn::g_force_variant;
+        std::vector<float> ms(nv, 0.f);
+        hipEvent_t e0, e1;
+        SG_HIP(hipEventCreate(&e0));
+        SG_HIP(hipEventCreate(&e1));
+        struct Restore {
+            int v;
+            hipEvent_t a, b;
+            ~Restore() {
+                knn::g_force_variant = v;
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+            }
+        } restore{saved, e0, e1};
+        // nbr / dist scratch inside the caller's workspace is not available,
+        // so the timed runs keep only the state (no final lists)
+        for (int v = 0; v < nv; ++v) {
+            knn::g_force_variant = v;
+            knn::run(X, dtype, n, d, ld, metric, k, prec, rerank, nullptr, -1, nullptr, nullptr, ws, ws_bytes, s);
+            SG_HIP(hipEventRecord(e0, s));
+            knn::run(X, dtype, n, d, ld, metric, k, prec, rerank, nullptr, -1, nullptr, nullptr, ws, ws_bytes, s);
+            SG_HIP(hipEventRecord(e1, s));
+            SG_HIP(hipEventSynchronize(e1));
+            SG_HIP(hipEventElapsedTime(&ms[v], e0, e1));
+        }
+        int best = 0;
+        for (int v = 1; v < nv; ++v)
+            if (ms[v] < ms[best]) best = v;
+        {
+            std::lock_guard<std::mutex> g(knn::g_tune_mu);
+            knn::g_tune[knn::tune_key(prec, d, ksel, n)] = best;
+        }
+        if (chosen) *chosen = best;
+        for (int v = 0; v < nv && v < max_times; ++v) times_ms[v] = ms[v];
     });
 }

@@ -1,0 +1,152 @@
+"""Summaries of rocprofv3 output for the distance kernel.
+
+Two records are kept as short text files:
+
+* a kernel-trace summary (per-kernel dispatch count and average duration from
+  ``--kernel-trace --stats -f csv``), and
+* a traffic record: HBM bytes per distance-kernel dispatch from two
+  ``--pmc`` runs (``FETCH_SIZE``, then ``WRITE_SIZE``, KiB per dispatch), each
+  scaled by what the same counter reads for a device copy of known size that
+  the profiled program performs first (``bench.py --calib-copy``: 256 MiB read
+  and 256 MiB written).  The record carries a hash of the distance kernel's
+  sources; a reader treats it as stale once the sources change.
+
+Usage::
+
+    python -m paper_2605_10135_amd.profiling stats  <kernel_stats.csv> <out.md> "<command>"
+    python -m paper_2605_10135_amd.profiling traffic <fetch.csv> <write.csv> <out.txt> "<fetch cmd>" "<write cmd>"
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("csrc/knn.hip", "csrc/common.hpp")
+CALIB_BYTES = 256 << 20          # bytes read and bytes written by the calibration copy
+DIST_KERNEL = "dist_topk"
+
+
+def kernel_sha() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _short(name: str) -> str:
+    name = name.strip('"')
+    return name.split("(")[0].replace("void ", "")[:110]
+
+
+def counter_avgs(path: str, counter: str) -> dict:
+    """kernel name -> (dispatches, mean counter value per dispatch)."""
+    acc = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            k = _short(r["Kernel_Name"])
+            n, s = acc.get(k, (0, 0.0))
+            acc[k] = (n + 1, s + float(r["Counter_Value"]))
+    return {k: (n, s / n) for k, (n, s) in acc.items()}
+
+
+def _find(avgs: dict, key: str):
+    hits = [(k, v) for k, v in avgs.items() if key in k]
+    if not hits:
+        raise SystemExit("no dispatch of a kernel matching %r" % key)
+    return max(hits, key=lambda kv: kv[1][0])
+
+
+def _calib(avgs: dict):
+    for key in ("copyBuffer", "CopyFunctor", "copy_kernel"):
+        hits = [(k, v) for k, v in avgs.items() if key in k]
+        if hits:
+            return hits[0]
+    raise SystemExit("no calibration copy dispatch found (run the program with --calib-copy)")
+
+
+def traffic(fetch_csv: str, write_csv: str, out: str, fetch_cmd: str, write_cmd: str) -> None:
+    f, w = counter_avgs(fetch_csv, "FETCH_SIZE"), counter_avgs(write_csv, "WRITE_SIZE")
+    (ck, (_, cf)), (_, (_, cw)) = _calib(f), _calib(w)
+    ffac = CALIB_BYTES / (cf * 1024.0)
+    wfac = CALIB_BYTES / (cw * 1024.0)
+    dk, (dn, dfetch) = _find(f, DIST_KERNEL)
+    _, (_, dwrite) = _find(w, DIST_KERNEL)
+    fetch_b = dfetch * 1024.0 * ffac
+    write_b = dwrite * 1024.0 * wfac
+    lines = [
+        "# HBM traffic of the distance kernel (rocprofv3 --pmc, per dispatch)",
+        "kernel: %s" % dk,
+        "dispatches: %d" % dn,
+        "calibration_kernel: %s (%d bytes read, %d written)" % (ck, CALIB_BYTES, CALIB_BYTES),
+        "fetch_kib_raw: %.1f" % dfetch,
+        "write_kib_raw: %.1f" % dwrite,
+        "calib_fetch_kib_raw: %.1f" % cf,
+        "calib_write_kib_raw: %.1f" % cw,
+        "fetch_factor: %.4f" % ffac,
+        "write_factor: %.4f" % wfac,
+        "fetch_bytes_per_launch: %.0f" % fetch_b,
+        "write_bytes_per_launch: %.0f" % write_b,
+        "traffic_bytes_per_launch: %.0f" % (fetch_b + write_b),
+        "kernel_sources_sha256: %s" % kernel_sha(),
+        "fetch_command: %s" % fetch_cmd,
+        "write_command: %s" % write_cmd,
+    ]
+    with open(out, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def read_traffic(path: str):
+    """Bytes per distance-kernel launch from a traffic record, or None when the
+    record is missing or was taken on other kernel sources."""
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    if rec.get("kernel_sources_sha256") != kernel_sha():
+        return None
+    try:
+        return {"bytes": float(rec["traffic_bytes_per_launch"]),
+                "fetch_bytes": float(rec["fetch_bytes_per_launch"]),
+                "write_bytes": float(rec["write_bytes_per_launch"]),
+                "fetch_factor": float(rec["fetch_factor"]), "write_factor": float(rec["write_factor"])}
+    except (KeyError, ValueError):
+        return None
+
+
+def stats(stats_csv: str, out: str, command: str) -> None:
+    rows = []
+    with open(stats_csv) as f:
+        for r in csv.DictReader(f):
+            rows.append((_short(r["Name"]), int(r["Calls"]), float(r["AverageNs"]) / 1e6,
+                         float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
+    rows.sort(key=lambda x: -x[3])
+    lines = ["# Kernel trace summary (rocprofv3 --kernel-trace --stats)", "",
+             "Command: `%s`" % command, "",
+             "Distance-kernel sources sha256: `%s`" % kernel_sha(), "",
+             "| kernel | calls | avg ms | total ms | % |", "|---|---:|---:|---:|---:|"]
+    for name, calls, avg, tot, pct in rows[:25]:
+        lines.append("| `%s` | %d | %.4f | %.3f | %.2f |" % (name, calls, avg, tot, pct))
+    with open(out, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    if len(sys.argv) >= 5 and sys.argv[1] == "stats":
+        stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif len(sys.argv) >= 7 and sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6])
+    else:
+        print(__doc__)
+        sys.exit(2)

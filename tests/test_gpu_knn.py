@@ -167,3 +167,101 @@ def test_knn_fp8_wide_rerank_recall():
     nbr, _ = sg.sg_knn_graph(torch.from_numpy(X).to(DEV), 32, "l2", "fp8", rerank=128)
     onbr, _ = oracle.knn(oracle.widen(X), 32)
     assert recall(nbr.cpu().numpy(), onbr) >= 0.95
+
+
+@pytest.mark.parametrize("prec", ["fp32", "f16"])
+@pytest.mark.parametrize("n,d,K", [(2100, 128, 64), (1300, 64, 32), (900, 96, 128), (700, 128, 256)])
+def test_knn_every_variant_bit_exact(prec, n, d, K):
+    """Each launch-shape variant of the distance kernel gives the oracle's lists."""
+    X = _u8(n, d, seed=n + d + K)
+    Xg = torch.from_numpy(X).to(DEV)
+    onbr, odist = oracle.knn(oracle.widen(X), K)
+    nv = sg.sg_knn_variant_count(d, K, prec)
+    assert nv >= 1
+    try:
+        for v in range(nv):
+            sg.sg_knn_force_variant(v)
+            nbr, dist = sg.sg_knn_graph(Xg, K, "l2", prec)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(nbr.cpu().numpy(), onbr, err_msg="variant %d" % v)
+            np.testing.assert_array_equal(dist.cpu().numpy(), odist.astype(np.float32))
+    finally:
+        sg.sg_knn_force_variant(-1)
+
+
+@pytest.mark.parametrize("prec,d", [("bf16", 96), ("fp8", 64), ("bf16", 128)])
+def test_knn_reduced_variants_agree(prec, d):
+    X = synthdata.unit_rows(synthdata.mixture(3000, d, 30, 0.3, seed=d))
+    Xg = torch.from_numpy(X).to(DEV)
+    nv = sg.sg_knn_variant_count(d, 64, prec)
+    outs = []
+    try:
+        for v in range(nv):
+            sg.sg_knn_force_variant(v)
+            nbr, dist = sg.sg_knn_graph(Xg, 64, "ip", prec, rerank=128)
+            torch.cuda.synchronize()
+            outs.append((nbr.cpu().numpy(), dist.cpu().numpy()))
+    finally:
+        sg.sg_knn_force_variant(-1)
+    for v in range(1, nv):
+        np.testing.assert_array_equal(outs[v][0], outs[0][0])
+        np.testing.assert_array_equal(outs[v][1], outs[0][1])
+
+
+def test_knn_many_merges_sampled_exact():
+    """A shard large enough that every query merges its buffer many times
+    (and subtiles overflow mid-way): sampled rows equal the oracle."""
+    X = synthdata.sift_like_u8(n=20000, d=128, seed=5, n_comp=40)
+    Xg = torch.from_numpy(X).to(DEV)
+    rows = np.random.default_rng(2).choice(20000, size=96, replace=False)
+    onbr, odist = oracle.knn(oracle.widen(X), 64, rows=rows)
+    nv = sg.sg_knn_variant_count(128, 64, "f16")
+    try:
+        for v in range(nv):
+            sg.sg_knn_force_variant(v)
+            for prec in ("f16", "fp32"):
+                nbr, dist = sg.sg_knn_graph(Xg, 64, "l2", prec)
+                torch.cuda.synchronize()
+                np.testing.assert_array_equal(nbr.cpu().numpy()[rows], onbr, err_msg="%s v%d" % (prec, v))
+                np.testing.assert_array_equal(dist.cpu().numpy()[rows], odist.astype(np.float32))
+    finally:
+        sg.sg_knn_force_variant(-1)
+
+
+def test_knn_autotune_records_a_valid_choice():
+    X = _u8(5000, 128, seed=77)
+    Xg = torch.from_numpy(X).to(DEV)
+    ref, _ = sg.sg_knn_graph(Xg, 64, "l2", "f16")
+    chosen, times = sg.sg_knn_autotune(Xg, 64, "l2", "f16")
+    assert 0 <= chosen < len(times) == sg.sg_knn_variant_count(128, 64, "f16")
+    assert all(t > 0 for t in times) and times[chosen] == min(times)
+    nbr, _ = sg.sg_knn_graph(Xg, 64, "l2", "f16")
+    torch.cuda.synchronize()
+    assert torch.equal(nbr, ref)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "f16"])
+@pytest.mark.parametrize("n,d,K,levels", [(5000, 32, 64, 256), (4500, 6, 40, 4), (6100, 128, 32, 256)])
+def test_knn_locality_order_bit_exact(prec, n, d, K, levels):
+    """Shards of >= 4096 rows are scanned in pivot order; every row's list
+    (ties included) still equals the oracle's."""
+    X = _u8(n, d, seed=n + levels, levels=levels)
+    nbr, dist = sg.sg_knn_graph(torch.from_numpy(X).to(DEV), K, "l2", prec)
+    torch.cuda.synchronize()
+    onbr, odist = oracle.knn(oracle.widen(X), K)
+    np.testing.assert_array_equal(nbr.cpu().numpy(), onbr)
+    np.testing.assert_array_equal(dist.cpu().numpy(), odist.astype(np.float32))
+
+
+def test_knn_locality_order_f32_and_rerank():
+    X = synthdata.unit_rows(synthdata.mixture(5200, 48, 40, 0.3, seed=9))
+    Xg = torch.from_numpy(X).to(DEV)
+    X64 = oracle.widen(X)
+    onbr, odist = oracle.knn(X64, 32, oracle.IP)
+    nbr, dist = sg.sg_knn_graph(Xg, 32, "ip", "fp32")
+    torch.cuda.synchronize()
+    bad = check_rows(X64, np.arange(len(X)), nbr.cpu().numpy(), dist.cpu().numpy(), onbr, odist, oracle.IP)
+    assert not bad, bad[:5]
+    nb2, d2 = sg.sg_knn_graph(Xg, 32, "ip", "bf16", rerank=64)
+    torch.cuda.synchronize()
+    assert recall(nb2.cpu().numpy(), onbr) >= 0.99
