@@ -133,6 +133,10 @@ def main():
     flops = float(sum(2.0 * d * float(n) * float(n) for n in sizes))
 
     forms = [args.chosen] + ([] if args.no_plain or args.chosen == "fp32" else ["fp32"])
+    # launch-shape autotuning on the largest shard (outside the timed region)
+    big = int(np.argmax(sizes))
+    tuned = {f: sg.sg_knn_autotune(shards[big], K, "l2", f) for f in forms}
+    log("autotune %s" % tuned)
     res = {}
     graph_of = {}
     for form in forms:
@@ -256,6 +260,7 @@ def main():
                    "search_recall_at_10_L64": recall10},
         "shard_rows_per_s": ch["shard_rows_ps"],
         "stages_ms": stages,
+        "autotune": {f: {"chosen": c, "variant_ms": t} for f, (c, t) in tuned.items()},
         "partition_s": t_part,
         "search_s_10k_queries_L64": t_search,
     }

@@ -663,16 +663,33 @@ struct TopkSmem {
     uint64_t buf[NQ * CBQ];
 };
 
+// Candidate tile order of a query block: first the tiles of the 256-row
+// group that holds the block's own rows (with rows in locality order these
+// hold the queries' closest neighbours, so the thresholds tighten at once),
+// then all other tiles in ascending order -- the same order for every block,
+// so that concurrently running workgroups stream the same rows through L2.
+struct ScanOrder {
+    int t0, R;
+    __device__ ScanOrder(int64_t first_row, int bc, int ntiles) {
+        R = (256 + bc - 1) / bc;
+        if (R > ntiles) R = ntiles;
+        const int own = (int)(first_row / 256 * 256 / bc);
+        t0 = own < ntiles - R ? own : ntiles - R;
+    }
+    __device__ int tile(int t) const {
+        if (t < R) return t0 + t;
+        const int g = t - R;
+        return g < t0 ? g : g + R;
+    }
+};
+
 // One block of NQ = 32*QB*WAVES queries (query rows qb*NQ.. of A.qops)
 // against all A.n candidate rows: the fused distance tile + top-k with
 // register-resident queries.  Candidate tiles (BC rows) are staged in LDS,
 // double buffered, the next tile already in flight in registers while the
 // current one is computed.  Within a tile the MFMAs of subtile s+1 are
 // issued before the selection epilogue of subtile s so that both run at once.
-// The scan starts at the tile holding the block's own rows and wraps around:
-// when operand rows are ordered by locality, the queries meet their close
-// neighbours first, the thresholds tighten early and later tiles rarely
-// admit anything.
+// Tiles are visited in ScanOrder.
 template <int P, int NSTEP, int KSEL, int WAVES, int QB, int CBQ, int BCR>
 __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t qb, const TopkArgs& A) {
     using S = Shape<P, NSTEP, BCR>;
@@ -708,8 +725,8 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
     sel.init_self_range();
 
     const int ntiles = (A.n + BC - 1) / BC;
-    const int t0 = (int)((qb * NQ / BC) % ntiles);
-    auto tile_row = [&](int t) { return ((t0 + t) % ntiles) * BC; };
+    const ScanOrder order(qb * NQ, BC, ntiles);
+    auto tile_row = [&](int t) { return order.tile(t) * BC; };
 
     // tile staging: global -> registers (prefetch) -> LDS
     intx4 pre[CPT];
@@ -791,9 +808,13 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
     __syncthreads();   // LDS is reused by the next block of a persistent workgroup
 }
 
+// Workgroups per CU a launch shape aims for: 32-row tiles keep the LDS of a
+// 4-wave workgroup near 50 KB, so three fit (12 waves; at most 168 VGPRs).
+constexpr int min_waves_per_simd(int waves, int bcr) { return waves == 4 && bcr == 32 ? 3 : 1; }
+
 // One query block per workgroup (blockIdx.x).
 template <int P, int NSTEP, int KSEL, int WAVES, int QB, int CBQ, int BCR>
-__global__ __launch_bounds__(WAVES * 64, 1) void dist_topk_kernel(TopkArgs A) {
+__global__ __launch_bounds__(WAVES * 64, min_waves_per_simd(WAVES, BCR)) void dist_topk_kernel(TopkArgs A) {
     __shared__ TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR> sm;
     topk_block<P, NSTEP, KSEL, WAVES, QB, CBQ, BCR>(sm, blockIdx.x, A);
 }
@@ -851,11 +872,11 @@ __global__ __launch_bounds__(KS_WAVES * 64, 1) void dist_topk_kstream_kernel(Top
     const int nch = DP / KS_DC;
     const int ntiles = (n + KS_BC - 1) / KS_BC;
     const int64_t total = (int64_t)ntiles * nch;
-    const int t0 = (int)(qb0 / KS_BC % ntiles);   // start at the block's own rows (see topk_block)
+    const ScanOrder order(qb0, KS_BC, ntiles);
     intx4 pre[CPT];
     float pre_norm = 0.f;
     auto prefetch = [&](int64_t g) {
-        const int t = (int)((t0 + g / nch) % ntiles), kc = (int)(g % nch);
+        const int t = order.tile((int)(g / nch)), kc = (int)(g % nch);
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
             const int c = tid + u * NT;
@@ -885,7 +906,7 @@ __global__ __launch_bounds__(KS_WAVES * 64, 1) void dist_topk_kstream_kernel(Top
     floatx16 acc[4];
     for (int64_t g = 0; g < total; ++g) {
         const int buf = (int)(g & 1);
-        const int t = (int)((t0 + g / nch) % ntiles), kc = (int)(g % nch);
+        const int t = order.tile((int)(g / nch)), kc = (int)(g % nch);
         if (kc == 0) {
 #pragma unroll
             for (int sub = 0; sub < 4; ++sub)
@@ -927,6 +948,65 @@ __global__ __launch_bounds__(KS_WAVES * 64, 1) void dist_topk_kstream_kernel(Top
     }
     sel.drain();
     if (A.nbr) write_lists(A, KSEL, qblk0, 32);
+}
+
+// Nearest candidate of every query row by (key, index): the pivot
+// assignment of the locality order.  One wave per 32 register-resident
+// queries; candidate tiles of 32 rows pass through LDS; each lane keeps its
+// best in registers and the two lanes of a query combine at the end.  No
+// self exclusion.  label[q] = index of the nearest candidate (0 if none).
+template <int P, int NSTEP, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void nearest_kernel(const uint8_t* __restrict__ ops,
+                                                             const float* __restrict__ ninit,
+                                                             const int32_t* __restrict__ sexp, int n,
+                                                             const uint8_t* __restrict__ qops,
+                                                             const int32_t* __restrict__ qsexp, int nq,
+                                                             float qmul, int32_t* __restrict__ label) {
+    using S = Shape<P, NSTEP, 32>;
+    constexpr int RB = S::ROW_BYTES, RS = S::RS, BC = 32;
+    constexpr int NT = WAVES * 64;
+    constexpr int CHUNKS = BC * RB / 16;
+    __shared__ __align__(16) uint8_t tile[BC * RS];
+    __shared__ __align__(16) float norm[BC];
+    __shared__ int32_t tsexp[BC];
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6, h = l >> 5, ql = l & 31;
+    const int64_t qg = ((int64_t)blockIdx.x * WAVES + w) * 32 + ql;
+    Frag<P, NSTEP> qf;
+    load_frag<P, NSTEP>(qf, qops + qg * RB + h * (RB / 2));
+    scale_query<P, NSTEP>(qf, qmul);
+    const int q_scale = P == SG_PREC_FP8 ? 127 + qsexp[qg] + 1 : 127;
+    float best = __builtin_inff();
+    int32_t bid = INT32_MAX;
+    for (int j0 = 0; j0 < n; j0 += BC) {
+        __syncthreads();
+        for (int c = tid; c < CHUNKS; c += NT) {
+            const int r = c / (RB / 16), o = c % (RB / 16);
+            *reinterpret_cast<intx4*>(&tile[r * RS + o * 16]) =
+                *reinterpret_cast<const intx4*>(ops + (int64_t)(j0 + r) * RB + o * 16);
+        }
+        if (tid < BC) {
+            norm[tid] = ninit[j0 + tid];
+            if constexpr (P == SG_PREC_FP8) tsexp[tid] = sexp[j0 + tid];
+        }
+        __syncthreads();
+        floatx16 acc;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[i] = norm[out_row(i, l)];
+        const int a_scale = P == SG_PREC_FP8 ? 127 + tsexp[ql] : 127;
+        acc = mfma_tile<P, NSTEP>(&tile[ql * RS + h * (RB / 2)], qf, acc, a_scale, q_scale);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int32_t r = j0 + out_row(i, l);
+            if (acc[i] < best || (acc[i] == best && r < bid)) {
+                best = acc[i];
+                bid = r;
+            }
+        }
+    }
+    const float ob = __builtin_bit_cast(float, lane_xor(__builtin_bit_cast(uint32_t, best), 32));
+    const int32_t oid = (int32_t)lane_xor((uint32_t)bid, 32);
+    if (ob < best || (ob == best && oid < bid)) bid = oid;
+    if (h == 0 && qg < nq) label[qg] = bid < n ? bid : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1077,6 +1157,9 @@ inline Layout layout(int64_t n, int d, int k, int prec, int rerank) {
 }
 
 typedef void (*topk_fn)(TopkArgs);
+typedef void (*near_fn)(const uint8_t*, const float*, const int32_t*, int, const uint8_t*, const int32_t*, int,
+                        float, int32_t*);
+constexpr int NEAR_WAVES = 4;
 typedef void (*kstream_fn)(TopkArgs, int);
 
 // A distance kernel and its launch geometry.
@@ -1087,6 +1170,7 @@ struct Kern {
     int nq_block = 0;             // queries per workgroup
     int threads = 0;
     int tile_rows = 0;            // candidate rows per LDS tile (0: k-streamed)
+    near_fn near = nullptr;       // nearest-candidate kernel on the same operands
 };
 
 template <int P, int NSTEP, int W, int QB = 1, int CBQ = CB, int BCR = 0>
@@ -1107,6 +1191,7 @@ Kern resident(int ksel) {
     k.nq_block = 32 * W * QB;
     k.threads = 64 * W;
     k.tile_rows = Shape<P, NSTEP, BCR>::BC;
+    k.near = nearest_kernel<P, NSTEP, NEAR_WAVES>;
     return k;
 }
 
@@ -1170,35 +1255,42 @@ Kern pick_kernel(int prec, int d, int ksel) {
 }
 
 // Alternatives to the default kernel of a row length: 4-wave workgroups with
-// 64-row tiles, of which two share a CU, so that one keeps the MFMA and VALU
-// units busy while the other waits at its tile barrier.  Same operand layout
-// as the default (same padded row length).
+// 64-row tiles (two per CU) or 32-row tiles (three per CU), so that other
+// workgroups keep the MFMA and VALU units busy while one waits at its tile
+// barrier or on a merge.  Same operand layout as the default (same padded
+// row length).
 std::vector<Kern> kernel_variants(int prec, int d, int ksel) {
     std::vector<Kern> v;
     const Kern def = pick_kernel(prec, d, ksel);
     if (!def.fn && !def.ks) return v;
     v.push_back(def);
     const int need = nstep_for(prec, padded_d(prec, d));
+#define SG_ALTS(PREC, NS)                                          \
+    do {                                                           \
+        v.push_back(resident<PREC, NS, 4, 1, CB, 64>(ksel));       \
+        v.push_back(resident<PREC, NS, 4, 1, CB, 32>(ksel));       \
+    } while (0)
     switch (prec) {
         case SG_PREC_FP32:
-            if (need <= 16) v.push_back(resident<SG_PREC_FP32, 16, 4, 1, CB, 64>(ksel));
-            else if (need <= 32) v.push_back(resident<SG_PREC_FP32, 32, 4, 1, CB, 64>(ksel));
+            if (need <= 16) SG_ALTS(SG_PREC_FP32, 16);
+            else if (need <= 32) SG_ALTS(SG_PREC_FP32, 32);
             break;
         case SG_PREC_F16:
-            if (need <= 4) v.push_back(resident<SG_PREC_F16, 4, 4, 1, CB, 64>(ksel));
-            else if (need <= 6) v.push_back(resident<SG_PREC_F16, 6, 4, 1, CB, 64>(ksel));
-            else if (need <= 8) v.push_back(resident<SG_PREC_F16, 8, 4, 1, CB, 64>(ksel));
+            if (need <= 4) SG_ALTS(SG_PREC_F16, 4);
+            else if (need <= 6) SG_ALTS(SG_PREC_F16, 6);
+            else if (need <= 8) SG_ALTS(SG_PREC_F16, 8);
             break;
         case SG_PREC_BF16:
-            if (need <= 4) v.push_back(resident<SG_PREC_BF16, 4, 4, 1, CB, 64>(ksel));
-            else if (need <= 6) v.push_back(resident<SG_PREC_BF16, 6, 4, 1, CB, 64>(ksel));
-            else if (need <= 8) v.push_back(resident<SG_PREC_BF16, 8, 4, 1, CB, 64>(ksel));
+            if (need <= 4) SG_ALTS(SG_PREC_BF16, 4);
+            else if (need <= 6) SG_ALTS(SG_PREC_BF16, 6);
+            else if (need <= 8) SG_ALTS(SG_PREC_BF16, 8);
             break;
         default:
-            if (need <= 1) v.push_back(resident<SG_PREC_FP8, 1, 4, 1, CB, 64>(ksel));
-            else if (need <= 2) v.push_back(resident<SG_PREC_FP8, 2, 4, 1, CB, 64>(ksel));
+            if (need <= 1) SG_ALTS(SG_PREC_FP8, 1);
+            else if (need <= 2) SG_ALTS(SG_PREC_FP8, 2);
             break;
     }
+#undef SG_ALTS
     return v;
 }
 
@@ -1292,6 +1384,8 @@ inline int64_t pad_rows(int64_t m) { return (m + PAD_ROWS - 1) / PAD_ROWS * PAD_
 // Locality order of a whole-shard build: rows are grouped by their nearest
 // of P evenly spaced pivot rows (about 256 rows per pivot), so that a
 // workgroup's queries and the candidates it scans first are close together.
+// (Register-resident kernels only; the k-streamed FP32 kernel keeps the input
+// order.)
 constexpr int64_t LOCAL_MIN_ROWS = 4096;   // smaller shards keep their order
 inline int64_t n_pivots(int64_t n) { return std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 8192); }
 inline bool use_locality(int64_t n, bool subset) { return !subset && n >= LOCAL_MIN_ROWS; }
@@ -1299,7 +1393,7 @@ inline bool use_locality(int64_t n, bool subset) { return !subset && n >= LOCAL_
 // Extra workspace of the locality order.
 inline size_t locality_bytes(const Layout& L, int64_t n, int prec) {
     const int64_t P = n_pivots(n), Pp = pad_rows(P);
-    return 2 * align_up((size_t)L.n_pad * 8, 256) + 2 * align_up((size_t)L.n_pad * 4, 256) +
+    return align_up((size_t)L.n_pad * 8, 256) + 2 * align_up((size_t)L.n_pad * 4, 256) +
            3 * align_up((size_t)(P + 1) * 8, 256) + align_up(exclusive_scan_tmp_bytes(P), 256) +
            align_up((size_t)Pp * L.DP * elem_bytes(prec), 256) + 3 * align_up((size_t)Pp * 4, 256) +
            align_up((size_t)P * 8, 256);
@@ -1382,7 +1476,7 @@ void run(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int
         set_error("sg_knn: workspace too small (need " + std::to_string(need) + " bytes)");
         throw Fail{SG_ERR_WORKSPACE};
     }
-    const bool local = use_locality(n, subset);
+    const bool local = use_locality(n, subset) && kern.near != nullptr;
     const int64_t nq_rows = subset ? nq : n;
     const int64_t nq_pad = subset ? pad_rows(nq) : L.n_pad;
     Carver cv(ws);
@@ -1416,7 +1510,6 @@ void run(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int
     if (local) {
         const int64_t P = n_pivots(n), Pp = pad_rows(P);
         perm = cv.take<int64_t>(L.n_pad);
-        int64_t* noself = cv.take<int64_t>(L.n_pad);
         pid = cv.take<int32_t>(L.n_pad);
         int32_t* lab = cv.take<int32_t>(L.n_pad);
         int64_t* cnt = cv.take<int64_t>(P + 1);
@@ -1437,14 +1530,9 @@ void run(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int
         prep_kernel<<<prep_grid, 256, 0, s>>>(X, dtype, n, d, ld, nullptr, n, L.n_pad, L.DP, prec, metric, ops,
                                               ninit, nout, sexp);
         SG_LAUNCH_CHECK();
-        fill<int64_t>(noself, -1, L.n_pad, s);
-        fill<uint64_t>(state, EMPTY_KEY, L.n_pad * 32, s);
-        const Kern ka = pick_kernel(prec, d, 32);
-        TopkArgs B{};
-        B.ops = pops; B.ninit = pinit; B.sexp = prec == SG_PREC_FP8 ? psexp : nullptr; B.n = (int)P;
-        B.qops = ops; B.qid = noself; B.qnout = nout; B.qsexp = sexp; B.nq = (int)n;
-        B.qmul = qmul; B.osc = osc; B.state = state; B.nbr = lab; B.k_out = 1;
-        launch_topk(ka, B, L.n_pad, L.DP, s);
+        kern.near<<<(unsigned)(L.n_pad / (32 * NEAR_WAVES)), NEAR_WAVES * 64, 0, s>>>(
+            pops, pinit, prec == SG_PREC_FP8 ? psexp : nullptr, (int)P, ops, sexp, (int)n, qmul, lab);
+        SG_LAUNCH_CHECK();
         // group the rows by pivot
         fill<int64_t>(cnt, 0, P + 1, s);
         fill<int64_t>(cur, 0, P + 1, s);
