@@ -153,6 +153,39 @@ sg_status sg_knn_rows(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64
                       void* stream);
 
 /* ------------------------------------------------------------------------
+ * sg_knn_graph_batched -- kNN graphs and pruned graphs of many shards at once
+ *
+ * The per-shard build of Sec. IV step 2 for all S shards of one GPU in a
+ * single pass (the batching form): shard s is rows [offsets_h[s],
+ * offsets_h[s+1]) of X (offsets_h[0] = 0, non-decreasing, S <= 64).  For each
+ * shard the result equals sg_knn_graph on that shard alone (ids local to the
+ * shard), followed by sg_prune to degree R:
+ *    graphs[offsets_h[s] + i][0..R)  pruned list of local row i of shard s,
+ *    knn   [offsets_h[s] + i][0..k)  its kNN list (knn may be NULL).
+ * k in 1..128, R in 1..min(k, 64); rows need a register-resident distance
+ * kernel (FP32 d <= 128, 16-bit d <= 768, FP8 d <= 1024).  The distance work
+ * of all shards is one persistent launch (largest shards first); the launch
+ * shape is the one sg_knn_autotune recorded for the largest shard, else the
+ * default.
+ *
+ * plan: NULL runs the sequence eagerly on `stream`.  Otherwise the stream must
+ * not be the default stream: if *plan is NULL the call captures the sequence
+ * into a HIP graph, instantiates it, stores the new plan in *plan and launches
+ * it; if *plan is a plan from an earlier call with identical arguments
+ * (pointers, sizes, stream, device, launch shape) the call replays it with one
+ * graph launch; other arguments give SG_ERR_ARG.  The plan is owned by the
+ * caller and freed with sg_batch_plan_destroy (NULL is accepted).
+ * ---------------------------------------------------------------------- */
+typedef struct sg_batch_plan sg_batch_plan;
+sg_status sg_knn_graph_batched_workspace_size(const int64_t* offsets_h, int32_t S, int32_t d, int32_t k,
+                                              int32_t R, sg_prec prec, size_t* bytes);
+sg_status sg_knn_graph_batched(const void* X, sg_dtype dtype, int32_t d, int64_t ld,
+                               const int64_t* offsets_h, int32_t S, sg_metric metric, int32_t k,
+                               int32_t R, sg_prec prec, int32_t* graphs, int32_t* knn, void* ws,
+                               size_t ws_bytes, void* stream, sg_batch_plan** plan);
+void sg_batch_plan_destroy(sg_batch_plan* plan);
+
+/* ------------------------------------------------------------------------
  * Distance-kernel variants and autotuning
  *
  * Each (precision, padded row length) has a default distance kernel and may

@@ -12,6 +12,8 @@ import ctypes as C
 import os
 import threading
 
+import numpy as np
+
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -69,6 +71,10 @@ _SIGS = {
     "sg_knn_variant_count": (i32, [i32, i32, i32, C.POINTER(C.c_int32)]),
     "sg_knn_autotune": (i32, [vp, i32, i64, i32, i64, i32, i32, i32, i32, vp, sz, vp, vp, vp, i32]),
     "sg_knn_force_variant": (i32, [i32]),
+    "sg_knn_graph_batched_workspace_size": (i32, [vp, i32, i32, i32, i32, i32, psz]),
+    "sg_knn_graph_batched": (i32, [vp, i32, i32, i64, vp, i32, i32, i32, i32, i32, vp, vp, vp, sz, vp,
+                                   C.POINTER(C.c_void_p)]),
+    "sg_batch_plan_destroy": (None, [vp]),
     "sg_mlp_workspace_size": (i32, [i32, i32, i32, i32, psz]),
     "sg_mlp_project_workspace_size": (i32, [i32, i32, i32, psz]),
     "sg_mlp_stats": (i32, [vp, i64, i32, i64, vp, i64, vp, vp, vp, sz, vp]),
@@ -198,6 +204,48 @@ def sg_knn_autotune(X, k, metric="l2", prec="fp32", rerank=0, stream=None):
 def sg_knn_force_variant(variant):
     """Make this thread's later kNN calls use variant `variant` (-1: the recorded choice)."""
     _check("sg_knn_force_variant", lib().sg_knn_force_variant(int(variant)))
+
+
+class BatchPlan:
+    """A captured batched build (HIP graph) for one fixed set of arguments;
+    pass it to sg_knn_graph_batched again to replay.  Freed on close()/GC."""
+
+    def __init__(self):
+        self.ptr = C.c_void_p(None)
+
+    def close(self):
+        if self.ptr.value:
+            lib().sg_batch_plan_destroy(self.ptr)
+            self.ptr = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sg_knn_graph_batched(X, offsets, k, R, metric="l2", prec="fp32", knn=True, out=None, stream=None,
+                         plan=None):
+    """Pruned graphs (and kNN lists) of the shards X[offsets[s]:offsets[s+1]]:
+    (graphs int32 [n, R], knn int32 [n, k] or None), ids local to each shard."""
+    L = lib()
+    dt, n, d, ld = _rows(X)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    S = off.size - 1
+    offp = off.ctypes.data_as(C.c_void_p)
+    m, p = METRICS[metric], PRECS[prec]
+    nbytes = _size(L.sg_knn_graph_batched_workspace_size, offp, S, d, k, R, p)
+    ws = _ws.get(nbytes, X.device, "batched")
+    if out is not None:
+        graphs, kn = out
+    else:
+        graphs = torch.empty((int(off[-1]), R), dtype=torch.int32, device=X.device)
+        kn = torch.empty((int(off[-1]), k), dtype=torch.int32, device=X.device) if knn else None
+    pp = C.byref(plan.ptr) if plan is not None else None
+    _check("sg_knn_graph_batched", L.sg_knn_graph_batched(_ptr(X), dt, d, ld, offp, S, m, k, R, p, _ptr(graphs),
+                                                          _ptr(kn), _ptr(ws), ws.numel(), _stream(stream), pp))
+    return graphs, kn
 
 
 def sg_knn_rows(X, rows, k, metric="l2", prec="fp32", rerank=0, stream=None):

@@ -1,0 +1,468 @@
+// batch.hip -- shard graphs of many shards in one pass (the batching form).
+//
+// The per-shard build of Sec. IV step 2 for all shards of one GPU at once:
+// every step runs as one launch over all shards (operand preparation, the
+// locality order, the distance + top-k kernel, the prune), so that small
+// shards do not leave the GPU idle.  The distance kernel is persistent: a grid
+// sized to the GPU's resident capacity takes (shard, query block) items from
+// a device counter, largest shards first (longest-processing-time order, so
+// that the tail is made of short items).  With a plan, the whole sequence is
+// captured once into a HIP graph and later calls replay it with one launch.
+#include <cstring>
+
+#include "knn_impl.hpp"
+
+struct sg_batch_plan {
+    hipGraphExec_t exec = nullptr;
+    std::vector<uint8_t> sig;   // the arguments the graph was captured with
+    int device = -1;
+};
+
+namespace sg {
+namespace batch {
+
+using namespace knn;
+
+constexpr int MAXS = 64;
+
+// The shard table, passed by value to the batched kernels.  Shard s holds
+// input / output rows [row0[s], row0[s+1]) (row0[0] = 0), operand rows
+// [pad0[s], pad0[s] + n_s) of a layout padded per shard to PAD_ROWS, pivot
+// labels [piv0[s], piv0[s+1]) and pivot operand rows from ppad0[s].  Work
+// items: the k-th largest shard, order[k], owns items [item0[k], item0[k+1]).
+struct Shards {
+    int S;
+    int64_t row0[MAXS + 1];
+    int64_t pad0[MAXS + 1];
+    int64_t piv0[MAXS + 1];
+    int64_t ppad0[MAXS + 1];
+    int32_t item0[MAXS + 1];
+    int32_t order[MAXS];
+};
+
+// largest s in [0, S) with b[s] <= x
+__device__ inline int shard_of(const int64_t* b, int S, int64_t x) {
+    int lo = 0, hi = S - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b[mid] <= x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Row maps of the identity operand layout and of the pivots; the locality
+// permutation starts empty (padding = -1).
+__global__ void maps_kernel(Shards sh, int64_t* __restrict__ idmap, int64_t* __restrict__ perm,
+                            int32_t* __restrict__ pid, int64_t* __restrict__ pivmap) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < sh.pad0[sh.S]; j += stride) {
+        const int s = shard_of(sh.pad0, sh.S, j);
+        const int64_t loc = j - sh.pad0[s], ns = sh.row0[s + 1] - sh.row0[s];
+        idmap[j] = loc < ns ? sh.row0[s] + loc : -1;
+        perm[j] = -1;
+        pid[j] = -1;
+    }
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < sh.ppad0[sh.S]; p += stride) {
+        const int s = shard_of(sh.ppad0, sh.S, p);
+        const int64_t lp = p - sh.ppad0[s], P = sh.piv0[s + 1] - sh.piv0[s];
+        const int64_t ns = sh.row0[s + 1] - sh.row0[s];
+        pivmap[p] = lp < P ? sh.row0[s] + lp * ns / P : -1;
+    }
+}
+
+// Nearest pivot of every row, each shard against its own pivots; labels are
+// global (shard s owns labels piv0[s]..).
+template <int P, int NSTEP>
+__global__ __launch_bounds__(NEAR_WAVES * 64) void near_batched_kernel(Shards sh, const uint8_t* __restrict__ pops,
+                                                                       const float* __restrict__ pinit,
+                                                                       const int32_t* __restrict__ psexp,
+                                                                       const uint8_t* __restrict__ ops,
+                                                                       const int32_t* __restrict__ sexp, float qmul,
+                                                                       int32_t* __restrict__ lab) {
+    constexpr int RB = Shape<P, NSTEP, 32>::ROW_BYTES;
+    constexpr int QR = NEAR_WAVES * 32;   // query rows per block; PAD_ROWS is a multiple
+    const int64_t r = (int64_t)blockIdx.x * QR;
+    const int s = shard_of(sh.pad0, sh.S, r);
+    const int64_t p0 = sh.pad0[s], pp0 = sh.ppad0[s];
+    nearest_block<P, NSTEP, NEAR_WAVES>((r - p0) / QR, pops + pp0 * RB, pinit + pp0, psexp ? psexp + pp0 : nullptr,
+                                        (int)(sh.piv0[s + 1] - sh.piv0[s]), ops + p0 * RB, sexp ? sexp + p0 : nullptr,
+                                        (int)(sh.row0[s + 1] - sh.row0[s]), qmul, lab + p0, (int32_t)sh.piv0[s]);
+}
+
+__global__ void count_batched_kernel(Shards sh, const int32_t* __restrict__ lab, int64_t* __restrict__ cnt) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < sh.pad0[sh.S];
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int s = shard_of(sh.pad0, sh.S, j);
+        if (j - sh.pad0[s] >= sh.row0[s + 1] - sh.row0[s]) continue;   // padding
+        int64_t c = lab[j];
+        if (c < sh.piv0[s] || c >= sh.piv0[s + 1]) c = sh.piv0[s];
+        atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[c]), 1ull);
+    }
+}
+
+// Rows of each shard grouped by label (labels of shard s follow those of
+// shard s-1, so the scan of the counts starts shard s at row0[s]).  Any order
+// within a label gives the same lists: keys carry the row ids.
+__global__ void scatter_batched_kernel(Shards sh, const int32_t* __restrict__ lab, const int64_t* __restrict__ off,
+                                       int64_t* __restrict__ cur, int64_t* __restrict__ perm,
+                                       int32_t* __restrict__ pid) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < sh.pad0[sh.S];
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int s = shard_of(sh.pad0, sh.S, j);
+        const int64_t loc = j - sh.pad0[s];
+        if (loc >= sh.row0[s + 1] - sh.row0[s]) continue;
+        int64_t c = lab[j];
+        if (c < sh.piv0[s] || c >= sh.piv0[s + 1]) c = sh.piv0[s];
+        const int64_t pos = off[c] + (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&cur[c]), 1ull);
+        const int64_t o = pos - sh.row0[s] + sh.pad0[s];
+        perm[o] = sh.row0[s] + loc;
+        pid[o] = (int32_t)(sh.row0[s] + loc);
+    }
+}
+
+// Persistent distance + top-k over all shards.  A holds the base pointers of
+// the whole batch (operand-layout arrays and the output lists); each item
+// narrows them to one shard.  Candidate ids and output rows are batch rows
+// (row0-based); every workgroup leaves once the counter passes the last item.
+template <int P, int NSTEP, int KSEL, int WAVES, int QB, int CBQ, int BCR>
+__global__ __launch_bounds__(WAVES * 64, min_waves_per_simd(WAVES, BCR)) void dist_topk_batched_kernel(
+    TopkArgs A, Shards sh, unsigned int* __restrict__ counter, int nitems) {
+    __shared__ TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR> sm;
+    __shared__ int s_item;
+    constexpr int RB = Shape<P, NSTEP, BCR>::ROW_BYTES;
+    while (true) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= nitems) break;
+        int k = 0;
+        while (k + 1 < sh.S && sh.item0[k + 1] <= it) ++k;
+        const int s = sh.order[k];
+        const int64_t p0 = sh.pad0[s];
+        TopkArgs B = A;
+        B.ops = A.ops + p0 * RB;
+        B.ninit = A.ninit + p0;
+        B.sexp = A.sexp ? A.sexp + p0 : nullptr;
+        B.cpid = A.cpid + p0;
+        B.n = (int)(sh.row0[s + 1] - sh.row0[s]);
+        B.qops = B.ops;
+        B.qid = nullptr;
+        B.qnout = A.qnout + p0;
+        B.qsexp = B.sexp;
+        B.qout = A.qout + p0;
+        B.nq = B.n;
+        B.state = A.state + p0 * KSEL;
+        topk_block<P, NSTEP, KSEL, WAVES, QB, CBQ, BCR>(sm, it - sh.item0[k], B);
+    }
+}
+
+// Batch-row ids -> shard-local ids, in place (SG_NONE stays).
+__global__ void localize_kernel(Shards sh, int32_t* __restrict__ lists, int width) {
+    const int64_t total = sh.row0[sh.S] * width;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / width;
+        const int32_t v = lists[e];
+        if (v >= 0) lists[e] = (int32_t)(v - sh.row0[shard_of(sh.row0, sh.S, r)]);
+    }
+}
+
+typedef void (*bfn)(TopkArgs, Shards, unsigned int*, int);
+typedef void (*bnear_fn)(Shards, const uint8_t*, const float*, const int32_t*, const uint8_t*, const int32_t*, float,
+                         int32_t*);
+
+struct BKern {
+    bfn fn = nullptr;
+    bnear_fn near = nullptr;
+    int DP = 0, nq_block = 0, threads = 0;
+};
+
+struct BatchedMaker {
+    int ksel;
+    std::vector<BKern> v;
+    template <int P, int NSTEP, int W, int QB, int CBQ, int BCR>
+    void add() {
+        BKern k;
+        k.fn = ksel <= 64 ? dist_topk_batched_kernel<P, NSTEP, 64, W, QB, CBQ, BCR>
+                          : dist_topk_batched_kernel<P, NSTEP, 128, W, QB, CBQ, BCR>;
+        k.near = near_batched_kernel<P, NSTEP>;
+        k.DP = 2 * NSTEP * Tr<P>::VEC;
+        k.nq_block = 32 * W * QB;
+        k.threads = 64 * W;
+        v.push_back(k);
+    }
+};
+
+// Everything a call needs, derived from its arguments.
+struct Plan {
+    Shards sh{};
+    int S = 0, ksel = 0, DP = 0, eb = 0, nitems = 0;
+    int64_t n_all = 0, n_max = 0;
+    BKern kern;
+    size_t prune_bytes = 0, scan_bytes = 0, total = 0;
+};
+
+Plan make_plan(const int64_t* off, int S, int d, int k, int R, int prec) {
+    SG_REQUIRE(S >= 1 && S <= MAXS, "S must be in 1..64");
+    SG_REQUIRE(off != nullptr, "offsets_h is NULL");
+    SG_REQUIRE(off[0] == 0, "offsets_h[0] must be 0");
+    SG_REQUIRE(d >= 1 && d <= 1024, "d out of range");
+    SG_REQUIRE(k >= 1 && k <= 128, "k must be in 1..128 for the batched build");
+    SG_REQUIRE(R >= 1 && R <= k && R <= 64, "R must be in 1..min(k, 64)");
+    SG_REQUIRE(prec >= SG_PREC_FP32 && prec <= SG_PREC_FP8, "unknown precision");
+    Plan p;
+    p.S = S;
+    p.sh.S = S;
+    p.ksel = ksel_for(k) < 64 ? 64 : ksel_for(k);
+    for (int s = 0; s < S; ++s) {
+        SG_REQUIRE(off[s + 1] >= off[s], "offsets_h must be non-decreasing");
+        SG_REQUIRE(off[s + 1] - off[s] < (int64_t(1) << 31), "shard too large");
+    }
+    SG_REQUIRE(off[S] < (int64_t(1) << 31), "more than 2^31 rows in the batch");
+    BatchedMaker m{p.ksel, {}};
+    SG_REQUIRE(for_shapes(prec, d, m), "no register-resident distance kernel for this precision and d");
+    int64_t pad = 0, piv = 0, ppad = 0;
+    for (int s = 0; s < S; ++s) {
+        const int64_t ns = off[s + 1] - off[s];
+        p.sh.row0[s] = off[s];
+        p.sh.pad0[s] = pad;
+        p.sh.piv0[s] = piv;
+        p.sh.ppad0[s] = ppad;
+        pad += pad_rows(ns);
+        const int64_t P = ns > 0 ? n_pivots(ns) : 0;
+        piv += P;
+        ppad += pad_rows(P);
+        p.n_max = std::max(p.n_max, ns);
+    }
+    p.sh.row0[S] = off[S];
+    p.sh.pad0[S] = pad;
+    p.sh.piv0[S] = piv;
+    p.sh.ppad0[S] = ppad;
+    p.n_all = off[S];
+    const int idx = chosen_variant(prec, d, p.ksel, p.n_max, (int)m.v.size());
+    p.kern = m.v[idx];
+    p.DP = p.kern.DP;
+    p.eb = elem_bytes(prec);
+    // work items: shards by descending size (ties by index), blocks of nq_block rows
+    std::vector<int> ord(S);
+    for (int s = 0; s < S; ++s) ord[s] = s;
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int a, int b) { return off[a + 1] - off[a] > off[b + 1] - off[b]; });
+    int64_t items = 0;
+    for (int k2 = 0; k2 < S; ++k2) {
+        p.sh.order[k2] = ord[k2];
+        p.sh.item0[k2] = (int32_t)items;
+        items += (p.sh.pad0[ord[k2] + 1] - p.sh.pad0[ord[k2]]) / p.kern.nq_block;
+    }
+    p.sh.item0[S] = (int32_t)items;
+    SG_REQUIRE(items < (int64_t(1) << 31), "too many work items");
+    p.nitems = (int)items;
+    size_t pb = 0;
+    if (sg_prune_workspace_size(p.n_all, k, R, &pb) != SG_OK) throw Fail{SG_ERR_INTERNAL};
+    p.prune_bytes = pb;
+    p.scan_bytes = exclusive_scan_tmp_bytes(std::max<int64_t>(piv, 1));
+    const size_t P8 = align_up((size_t)pad * 8, 256), P4 = align_up((size_t)pad * 4, 256);
+    const size_t Q8 = align_up((size_t)ppad * 8, 256), Q4 = align_up((size_t)ppad * 4, 256);
+    const size_t L8 = align_up((size_t)(piv + 1) * 8, 256);
+    p.total = align_up((size_t)pad * p.DP * p.eb, 256) + 3 * P4        // ops, ninit, nout, sexp
+              + 2 * P8 + 2 * P4                                       // idmap, perm, pid, lab
+              + Q8 + align_up((size_t)ppad * p.DP * p.eb, 256) + 3 * Q4   // pivots
+              + 3 * L8 + align_up(p.scan_bytes, 256)                  // label counts / offsets / cursors
+              + align_up((size_t)pad * p.ksel * 8, 256)               // state
+              + 256                                                   // counter
+              + align_up((size_t)p.n_all * k * 4, 256)                // kNN lists (when not returned)
+              + align_up(p.prune_bytes, 256) + 1024;
+    return p;
+}
+
+// Enqueue the whole build on s (no host synchronisation, no memset: valid
+// inside a stream capture).
+void enqueue(const Plan& p, const void* X, int dtype, int d, int64_t ld, int metric, int k, int R, int prec,
+             int32_t* graphs, int32_t* knn_out, void* ws, hipStream_t s) {
+    const int64_t pad = p.sh.pad0[p.S], ppad = p.sh.ppad0[p.S], piv = p.sh.piv0[p.S];
+    Carver cv(ws);
+    uint8_t* ops = cv.take<uint8_t>((size_t)pad * p.DP * p.eb);
+    float* ninit = cv.take<float>(pad);
+    float* nout = cv.take<float>(pad);
+    int32_t* sexp = cv.take<int32_t>(pad);
+    int64_t* idmap = cv.take<int64_t>(pad);
+    int64_t* perm = cv.take<int64_t>(pad);
+    int32_t* pid = cv.take<int32_t>(pad);
+    int32_t* lab = cv.take<int32_t>(pad);
+    int64_t* pivmap = cv.take<int64_t>(ppad);
+    uint8_t* pops = cv.take<uint8_t>((size_t)ppad * p.DP * p.eb);
+    float* pinit = cv.take<float>(ppad);
+    float* pnout = cv.take<float>(ppad);
+    int32_t* psexp = cv.take<int32_t>(ppad);
+    int64_t* cnt = cv.take<int64_t>(piv + 1);
+    int64_t* loff = cv.take<int64_t>(piv + 1);
+    int64_t* cur = cv.take<int64_t>(piv + 1);
+    void* scan_tmp = cv.take<char>(p.scan_bytes);
+    uint64_t* state = cv.take<uint64_t>((size_t)pad * p.ksel);
+    unsigned int* counter = cv.take<unsigned int>(64);
+    int32_t* knn_ws = cv.take<int32_t>((size_t)p.n_all * k);
+    void* prune_ws = cv.take<char>(p.prune_bytes);
+    int32_t* knn = knn_out ? knn_out : knn_ws;
+    const bool fp8 = prec == SG_PREC_FP8;
+    const bool plain_ip = metric == SG_IP && !norm_corrected_ip(metric, prec);
+    const float qmul = plain_ip ? -1.0f : -2.0f;
+    const float osc = norm_corrected_ip(metric, prec) ? 0.5f : 1.0f;
+    const unsigned eg = (unsigned)std::min<int64_t>(cdiv(std::max(pad, ppad), 256), 8192);
+
+    maps_kernel<<<eg, 256, 0, s>>>(p.sh, idmap, perm, pid, pivmap);
+    SG_LAUNCH_CHECK();
+    prep_kernel<<<(unsigned)cdiv(ppad, 4), 256, 0, s>>>(X, dtype, ppad, d, ld, pivmap, p.n_all, ppad, p.DP, prec,
+                                                       metric, pops, pinit, pnout, fp8 ? psexp : nullptr);
+    SG_LAUNCH_CHECK();
+    prep_kernel<<<(unsigned)cdiv(pad, 4), 256, 0, s>>>(X, dtype, pad, d, ld, idmap, p.n_all, pad, p.DP, prec, metric,
+                                                      ops, ninit, nout, fp8 ? sexp : nullptr);
+    SG_LAUNCH_CHECK();
+    p.kern.near<<<(unsigned)(pad / (NEAR_WAVES * 32)), NEAR_WAVES * 64, 0, s>>>(
+        p.sh, pops, pinit, fp8 ? psexp : nullptr, ops, fp8 ? sexp : nullptr, qmul, lab);
+    SG_LAUNCH_CHECK();
+    fill<int64_t>(cnt, 0, piv + 1, s);
+    fill<int64_t>(cur, 0, piv + 1, s);
+    count_batched_kernel<<<eg, 256, 0, s>>>(p.sh, lab, cnt);
+    SG_LAUNCH_CHECK();
+    exclusive_scan_i64(cnt, loff, piv, scan_tmp, s);
+    scatter_batched_kernel<<<eg, 256, 0, s>>>(p.sh, lab, loff, cur, perm, pid);
+    SG_LAUNCH_CHECK();
+    prep_kernel<<<(unsigned)cdiv(pad, 4), 256, 0, s>>>(X, dtype, pad, d, ld, perm, p.n_all, pad, p.DP, prec, metric,
+                                                      ops, ninit, nout, fp8 ? sexp : nullptr);
+    SG_LAUNCH_CHECK();
+    fill<uint64_t>(state, EMPTY_KEY, pad * p.ksel, s);
+    fill<unsigned int>(counter, 0u, 1, s);
+
+    TopkArgs A{};
+    A.ops = ops;
+    A.ninit = ninit;
+    A.sexp = fp8 ? sexp : nullptr;
+    A.cpid = pid;
+    A.qnout = nout;
+    A.qout = perm;
+    A.qmul = qmul;
+    A.osc = osc;
+    A.state = state;
+    A.nbr = knn;
+    A.dist = nullptr;
+    A.k_out = k;
+    int dev = 0, cus = 0, per_cu = 0;
+    SG_HIP(hipGetDevice(&dev));
+    SG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    SG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(p.kern.fn),
+                                                        p.kern.threads, 0));
+    const int grid = std::max(1, std::min(p.nitems, cus * std::max(per_cu, 1)));
+    p.kern.fn<<<grid, p.kern.threads, 0, s>>>(A, p.sh, counter, p.nitems);
+    SG_LAUNCH_CHECK();
+
+    const sg_status pr = sg_prune(knn, p.n_all, k, R, graphs, prune_ws, p.prune_bytes, s);
+    if (pr != SG_OK) throw Fail{pr};
+    const unsigned lg = (unsigned)std::min<int64_t>(cdiv(p.n_all * R, 256), 8192);
+    localize_kernel<<<lg, 256, 0, s>>>(p.sh, graphs, R);
+    SG_LAUNCH_CHECK();
+    if (knn_out) {
+        localize_kernel<<<(unsigned)std::min<int64_t>(cdiv(p.n_all * k, 256), 8192), 256, 0, s>>>(p.sh, knn_out, k);
+        SG_LAUNCH_CHECK();
+    }
+}
+
+std::vector<uint8_t> signature(const void* X, int dtype, int d, int64_t ld, const int64_t* off, int S, int metric,
+                               int k, int R, int prec, const int32_t* graphs, const int32_t* knn, const void* ws,
+                               size_t ws_bytes, hipStream_t s, const Plan& p) {
+    std::vector<uint8_t> v;
+    auto put = [&](const void* a, size_t n) {
+        const uint8_t* b = static_cast<const uint8_t*>(a);
+        v.insert(v.end(), b, b + n);
+    };
+    put(&X, sizeof X);
+    put(&dtype, sizeof dtype);
+    put(&d, sizeof d);
+    put(&ld, sizeof ld);
+    put(off, sizeof(int64_t) * (S + 1));
+    put(&S, sizeof S);
+    put(&metric, sizeof metric);
+    put(&k, sizeof k);
+    put(&R, sizeof R);
+    put(&prec, sizeof prec);
+    put(&graphs, sizeof graphs);
+    put(&knn, sizeof knn);
+    put(&ws, sizeof ws);
+    put(&ws_bytes, sizeof ws_bytes);
+    put(&s, sizeof s);
+    put(&p.kern.fn, sizeof p.kern.fn);
+    return v;
+}
+
+}  // namespace batch
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" sg_status sg_knn_graph_batched_workspace_size(const int64_t* offsets_h, int32_t S, int32_t d, int32_t k,
+                                                         int32_t R, sg_prec prec, size_t* bytes) {
+    return guarded([&] {
+        SG_REQUIRE(bytes != nullptr, "bytes is NULL");
+        *bytes = batch::make_plan(offsets_h, S, d, k, R, prec).total;
+    });
+}
+
+extern "C" sg_status sg_knn_graph_batched(const void* X, sg_dtype dtype, int32_t d, int64_t ld,
+                                          const int64_t* offsets_h, int32_t S, sg_metric metric, int32_t k,
+                                          int32_t R, sg_prec prec, int32_t* graphs, int32_t* knn, void* ws,
+                                          size_t ws_bytes, void* stream, sg_batch_plan** plan) {
+    return guarded([&] {
+        const batch::Plan p = batch::make_plan(offsets_h, S, d, k, R, prec);
+        knn::check_args(X, dtype, p.n_all, d, ld, metric, k, prec, 0);
+        SG_REQUIRE(graphs != nullptr, "graphs is NULL");
+        if (ws == nullptr || ws_bytes < p.total) {
+            set_error("sg_knn_graph_batched: workspace too small (need " + std::to_string(p.total) + " bytes)");
+            throw Fail{SG_ERR_WORKSPACE};
+        }
+        if (p.n_all == 0) return;
+        hipStream_t s = as_stream(stream);
+        if (plan == nullptr) {
+            batch::enqueue(p, X, dtype, d, ld, metric, k, R, prec, graphs, knn, ws, s);
+            return;
+        }
+        SG_REQUIRE(s != nullptr, "capturing a plan needs a non-default stream");
+        const std::vector<uint8_t> sig =
+            batch::signature(X, dtype, d, ld, offsets_h, S, metric, k, R, prec, graphs, knn, ws, ws_bytes, s, p);
+        int dev = 0;
+        SG_HIP(hipGetDevice(&dev));
+        if (*plan != nullptr) {
+            SG_REQUIRE((*plan)->sig == sig && (*plan)->device == dev,
+                       "the plan was captured for other arguments (destroy it and pass a NULL plan)");
+            SG_HIP(hipGraphLaunch((*plan)->exec, s));
+            return;
+        }
+        SG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipGraph_t graph = nullptr;
+        try {
+            batch::enqueue(p, X, dtype, d, ld, metric, k, R, prec, graphs, knn, ws, s);
+        } catch (...) {
+            (void)hipStreamEndCapture(s, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        SG_HIP(hipStreamEndCapture(s, &graph));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        SG_HIP(e);
+        sg_batch_plan* np = new sg_batch_plan;
+        np->exec = exec;
+        np->sig = sig;
+        np->device = dev;
+        *plan = np;
+        SG_HIP(hipGraphLaunch(exec, s));
+    });
+}
+
+extern "C" void sg_batch_plan_destroy(sg_batch_plan* plan) {
+    if (!plan) return;
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    delete plan;
+}

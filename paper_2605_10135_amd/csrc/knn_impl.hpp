@@ -1,0 +1,1423 @@
+// knn_impl.hpp -- device code and shared host helpers of the fused distance +
+// top-k kernels: operand preparation, the register-resident and k-streamed
+// distance kernels with their selection epilogue, the nearest-pivot kernel of
+// the locality order, the FP32 re-rank, launch-shape variants and workspace
+// layout.  Included by knn.hip (one shard) and batch.hip (many shards).
+#pragma once
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "common.hpp"
+
+namespace sg {
+namespace knn {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
+typedef int intx4 __attribute__((ext_vector_type(4)));
+
+constexpr int TWAVES = 8;        // waves per workgroup of the distance kernel
+constexpr int TQB = 1;           // 32-query blocks per wave
+constexpr int BQ = 32 * TQB * TWAVES;   // query rows per workgroup
+constexpr int CB = 32;           // per-query candidate buffer (default; at most 32)
+constexpr int PAD_ROWS = BQ;     // operand rows are padded to a multiple of this (>= any tile)
+
+// ---------------------------------------------------------------------------
+// operand traits: element bytes, elements per lane per MFMA step
+// ---------------------------------------------------------------------------
+template <int P> struct Tr;
+template <> struct Tr<SG_PREC_FP32> { static constexpr int EB = 4, VEC = 1; };
+template <> struct Tr<SG_PREC_F16> { static constexpr int EB = 2, VEC = 8; };
+template <> struct Tr<SG_PREC_BF16> { static constexpr int EB = 2, VEC = 8; };
+template <> struct Tr<SG_PREC_FP8> { static constexpr int EB = 1, VEC = 32; };
+
+// padded row length (elements) for a given d: two lane-halves, each a whole
+// number of MFMA steps
+__host__ __device__ inline int padded_d(int prec, int d) {
+    int g = 2 * (prec == SG_PREC_FP32 ? 2 : prec == SG_PREC_FP8 ? 32 : 8);
+    return (d + g - 1) / g * g;
+}
+__host__ __device__ inline int elem_bytes(int prec) {
+    return prec == SG_PREC_FP32 ? 4 : prec == SG_PREC_FP8 ? 1 : 2;
+}
+
+// ---------------------------------------------------------------------------
+// prep: conversion, norms, FP8 scales
+// ---------------------------------------------------------------------------
+__device__ inline float load_elem(const void* X, int dtype, int64_t idx) {
+    switch (dtype) {
+        case SG_F32: return static_cast<const float*>(X)[idx];
+        case SG_F16: return (float)static_cast<const _Float16*>(X)[idx];
+        case SG_BF16: {
+            uint32_t b = (uint32_t) static_cast<const uint16_t*>(X)[idx] << 16;
+            return __builtin_bit_cast(float, b);
+        }
+        default: return (float)static_cast<const uint8_t*>(X)[idx];
+    }
+}
+
+// FP32 -> BF16 bits, round to nearest even (NaN kept quiet)
+__device__ inline uint16_t to_bf16_bits(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// FP32 -> OCP E4M3 code, round to nearest even, saturating at 448.  Works on
+// the bit pattern: normal codes carry 3 mantissa bits, subnormals are
+// multiples of 2^-9.
+__device__ inline uint8_t to_fp8_bits(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    uint8_t sign = (uint8_t)((u >> 24) & 0x80);
+    uint32_t a = u & 0x7fffffffu;
+    if (a > 0x7f800000u) return 0x7f;                       // NaN
+    if (a >= 0x43e00000u) return sign | 0x7e;               // |f| >= 448
+    int e = (int)(a >> 23) - 127;                           // unbiased exponent
+    if (e < -6) {
+        // subnormal range: value / 2^-9 rounded to an integer 0..8
+        float v = __builtin_bit_cast(float, a) * 512.0f;    // exact (power of two)
+        float r = __builtin_rintf(v);                       // ties to even
+        return sign | (uint8_t)r;
+    }
+    uint32_t mant = a & 0x7fffffu;                          // 23 bits, keep 3
+    uint32_t keep = mant >> 20;
+    uint32_t rest = mant & 0xfffffu;
+    if (rest > 0x80000u || (rest == 0x80000u && (keep & 1u))) keep += 1;
+    int ex = e + 7;
+    if (keep == 8) {
+        keep = 0;
+        ex += 1;
+    }
+    uint32_t code = ((uint32_t)ex << 3) | keep;
+    if (code > 0x7e) code = 0x7e;
+    return sign | (uint8_t)code;
+}
+
+__device__ inline float fp8_value(uint8_t c) {
+    int e = (c >> 3) & 15, m = c & 7;
+    float v = e == 0 ? (float)m * (1.0f / 512.0f)
+                     : __builtin_ldexpf(1.0f + (float)m * 0.125f, e - 7);
+    return (c & 0x80) ? -v : v;
+}
+
+// Ranking-key form per (metric, precision):
+//   L2             key = ||c~||^2 - 2 q~.c~            dist = key + ||q~||^2
+//   IP, FP32/F16   key = -q.c                           dist = key
+//   IP, BF16/FP8   key = ||c~||^2 - ||c||^2 - 2 q~.c~   dist = (key + ||q~||^2 - ||q||^2) / 2
+// (x~ = the rounded operand row).  The reduced-precision IP key is the L2 key
+// of the rounded rows with the exact norm put back: its rounding error scales
+// with ||q - c|| instead of ||q|| ||c||, which keeps near neighbours apart.
+__host__ __device__ inline bool norm_corrected_ip(int metric, int prec) {
+    return metric == SG_IP && (prec == SG_PREC_BF16 || prec == SG_PREC_FP8);
+}
+
+// One wave per operand row (source row rowmap[row], or row itself when
+// rowmap is NULL).  Writes the converted row (zero padded to DP),
+// the accumulator start of the row as a candidate (ninit, +inf for padding
+// rows), its output offset as a query (nout) and, for FP8, the row's scale
+// exponent.
+static __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_t n, int d, int64_t ld,
+                            const int64_t* __restrict__ rowmap, int64_t n_src, int64_t n_pad, int DP,
+                            int prec, int metric, uint8_t* __restrict__ ops, float* __restrict__ ninit,
+                            float* __restrict__ nout, int32_t* __restrict__ sexp) {
+    const int l = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= n_pad) return;
+    const int eb = elem_bytes(prec);
+    uint8_t* out = ops + row * (int64_t)DP * eb;
+    const int64_t src_row = row < n ? (rowmap ? rowmap[row] : row) : -1;
+    if (src_row < 0 || src_row >= n_src) {      // padding (or an out-of-range listed row)
+        for (int t = l; t < DP; t += 64) {
+            if (eb == 4) reinterpret_cast<float*>(out)[t] = 0.f;
+            else if (eb == 2) reinterpret_cast<uint16_t*>(out)[t] = 0;
+            else out[t] = 0;
+        }
+        if (l == 0) {
+            ninit[row] = __builtin_nanf("");   // never admitted: NaN fails every comparison
+            nout[row] = 0.f;
+            if (sexp) sexp[row] = 0;
+        }
+        return;
+    }
+    const int64_t base = src_row * ld;
+    int sx = 0;
+    float inv = 1.0f;
+    if (prec == SG_PREC_FP8) {
+        float amax = 0.f;
+        for (int t = l; t < d; t += 64) amax = fmaxf(amax, fabsf(load_elem(X, dtype, base + t)));
+        for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+        // smallest power of two s with amax / s <= 448
+        if (amax > 0.f) {
+            sx = (int)ceilf(log2f(amax / 448.0f));
+            while (__builtin_ldexpf(amax, -sx) > 448.0f) ++sx;
+            while (sx > -126 && __builtin_ldexpf(amax, -(sx - 1)) <= 448.0f) --sx;
+        }
+        inv = __builtin_ldexpf(1.0f, -sx);
+    }
+    float ssq = 0.f, ssx = 0.f;
+    for (int t = l; t < DP; t += 64) {
+        float v = t < d ? load_elem(X, dtype, base + t) : 0.f;
+        float q;
+        switch (prec) {
+            case SG_PREC_FP32:
+                reinterpret_cast<float*>(out)[t] = v;
+                q = v;
+                break;
+            case SG_PREC_F16: {
+                _Float16 h = (_Float16)v;
+                reinterpret_cast<_Float16*>(out)[t] = h;
+                q = (float)h;
+                break;
+            }
+            case SG_PREC_BF16: {
+                uint16_t b = to_bf16_bits(v);
+                reinterpret_cast<uint16_t*>(out)[t] = b;
+                q = __builtin_bit_cast(float, (uint32_t)b << 16);
+                break;
+            }
+            default: {
+                uint8_t c = to_fp8_bits(v * inv);
+                out[t] = c;
+                q = __builtin_ldexpf(fp8_value(c), sx);
+                break;
+            }
+        }
+        ssq += q * q;
+        ssx += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        ssq += __shfl_xor(ssq, o, 64);
+        ssx += __shfl_xor(ssx, o, 64);
+    }
+    if (l == 0) {
+        if (metric == SG_L2) {
+            ninit[row] = ssq;
+            nout[row] = ssq;
+        } else if (norm_corrected_ip(metric, prec)) {
+            ninit[row] = ssq - ssx;
+            nout[row] = ssq - ssx;
+        } else {
+            ninit[row] = 0.f;
+            nout[row] = 0.f;
+        }
+        if (sexp) sexp[row] = sx;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fused distance tile + top-k
+// ---------------------------------------------------------------------------
+
+// row of the 32x32 MFMA output held by accumulator register i of lane l
+__device__ inline int out_row(int i, int l) { return ((i >> 2) << 3) + ((l >> 5) << 2) + (i & 3); }
+
+template <int P, int NSTEP>
+struct Frag;
+
+template <int NSTEP>
+struct Frag<SG_PREC_FP32, NSTEP> {
+    float v[NSTEP];
+};
+template <int NSTEP>
+struct Frag<SG_PREC_F16, NSTEP> {
+    half8 v[NSTEP];
+};
+template <int NSTEP>
+struct Frag<SG_PREC_BF16, NSTEP> {
+    bf16x8 v[NSTEP];
+};
+template <int NSTEP>
+struct Frag<SG_PREC_FP8, NSTEP> {
+    intx8 v[NSTEP];
+};
+
+// Load lane l's half-row (elements [h*DH, (h+1)*DH)) from a byte row.
+template <int P, int NSTEP>
+__device__ inline void load_frag(Frag<P, NSTEP>& f, const uint8_t* rowp) {
+    if constexpr (P == SG_PREC_FP32) {
+#pragma unroll
+        for (int s = 0; s < NSTEP; s += 2) {
+            float2 v = *reinterpret_cast<const float2*>(rowp + s * 4);
+            f.v[s] = v.x;
+            f.v[s + 1] = v.y;
+        }
+    } else if constexpr (P == SG_PREC_FP8) {
+#pragma unroll
+        for (int s = 0; s < NSTEP; ++s) {
+            intx4 a = *reinterpret_cast<const intx4*>(rowp + s * 32);
+            intx4 b = *reinterpret_cast<const intx4*>(rowp + s * 32 + 16);
+            f.v[s] = intx8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < NSTEP; ++s) {
+            intx4 a = *reinterpret_cast<const intx4*>(rowp + s * 16);
+            if constexpr (P == SG_PREC_F16)
+                f.v[s] = __builtin_bit_cast(half8, a);
+            else
+                f.v[s] = __builtin_bit_cast(bf16x8, a);
+        }
+    }
+}
+
+// Scale the query fragment by qmul (-2 or -1, exact) so that the MFMA yields
+// the ranking key.  FP8 (always the -2 form) flips the code signs and carries
+// the x2 in the scale exponent.
+template <int P, int NSTEP>
+__device__ inline void scale_query(Frag<P, NSTEP>& f, float qmul) {
+    if constexpr (P == SG_PREC_FP8) {
+#pragma unroll
+        for (int s = 0; s < NSTEP; ++s)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) f.v[s][e] ^= (int)0x80808080u;
+    } else {
+        const float m = qmul;
+#pragma unroll
+        for (int s = 0; s < NSTEP; ++s) {
+            if constexpr (P == SG_PREC_FP32) {
+                f.v[s] *= m;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    if constexpr (P == SG_PREC_F16)
+                        f.v[s][e] = (_Float16)((float)f.v[s][e] * m);
+                    else
+                        f.v[s][e] = (__bf16)((float)f.v[s][e] * m);
+                }
+            }
+        }
+    }
+}
+
+template <int P>
+__device__ inline floatx16 mfma_step(const void* a, const void* b, floatx16 acc, int sa, int sb);
+
+// Largest divisor of n that is at most m.
+constexpr int group_of(int n, int m) {
+    for (int g = m; g > 1; --g)
+        if (n % g == 0) return g;
+    return 1;
+}
+
+// acc += A(32 candidate rows at arow, LDS) x Q(32 queries) over the padded
+// row, in groups of steps whose A fragments are all requested before the
+// group's MFMA chain starts, so that one LDS round trip covers the group.
+template <int P, int NSTEP>
+__device__ inline floatx16 mfma_tile(const uint8_t* arow, const Frag<P, NSTEP>& q, floatx16 acc,
+                                     int sa, int sb) {
+    if constexpr (P == SG_PREC_FP32) {
+        constexpr int G = 4 * group_of(NSTEP / 4, 4);   // floats per group
+        static_assert(NSTEP % 4 == 0, "FP32 steps come in whole float4s");
+#pragma unroll
+        for (int g = 0; g < NSTEP; g += G) {
+            floatx4 a[G / 4];
+#pragma unroll
+            for (int s = 0; s < G / 4; ++s) a[s] = *reinterpret_cast<const floatx4*>(arow + (g + 4 * s) * 4);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int s = 0; s < G; ++s)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s / 4][s % 4], q.v[g + s], acc, 0, 0, 0);
+        }
+    } else if constexpr (P == SG_PREC_F16 || P == SG_PREC_BF16) {
+        constexpr int G = group_of(NSTEP, 8);
+#pragma unroll
+        for (int g = 0; g < NSTEP; g += G) {
+            intx4 a[G];
+#pragma unroll
+            for (int s = 0; s < G; ++s) a[s] = *reinterpret_cast<const intx4*>(arow + (g + s) * 16);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int s = 0; s < G; ++s) {
+                if constexpr (P == SG_PREC_F16)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, a[s]), q.v[g + s],
+                                                                 acc, 0, 0, 0);
+                else
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[s]),
+                                                                  q.v[g + s], acc, 0, 0, 0);
+            }
+        }
+    } else {
+        constexpr int G = group_of(NSTEP, 4);
+#pragma unroll
+        for (int g = 0; g < NSTEP; g += G) {
+            intx4 a[2 * G];
+#pragma unroll
+            for (int s = 0; s < 2 * G; ++s) a[s] = *reinterpret_cast<const intx4*>(arow + g * 32 + s * 16);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int s = 0; s < G; ++s) {
+                const intx8 f = intx8{a[2 * s][0], a[2 * s][1], a[2 * s][2], a[2 * s][3],
+                                      a[2 * s + 1][0], a[2 * s + 1][1], a[2 * s + 1][2], a[2 * s + 1][3]};
+                acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(f, q.v[g + s], acc, 0, 0, 0, sa, 0, sb);
+            }
+        }
+    }
+    return acc;
+}
+
+template <int P, int NSTEP, int BCR = 0>
+struct Shape {
+    static constexpr int DH = NSTEP * Tr<P>::VEC;             // elements per lane-half
+    static constexpr int ROW_BYTES = 2 * DH * Tr<P>::EB;      // padded operand row
+    static constexpr int RS = ROW_BYTES + 16;                 // LDS row stride (bank spread)
+    // candidate rows per LDS tile (BCR, or by default so that two tiles, the
+    // double buffer, stay within ~70 KB)
+    static constexpr int BC = BCR > 0 ? BCR : ROW_BYTES <= 256 ? 128 : ROW_BYTES <= 512 ? 64 : 32;
+    static constexpr int NSUB = BC / 32;
+    static_assert(BC % 32 == 0, "tiles hold whole 32-row subtiles");
+};
+
+// Bitonic merge (ascending) of 64*PER keys held as v[p] (element p*64 + lane)
+// that already form a bitonic sequence.
+template <int PER>
+__device__ inline void bitonic_merge_multi(uint64_t (&v)[PER]) {
+    const int l = lane_id();
+#pragma unroll
+    for (int j = 32 * PER; j > 0; j >>= 1) {
+        if (j >= 64) {
+            const int jp = j >> 6;
+#pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                const int q = p ^ jp;
+                if (q > p) {
+                    uint64_t a = v[p], b = v[q];
+                    v[p] = a < b ? a : b;
+                    v[q] = a < b ? b : a;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < PER; ++p) v[p] = cmpx(v[p], j, (l & j) == 0);
+        }
+    }
+}
+
+// Merge one query's candidate buffer (c <= 32 keys in LDS) into its
+// sorted top-KSEL list in the workspace, all in registers: the list's load is
+// issued first; the buffer is sorted descending in lanes 0..31 and moved to
+// lanes 32..63, where the element-wise minimum with the list's last 64 keys
+// leaves the KSEL smallest of both as a bitonic sequence, which is then
+// merged.  Returns the new admission threshold: the KSEL-th distance (+inf
+// while the list is not full).
+template <int KSEL>
+__device__ float merge_query(uint64_t* __restrict__ gstate, const uint64_t* buf, int c) {
+    constexpr int PER = KSEL >= 64 ? KSEL / 64 : 1;
+    const int l = lane_id();
+    uint64_t v[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int e = p * 64 + l;
+        v[p] = e < KSEL ? gstate[e] : EMPTY_KEY;
+    }
+    uint64_t b = l < c ? buf[l] : EMPTY_KEY;
+    b = low_half_to_high(half_sort_desc_u64(b));
+    if (l >= 32 && b < v[PER - 1]) v[PER - 1] = b;
+    bitonic_merge_multi<PER>(v);
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int e = p * 64 + l;
+        if (e < KSEL) gstate[e] = v[p];
+    }
+    return key_dist(readlane_u64(v[(KSEL - 1) / 64], (KSEL - 1) & 63));
+}
+
+// Per-wave selection state: the admission threshold of each of the wave's
+// 32*QB queries (lanes l and l+32 share query l%32 of each block), the id
+// excluded as the query itself, and the LDS buffers / counters and workspace
+// top-KSEL lists of those queries.
+template <int KSEL, int QB, int CBQ = CB>
+struct Selector {
+    static_assert(CBQ <= 32, "a buffer is sorted inside one wave half");
+    float thr[QB];
+    int64_t qself[QB];
+    int64_t qlo, qhi;  // wave-uniform range of the wave's query ids
+    uint64_t* state;   // state row of the wave's first query
+    uint64_t* buf;     // LDS buffers of the wave's queries (32*QB*CBQ keys)
+    int fill[QB];      // buffer fill of the lane's query (same in both lanes)
+
+    // After qself is set: the smallest and largest query id of the wave, so
+    // that a subtile whose candidate ids miss [qlo, qhi] skips the per-lane
+    // self test with one scalar comparison (no valid query: qlo > qhi).
+    __device__ void init_self_range() {
+        uint64_t lo = (uint64_t)INT64_MAX, hi = 0;
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+            if (qself[b] >= 0) {
+                lo = (uint64_t)qself[b] < lo ? (uint64_t)qself[b] : lo;
+                hi = (uint64_t)qself[b] > hi ? (uint64_t)qself[b] : hi;
+            }
+        }
+#pragma unroll
+        for (int j = 1; j < 64; j <<= 1) {
+            const uint64_t ol = lane_xor_u64(lo, j), oh = lane_xor_u64(hi, j);
+            lo = ol < lo ? ol : lo;
+            hi = oh > hi ? oh : hi;
+        }
+        qlo = (int64_t)readlane_u64(lo, 0);
+        qhi = (int64_t)readlane_u64(hi, 0);
+    }
+
+    // Smallest of a lane's 16 distances (eight 3-input minimums; NaN only if all are).
+    __device__ static float min16(const floatx16& a) {
+        const float p0 = fminf(fminf(a[0], a[1]), a[2]), p1 = fminf(fminf(a[3], a[4]), a[5]);
+        const float p2 = fminf(fminf(a[6], a[7]), a[8]), p3 = fminf(fminf(a[9], a[10]), a[11]);
+        const float p4 = fminf(fminf(a[12], a[13]), a[14]);
+        return fminf(fminf(fminf(p0, p1), p2), fminf(fminf(p3, p4), a[15]));
+    }
+
+    // Admit the candidates of one 32x32 subtile (operand rows cbase..cbase+31,
+    // whose ids are tpid[0..32), or cbase.. when tpid is NULL) whose key is
+    // <= the threshold, one accumulator element at a time: from the element's
+    // ballot the two lanes of a query see each other's hit, so they write
+    // their keys at known slots (no atomics) and both keep the query's buffer
+    // fill in a register.  Round 1 stops at the first element some buffer
+    // cannot take; then every query whose buffer could not take two keys per
+    // remaining element is merged, and round 2 finishes the subtile without
+    // checks (CBQ = 32 guarantees the room).  A merged query's lowered
+    // threshold takes effect at the next subtile.  Admission is exact in any
+    // candidate order: a candidate whose distance exceeds the K-th distance of
+    // a subset already seen cannot be in the top K, and one that equals it is
+    // admitted and ranked by (distance, id) in the merge.  The query itself
+    // and padding rows are NaN, which no comparison admits.
+    __device__ void admit(floatx16 (&acc)[QB], int64_t cbase, const int32_t* tpid) {
+        static_assert(CBQ == 32, "round 2 relies on room for 32 keys after a merge");
+        const int l = lane_id();
+        const int ql = l & 31;
+        const int h = l >> 5;
+        if (cbase <= qhi && cbase + 31 >= qlo) {
+            const int32_t rel0 = (int32_t)(cbase - qlo);
+#pragma unroll
+            for (int b = 0; b < QB; ++b) {
+                const int32_t me = qself[b] >= 0 ? (int32_t)(qself[b] - qlo) : INT32_MIN;
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    if (rel0 + out_row(i, l) == me) acc[b][i] = __builtin_nanf("");
+            }
+        }
+        bool any = false;
+#pragma unroll
+        for (int b = 0; b < QB; ++b) any |= min16(acc[b]) <= thr[b];
+        if (!__builtin_amdgcn_ballot_w64(any)) return;
+        // the ids of this lane's 16 rows: groups of 4 consecutive rows
+        int32_t ids[16];
+        if (tpid) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const intx4 v = *reinterpret_cast<const intx4*>(tpid + g * 8 + h * 4);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) ids[g * 4 + e] = v[e];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) ids[i] = (int32_t)(cbase + out_row(i, l));
+        }
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+            const float t = thr[b];
+            int c = fill[b];
+            uint64_t* qbuf = buf + (b * 32 + ql) * CBQ;
+            int stop = 16;   // wave-uniform: first element round 1 left
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                if (i >= stop) continue;
+                const bool hit = acc[b][i] <= t;
+                const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+                if (m == 0) continue;
+                const int pa = (int)(((uint32_t)m >> ql) & 1u);
+                const int pb = (int)(((uint32_t)(m >> 32) >> ql) & 1u);
+                if (__builtin_amdgcn_ballot_w64(c + pa + pb > CBQ)) {
+                    stop = i;
+                    continue;
+                }
+                if (hit) qbuf[c + (h ? pa : 0)] = make_key(acc[b][i], ids[i]);
+                c += pa + pb;
+            }
+            if (stop < 16) {
+                const int room = 2 * (16 - stop);
+                uint32_t need = (uint32_t)__builtin_amdgcn_ballot_w64(h == 0 && c + room > CBQ);
+                float tnext = t;
+                while (need) {
+                    const int qi = __builtin_ctz(need);
+                    need &= need - 1;
+                    const int q2 = b * 32 + qi;
+                    const float tq = merge_query<KSEL>(state + (int64_t)q2 * KSEL, buf + q2 * CBQ,
+                                                       __builtin_amdgcn_readlane(c, qi));
+                    if (ql == qi) {
+                        c = 0;
+                        tnext = tq;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    if (i < stop) continue;
+                    const bool hit = acc[b][i] <= t;
+                    const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+                    if (m == 0) continue;
+                    const int pa = (int)(((uint32_t)m >> ql) & 1u);
+                    const int pb = (int)(((uint32_t)(m >> 32) >> ql) & 1u);
+                    if (hit) qbuf[c + (h ? pa : 0)] = make_key(acc[b][i], ids[i]);
+                    c += pa + pb;
+                }
+                thr[b] = tnext;
+            }
+            fill[b] = c;
+        }
+    }
+
+    // Merge every non-empty buffer (end of the candidate stream).
+    __device__ void drain() {
+        const int l = lane_id();
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+            const uint64_t m = __builtin_amdgcn_ballot_w64(l < 32 && fill[b] > 0);
+            uint32_t need = (uint32_t)m;
+            while (need) {
+                const int qi = __builtin_ctz(need);
+                need &= need - 1;
+                const int q2 = b * 32 + qi;
+                merge_query<KSEL>(state + (int64_t)q2 * KSEL, buf + q2 * CBQ,
+                                  __builtin_amdgcn_readlane(fill[b], qi));
+            }
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+};
+
+// Arguments of one distance-kernel launch (a block of queries against one
+// candidate set).  Candidate operand row j has id cpid[j] (NULL: j); query
+// row q writes output row qout[q] (NULL: q) and excludes the candidate whose
+// operand row is qid[q] (NULL: q; negative: none).
+struct TopkArgs {
+    const uint8_t* ops;      // candidate operands, padded rows
+    const float* ninit;      // accumulator start per candidate (NaN: padding)
+    const int32_t* sexp;     // FP8 row scale exponents (else NULL)
+    const int32_t* cpid;     // candidate ids (nullable)
+    int n;                   // candidate rows
+    const uint8_t* qops;     // query operands (padded to whole blocks)
+    const int64_t* qid;      // self row per query (nullable)
+    const float* qnout;      // output term per query
+    const int32_t* qsexp;
+    const int64_t* qout;     // output row per query (nullable)
+    int nq;                  // query rows
+    float qmul, osc;
+    uint64_t* state;         // sorted top-KSEL keys per query (operand order)
+    int32_t* nbr;            // nullable: no lists written
+    float* dist;             // nullable
+    int k_out;
+};
+
+// Final lists of the wave's queries: ids and output distances.
+__device__ inline void write_lists(const TopkArgs& A, int ksel, int64_t q0, int nqw) {
+    const int l = lane_id();
+    for (int qi = 0; qi < nqw; ++qi) {
+        const int64_t q = q0 + qi;
+        if (q >= A.nq) break;
+        const float qn = A.qnout[q];
+        const int64_t o = A.qout ? A.qout[q] : q;
+        for (int t = l; t < A.k_out; t += 64) {
+            const uint64_t key = A.state[q * ksel + t];
+            A.nbr[o * A.k_out + t] = key_id(key);
+            if (A.dist)
+                A.dist[o * A.k_out + t] = key == EMPTY_KEY ? __builtin_inff() : (key_dist(key) + qn) * A.osc;
+        }
+    }
+}
+
+// LDS of the register-resident kernel.
+template <int P, int NSTEP, int WAVES, int QB, int CBQ, int BCR>
+struct TopkSmem {
+    using S = Shape<P, NSTEP, BCR>;
+    static constexpr int NQ = 32 * QB * WAVES;
+    __align__(16) uint8_t tile[2][S::BC * S::RS];
+    __align__(16) float norm[2][S::BC];
+    __align__(16) int32_t pid[2][S::BC];
+    int32_t sexp[2][P == SG_PREC_FP8 ? S::BC : 1];
+    uint64_t buf[NQ * CBQ];
+};
+
+// Candidate tile order of a query block: first the tiles of the 256-row
+// group that holds the block's own rows (with rows in locality order these
+// hold the queries' closest neighbours, so the thresholds tighten at once),
+// then all other tiles in ascending order -- the same order for every block,
+// so that concurrently running workgroups stream the same rows through L2.
+struct ScanOrder {
+    int t0, R;
+    __device__ ScanOrder(int64_t first_row, int bc, int ntiles) {
+        R = (256 + bc - 1) / bc;
+        if (R > ntiles) R = ntiles;
+        const int own = (int)(first_row / 256 * 256 / bc);
+        t0 = own < ntiles - R ? own : ntiles - R;
+    }
+    __device__ int tile(int t) const {
+        if (t < R) return t0 + t;
+        const int g = t - R;
+        return g < t0 ? g : g + R;
+    }
+};
+
+// One block of NQ = 32*QB*WAVES queries (query rows qb*NQ.. of A.qops)
+// against all A.n candidate rows: the fused distance tile + top-k with
+// register-resident queries.  Candidate tiles (BC rows) are staged in LDS,
+// double buffered, the next tile already in flight in registers while the
+// current one is computed.  Within a tile the MFMAs of subtile s+1 are
+// issued before the selection epilogue of subtile s so that both run at once.
+// Tiles are visited in ScanOrder.
+template <int P, int NSTEP, int KSEL, int WAVES, int QB, int CBQ, int BCR>
+__device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t qb, const TopkArgs& A) {
+    using S = Shape<P, NSTEP, BCR>;
+    constexpr int BC = S::BC, NSUB = S::NSUB, RB = S::ROW_BYTES, RS = S::RS;
+    constexpr int NT = WAVES * 64;
+    constexpr int NQ = 32 * QB * WAVES;
+    constexpr int CHUNKS = BC * RB / 16;                        // 16-byte chunks per tile
+    constexpr int CPT = (CHUNKS + NT - 1) / NT;                 // chunks per thread
+
+    const int tid = threadIdx.x;
+    const int l = tid & 63;
+    const int w = tid >> 6;
+    const int h = l >> 5;
+    const int ql = l & 31;
+    const int64_t qblk0 = qb * NQ + w * 32 * QB;   // first query of this wave
+
+    Frag<P, NSTEP> qf[QB];
+    int q_scale[QB];
+    Selector<KSEL, QB, CBQ> sel;
+    sel.state = A.state + qblk0 * KSEL;
+    sel.buf = sm.buf + w * 32 * QB * CBQ;
+#pragma unroll
+    for (int b = 0; b < QB; ++b) {
+        const int64_t qg = qblk0 + b * 32 + ql;
+        load_frag<P, NSTEP>(qf[b], A.qops + qg * RB + h * (RB / 2));
+        scale_query<P, NSTEP>(qf[b], A.qmul);
+        q_scale[b] = 127;
+        if constexpr (P == SG_PREC_FP8) q_scale[b] = 127 + A.qsexp[qg] + 1;
+        sel.thr[b] = __builtin_inff();
+        sel.fill[b] = 0;
+        sel.qself[b] = qg < A.nq ? (A.qid ? A.qid[qg] : qg) : -1;
+    }
+    sel.init_self_range();
+
+    const int ntiles = (A.n + BC - 1) / BC;
+    const ScanOrder order(qb * NQ, BC, ntiles);
+    auto tile_row = [&](int t) { return order.tile(t) * BC; };
+
+    // tile staging: global -> registers (prefetch) -> LDS
+    intx4 pre[CPT];
+    float pre_norm = 0.f;
+    int32_t pre_pid = 0, pre_sexp = 0;
+    auto prefetch = [&](int j0) {
+        const uint8_t* src = A.ops + (int64_t)j0 * RB;
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int c = tid + u * NT;
+            if (c < CHUNKS) pre[u] = *reinterpret_cast<const intx4*>(src + (int64_t)c * 16);
+        }
+        if (tid < BC) {
+            pre_norm = A.ninit[j0 + tid];
+            if (A.cpid) pre_pid = A.cpid[j0 + tid];
+            if constexpr (P == SG_PREC_FP8) pre_sexp = A.sexp[j0 + tid];
+        }
+    };
+    auto commit = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int c = tid + u * NT;
+            if (c < CHUNKS) {
+                const int r = c / (RB / 16), o = c % (RB / 16);
+                *reinterpret_cast<intx4*>(&sm.tile[buf][r * RS + o * 16]) = pre[u];
+            }
+        }
+        if (tid < BC) {
+            sm.norm[buf][tid] = pre_norm;
+            sm.pid[buf][tid] = pre_pid;
+            if constexpr (P == SG_PREC_FP8) sm.sexp[buf][tid] = pre_sexp;
+        }
+    };
+    auto compute = [&](floatx16 (&acc)[QB], int buf, int sub) {
+        floatx4 nv[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+            nv[g] = *reinterpret_cast<const floatx4*>(&sm.norm[buf][sub * 32 + g * 8 + h * 4]);
+        int a_scale = 127;
+        if constexpr (P == SG_PREC_FP8) a_scale = 127 + sm.sexp[buf][sub * 32 + ql];
+        const uint8_t* arow = &sm.tile[buf][(sub * 32 + ql) * RS + h * (RB / 2)];
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[b][i] = nv[i >> 2][i & 3];
+        }
+#pragma unroll
+        for (int b = 0; b < QB; ++b) acc[b] = mfma_tile<P, NSTEP>(arow, qf[b], acc[b], a_scale, q_scale[b]);
+    };
+
+    prefetch(tile_row(0));
+    commit(0);
+    __syncthreads();
+    if (ntiles > 1) prefetch(tile_row(1));
+    for (int t = 0; t < ntiles; ++t) {
+        const int buf = t & 1;
+        const int j0 = tile_row(t);
+        const int32_t* tp = A.cpid ? sm.pid[buf] : nullptr;
+        floatx16 accA[QB], accB[QB];
+        compute(accA, buf, 0);
+#pragma unroll
+        for (int sub = 0; sub < NSUB; ++sub) {
+            if (sub % 2 == 0) {
+                if (sub + 1 < NSUB) compute(accB, buf, sub + 1);
+                sel.admit(accA, j0 + sub * 32, tp ? tp + sub * 32 : nullptr);
+            } else {
+                if (sub + 1 < NSUB) compute(accA, buf, sub + 1);
+                sel.admit(accB, j0 + sub * 32, tp ? tp + sub * 32 : nullptr);
+            }
+        }
+        if (t + 1 < ntiles) {
+            commit(buf ^ 1);
+            if (t + 2 < ntiles) prefetch(tile_row(t + 2));
+        }
+        __syncthreads();
+    }
+    sel.drain();
+    if (A.nbr) write_lists(A, KSEL, qblk0, 32 * QB);
+    __syncthreads();   // LDS is reused by the next block of a persistent workgroup
+}
+
+// Workgroups per CU a launch shape aims for: 32-row tiles keep the LDS of a
+// 4-wave workgroup near 50 KB, so three fit (12 waves; at most 168 VGPRs).
+constexpr int min_waves_per_simd(int waves, int bcr) { return waves == 4 && bcr == 32 ? 3 : 1; }
+
+// One query block per workgroup (blockIdx.x).
+template <int P, int NSTEP, int KSEL, int WAVES, int QB, int CBQ, int BCR>
+__global__ __launch_bounds__(WAVES * 64, min_waves_per_simd(WAVES, BCR)) void dist_topk_kernel(TopkArgs A) {
+    __shared__ TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR> sm;
+    topk_block<P, NSTEP, KSEL, WAVES, QB, CBQ, BCR>(sm, blockIdx.x, A);
+}
+
+
+// Fused distance tile + top-k for FP32 rows too wide for register-resident
+// queries: a 128 x 128 (queries x candidates) workgroup tile accumulated over
+// k in chunks of 32, both operands staged through LDS (double buffered, the
+// next chunk loading into registers during the current chunk's MFMAs); the
+// selection runs on the four 32x32 subtiles of each wave once a candidate
+// tile's k-loop is complete.
+constexpr int KS_WAVES = 4;
+constexpr int KS_NQ = 128;
+constexpr int KS_BC = 128;
+constexpr int KS_DC = 32;
+constexpr int KS_RS = KS_DC + 4;    // LDS row stride (floats)
+
+template <int KSEL>
+__global__ __launch_bounds__(KS_WAVES * 64, 1) void dist_topk_kstream_kernel(TopkArgs A, int DP) {
+    const float* __restrict__ ops = reinterpret_cast<const float*>(A.ops);
+    const float* __restrict__ ninit = A.ninit;
+    const int n = A.n;
+    const float* __restrict__ qops = reinterpret_cast<const float*>(A.qops);
+    const int64_t* __restrict__ qid = A.qid;
+    const int nq = A.nq;
+    const float qmul = A.qmul;
+    uint64_t* __restrict__ state = A.state;
+    constexpr int NT = KS_WAVES * 64;
+    constexpr int CPR = KS_DC / 4;                       // 16-byte chunks per row per k-chunk
+    constexpr int CPT = (KS_NQ + KS_BC) * CPR / NT;      // per thread per k-chunk
+    __shared__ __align__(16) float s_q[2][KS_NQ * KS_RS];
+    __shared__ __align__(16) float s_c[2][KS_BC * KS_RS];
+    __shared__ __align__(16) float s_norm[KS_BC];
+    __shared__ uint64_t s_buf[KS_NQ * CB];
+
+    const int tid = threadIdx.x;
+    const int l = tid & 63;
+    const int w = tid >> 6;
+    const int h = l >> 5;
+    const int ql = l & 31;
+    const int64_t qb0 = (int64_t)blockIdx.x * KS_NQ;
+    const int64_t qblk0 = qb0 + w * 32;
+
+    Selector<KSEL, 1> sel;
+    sel.state = state + qblk0 * KSEL;
+    sel.buf = s_buf + w * 32 * CB;
+    {
+        const int64_t qg = qblk0 + ql;
+        sel.thr[0] = __builtin_inff();
+        sel.fill[0] = 0;
+        sel.qself[0] = qg < nq ? (qid ? qid[qg] : qg) : -1;
+    }
+    sel.init_self_range();
+
+    const int nch = DP / KS_DC;
+    const int ntiles = (n + KS_BC - 1) / KS_BC;
+    const int64_t total = (int64_t)ntiles * nch;
+    const ScanOrder order(qb0, KS_BC, ntiles);
+    intx4 pre[CPT];
+    float pre_norm = 0.f;
+    auto prefetch = [&](int64_t g) {
+        const int t = order.tile((int)(g / nch)), kc = (int)(g % nch);
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int c = tid + u * NT;
+            const int r = c / CPR, o = c % CPR;
+            const float* src = r < KS_NQ ? qops + (qb0 + r) * DP
+                                         : ops + ((int64_t)t * KS_BC + (r - KS_NQ)) * DP;
+            pre[u] = *reinterpret_cast<const intx4*>(src + kc * KS_DC + o * 4);
+        }
+        if (kc == 0 && tid < KS_BC) pre_norm = ninit[(int64_t)t * KS_BC + tid];
+    };
+    auto commit = [&](int64_t g, int buf) {
+        const int kc = (int)(g % nch);
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int c = tid + u * NT;
+            const int r = c / CPR, o = c % CPR;
+            float* dst = r < KS_NQ ? &s_q[buf][r * KS_RS + o * 4] : &s_c[buf][(r - KS_NQ) * KS_RS + o * 4];
+            *reinterpret_cast<intx4*>(dst) = pre[u];
+        }
+        if (kc == 0 && tid < KS_BC) s_norm[tid] = pre_norm;
+    };
+
+    prefetch(0);
+    commit(0, 0);
+    __syncthreads();
+    if (total > 1) prefetch(1);
+    floatx16 acc[4];
+    for (int64_t g = 0; g < total; ++g) {
+        const int buf = (int)(g & 1);
+        const int t = order.tile((int)(g / nch)), kc = (int)(g % nch);
+        if (kc == 0) {
+#pragma unroll
+            for (int sub = 0; sub < 4; ++sub)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) acc[sub][i] = s_norm[sub * 32 + out_row(i, l)];
+        }
+        // B fragment: this lane's query, the lane half's 16 k values of the chunk
+        float bq[KS_DC / 2];
+#pragma unroll
+        for (int v = 0; v < KS_DC / 8; ++v) {
+            floatx4 x = *reinterpret_cast<const floatx4*>(&s_q[buf][(w * 32 + ql) * KS_RS + h * (KS_DC / 2) + v * 4]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) bq[v * 4 + e] = x[e] * qmul;
+        }
+#pragma unroll
+        for (int sub = 0; sub < 4; ++sub) {
+            const float* arow = &s_c[buf][(sub * 32 + ql) * KS_RS + h * (KS_DC / 2)];
+#pragma unroll
+            for (int v = 0; v < KS_DC / 8; ++v) {
+                floatx4 a = *reinterpret_cast<const floatx4*>(arow + v * 4);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    acc[sub] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[e], bq[v * 4 + e], acc[sub], 0, 0, 0);
+            }
+        }
+        if (kc == nch - 1) {
+#pragma unroll
+            for (int sub = 0; sub < 4; ++sub) {
+                floatx16 one[1] = {acc[sub]};
+                const int64_t cb = (int64_t)t * KS_BC + sub * 32;
+                sel.admit(one, cb, A.cpid ? A.cpid + cb : nullptr);
+            }
+        }
+        if (g + 1 < total) {
+            commit(g + 1, buf ^ 1);
+            if (g + 2 < total) prefetch(g + 2);
+        }
+        __syncthreads();
+    }
+    sel.drain();
+    if (A.nbr) write_lists(A, KSEL, qblk0, 32);
+}
+
+// Nearest candidate of every query row by (key, index): the pivot
+// assignment of the locality order.  One wave per 32 register-resident
+// queries; candidate tiles of 32 rows pass through LDS; each lane keeps its
+// best in registers and the two lanes of a query combine at the end.  No
+// self exclusion.  label[q] = label_base + index of the nearest candidate (0
+// if none).  blk: the block of WAVES*32 query rows.
+template <int P, int NSTEP, int WAVES>
+__device__ void nearest_block(int64_t blk, const uint8_t* __restrict__ ops, const float* __restrict__ ninit,
+                              const int32_t* __restrict__ sexp, int n, const uint8_t* __restrict__ qops,
+                              const int32_t* __restrict__ qsexp, int nq, float qmul, int32_t* __restrict__ label,
+                              int32_t label_base) {
+    using S = Shape<P, NSTEP, 32>;
+    constexpr int RB = S::ROW_BYTES, RS = S::RS, BC = 32;
+    constexpr int NT = WAVES * 64;
+    constexpr int CHUNKS = BC * RB / 16;
+    __shared__ __align__(16) uint8_t tile[BC * RS];
+    __shared__ __align__(16) float norm[BC];
+    __shared__ int32_t tsexp[BC];
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6, h = l >> 5, ql = l & 31;
+    const int64_t qg = (blk * WAVES + w) * 32 + ql;
+    Frag<P, NSTEP> qf;
+    load_frag<P, NSTEP>(qf, qops + qg * RB + h * (RB / 2));
+    scale_query<P, NSTEP>(qf, qmul);
+    const int q_scale = P == SG_PREC_FP8 ? 127 + qsexp[qg] + 1 : 127;
+    float best = __builtin_inff();
+    int32_t bid = INT32_MAX;
+    for (int j0 = 0; j0 < n; j0 += BC) {
+        __syncthreads();
+        for (int c = tid; c < CHUNKS; c += NT) {
+            const int r = c / (RB / 16), o = c % (RB / 16);
+            *reinterpret_cast<intx4*>(&tile[r * RS + o * 16]) =
+                *reinterpret_cast<const intx4*>(ops + (int64_t)(j0 + r) * RB + o * 16);
+        }
+        if (tid < BC) {
+            norm[tid] = ninit[j0 + tid];
+            if constexpr (P == SG_PREC_FP8) tsexp[tid] = sexp[j0 + tid];
+        }
+        __syncthreads();
+        floatx16 acc;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[i] = norm[out_row(i, l)];
+        const int a_scale = P == SG_PREC_FP8 ? 127 + tsexp[ql] : 127;
+        acc = mfma_tile<P, NSTEP>(&tile[ql * RS + h * (RB / 2)], qf, acc, a_scale, q_scale);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int32_t r = j0 + out_row(i, l);
+            if (acc[i] < best || (acc[i] == best && r < bid)) {
+                best = acc[i];
+                bid = r;
+            }
+        }
+    }
+    const float ob = __builtin_bit_cast(float, lane_xor(__builtin_bit_cast(uint32_t, best), 32));
+    const int32_t oid = (int32_t)lane_xor((uint32_t)bid, 32);
+    if (ob < best || (ob == best && oid < bid)) bid = oid;
+    if (h == 0 && qg < nq) label[qg] = label_base + (bid < n ? bid : 0);
+}
+
+template <int P, int NSTEP, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void nearest_kernel(const uint8_t* __restrict__ ops,
+                                                             const float* __restrict__ ninit,
+                                                             const int32_t* __restrict__ sexp, int n,
+                                                             const uint8_t* __restrict__ qops,
+                                                             const int32_t* __restrict__ qsexp, int nq,
+                                                             float qmul, int32_t* __restrict__ label) {
+    nearest_block<P, NSTEP, WAVES>(blockIdx.x, ops, ninit, sexp, n, qops, qsexp, nq, qmul, label, 0);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 re-rank of the top-c candidates (difference form)
+// ---------------------------------------------------------------------------
+
+// Ascending bitonic sort of 64*PER keys held as v[p] in lane l (element p*64+l).
+template <int PER>
+__device__ inline void wave_sort_multi(uint64_t (&v)[PER]) {
+    const int l = lane_id();
+    constexpr int N = 64 * PER;
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 64) {
+                const int jp = j >> 6;
+#pragma unroll
+                for (int p = 0; p < PER; ++p) {
+                    int q = p ^ jp;
+                    if (q > p) {
+                        int e = p * 64 + l;
+                        bool up = (e & k) == 0;
+                        uint64_t a = v[p], b = v[q];
+                        uint64_t mn = a < b ? a : b, mx = a < b ? b : a;
+                        v[p] = up ? mn : mx;
+                        v[q] = up ? mx : mn;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int p = 0; p < PER; ++p) {
+                    const int e = p * 64 + l;
+                    v[p] = cmpx(v[p], j, ((e & k) == 0) == ((l & j) == 0));
+                }
+            }
+        }
+    }
+}
+
+__device__ inline int32_t cand_id(uint64_t key) { return key_id(key); }
+__device__ inline int32_t cand_id(int32_t id) { return id; }
+
+template <int PER, typename CT = uint64_t>
+__global__ __launch_bounds__(256) void rerank_kernel(const void* __restrict__ X, int dtype, int64_t n,
+                                                     int d, int64_t ld, int metric,
+                                                     const int64_t* __restrict__ rowmap,
+                                                     int64_t n_src, const CT* __restrict__ cand,
+                                                     int kstate,
+                                                     int c, int k, int32_t* __restrict__ nbr,
+                                                     float* __restrict__ dist,
+                                                     const int64_t* __restrict__ orow) {
+    extern __shared__ float s_q[];   // 4 waves x d
+    const int l = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 4 + w;
+    float* q = s_q + w * d;
+    if (i < n) {
+        int64_t src = rowmap ? rowmap[i] : i;
+        if (src < 0 || src >= n_src) src = -1;
+        for (int t = l; t < d; t += 64) q[t] = src >= 0 ? load_elem(X, dtype, src * ld + t) : 0.f;
+    }
+    __syncthreads();
+    if (i >= n) return;
+    uint64_t v[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        int e = p * 64 + l;
+        int32_t j = e < c ? cand_id(cand[i * kstate + e]) : SG_NONE;
+        if (j < 0 || j >= n_src || j == (rowmap ? rowmap[i] : i)) {   // absent, out of range or self
+            v[p] = EMPTY_KEY;
+            continue;
+        }
+        const int64_t jb = (int64_t)j * ld;
+        float s = 0.f;
+        if (metric == SG_L2) {
+            for (int t = 0; t < d; ++t) {
+                float u = q[t] - load_elem(X, dtype, jb + t);
+                s = fmaf(u, u, s);
+            }
+        } else {
+            for (int t = 0; t < d; ++t) s = fmaf(q[t], load_elem(X, dtype, jb + t), s);
+            s = -s;
+        }
+        v[p] = make_key(s, j);
+    }
+    wave_sort_multi<PER>(v);
+    // a repeated candidate id gives equal adjacent keys: keep the first copy
+    // (every lane runs every shuffle: element p*64+l-1 is lane l-1 of v[p],
+    // or lane 63 of v[p-1] for l == 0)
+    uint64_t prev[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const uint64_t a = shfl_u64(v[p], (l + 63) & 63);
+        const uint64_t b = shfl_u64(v[p > 0 ? p - 1 : 0], 63);
+        prev[p] = l > 0 ? a : (p > 0 ? b : ~v[0]);
+    }
+    int kept = 0;
+    const int64_t o = orow ? orow[i] : i;
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const bool keep = v[p] != EMPTY_KEY && v[p] != prev[p];
+        const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
+        const int pos = kept + __builtin_popcountll(m & ((1ull << l) - 1));
+        if (keep && pos < k) {
+            nbr[o * k + pos] = key_id(v[p]);
+            if (dist) dist[o * k + pos] = key_dist(v[p]);
+        }
+        kept += __builtin_popcountll(m);
+    }
+    for (int e = kept + l; e < k; e += 64) {
+        nbr[o * k + e] = SG_NONE;
+        if (dist) dist[o * k + e] = __builtin_inff();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+inline int ksel_for(int k) { return k <= 32 ? 32 : k <= 64 ? 64 : k <= 128 ? 128 : 256; }
+
+// Largest resident query half-row supported: the query fragment of 32 rows
+// lives in 64 VGPRs per lane at most.
+inline int nstep_for(int prec, int DP) {
+    int vec = prec == SG_PREC_FP32 ? 1 : prec == SG_PREC_FP8 ? 32 : 8;
+    return DP / 2 / vec;
+}
+
+struct Layout {
+    int64_t n_pad;
+    int DP;
+    int ksel;
+    size_t ops_bytes, norms_bytes, sexp_bytes, state_bytes, total;
+};
+
+inline Layout layout(int64_t n, int d, int k, int prec, int rerank) {
+    Layout L;
+    L.n_pad = (n + PAD_ROWS - 1) / PAD_ROWS * PAD_ROWS;
+    L.DP = padded_d(prec, d);
+    L.ksel = ksel_for(rerank > 0 ? rerank : k);
+    L.ops_bytes = (size_t)L.n_pad * L.DP * elem_bytes(prec);
+    L.norms_bytes = (size_t)L.n_pad * 4 * 2;
+    L.sexp_bytes = prec == SG_PREC_FP8 ? (size_t)L.n_pad * 4 : 0;
+    L.state_bytes = (size_t)L.n_pad * L.ksel * 8;
+    L.total = align_up(L.ops_bytes, 256) + align_up(L.norms_bytes, 256) + align_up(L.sexp_bytes, 256) +
+              align_up(L.state_bytes, 256) + 1024;
+    return L;
+}
+
+typedef void (*topk_fn)(TopkArgs);
+typedef void (*near_fn)(const uint8_t*, const float*, const int32_t*, int, const uint8_t*, const int32_t*, int,
+                        float, int32_t*);
+constexpr int NEAR_WAVES = 4;
+typedef void (*kstream_fn)(TopkArgs, int);
+
+// A distance kernel and its launch geometry.
+struct Kern {
+    topk_fn fn = nullptr;         // resident-query kernel, or
+    kstream_fn ks = nullptr;      // k-streamed FP32 kernel
+    int DP = 0;                   // padded operand row length it expects
+    int nq_block = 0;             // queries per workgroup
+    int threads = 0;
+    int tile_rows = 0;            // candidate rows per LDS tile (0: k-streamed)
+    near_fn near = nullptr;       // nearest-candidate kernel on the same operands
+};
+
+template <int P, int NSTEP, int W, int QB = 1, int CBQ = CB, int BCR = 0>
+topk_fn pick_ksel(int ksel) {
+    switch (ksel) {
+        case 32: return dist_topk_kernel<P, NSTEP, 32, W, QB, CBQ, BCR>;
+        case 64: return dist_topk_kernel<P, NSTEP, 64, W, QB, CBQ, BCR>;
+        case 128: return dist_topk_kernel<P, NSTEP, 128, W, QB, CBQ, BCR>;
+        default: return dist_topk_kernel<P, NSTEP, 256, W, QB, CBQ, BCR>;
+    }
+}
+
+template <int P, int NSTEP, int W, int QB = 1, int CBQ = CB, int BCR = 0>
+Kern resident(int ksel) {
+    Kern k;
+    k.fn = pick_ksel<P, NSTEP, W, QB, CBQ, BCR>(ksel);
+    k.DP = 2 * NSTEP * Tr<P>::VEC;
+    k.nq_block = 32 * W * QB;
+    k.threads = 64 * W;
+    k.tile_rows = Shape<P, NSTEP, BCR>::BC;
+    k.near = nearest_kernel<P, NSTEP, NEAR_WAVES>;
+    return k;
+}
+
+// The launch shapes of a precision and padded row length, default first:
+// m.template add<P, NSTEP, WAVES, QB, CBQ, BCR>() is called once per shape in
+// a fixed order, so that the single-shard and the batched drivers (and the
+// recorded autotuning choice, an index into this order) agree.  Resident-query
+// kernels exist for the half-row lengths below (8 waves while the query
+// fragment fits two waves per SIMD, 4 waves beyond); a smaller d pads up to
+// the next one.  Short rows also get 4-wave shapes with 64-row tiles (two
+// workgroups per CU) or 32-row tiles (three per CU), so that other workgroups
+// keep the MFMA and VALU units busy while one waits at its tile barrier or on
+// a merge.  Returns false if no resident kernel serves the row length (FP32
+// rows wider than 128 use the k-streamed kernel).
+template <class M>
+bool for_shapes(int prec, int d, M& m) {
+    const int need = nstep_for(prec, padded_d(prec, d));
+#define SG_ONE(PR, NS, W0) m.template add<PR, NS, W0, 1, CB, 0>()
+#define SG_THREE(PR, NS, W0)                     \
+    do {                                         \
+        m.template add<PR, NS, W0, 1, CB, 0>();  \
+        m.template add<PR, NS, 4, 1, CB, 64>();  \
+        m.template add<PR, NS, 4, 1, CB, 32>();  \
+    } while (0)
+    switch (prec) {
+        case SG_PREC_FP32:
+            if (need <= 16) SG_THREE(SG_PREC_FP32, 16, TWAVES);
+            else if (need <= 32) SG_THREE(SG_PREC_FP32, 32, TWAVES);
+            else if (need <= 48) SG_ONE(SG_PREC_FP32, 48, TWAVES);
+            else if (need <= 64) SG_ONE(SG_PREC_FP32, 64, TWAVES);
+            else return false;
+            return true;
+        case SG_PREC_F16:
+            if (need <= 2) SG_ONE(SG_PREC_F16, 2, TWAVES);
+            else if (need <= 4) SG_THREE(SG_PREC_F16, 4, TWAVES);
+            else if (need <= 6) SG_THREE(SG_PREC_F16, 6, TWAVES);
+            else if (need <= 8) SG_THREE(SG_PREC_F16, 8, TWAVES);
+            else if (need <= 12) SG_ONE(SG_PREC_F16, 12, TWAVES);
+            else if (need <= 16) SG_ONE(SG_PREC_F16, 16, TWAVES);
+            else if (need <= 24) SG_ONE(SG_PREC_F16, 24, 4);
+            else if (need <= 32) SG_ONE(SG_PREC_F16, 32, 4);
+            else if (need <= 48) SG_ONE(SG_PREC_F16, 48, 4);
+            else return false;
+            return true;
+        case SG_PREC_BF16:
+            if (need <= 2) SG_ONE(SG_PREC_BF16, 2, TWAVES);
+            else if (need <= 4) SG_THREE(SG_PREC_BF16, 4, TWAVES);
+            else if (need <= 6) SG_THREE(SG_PREC_BF16, 6, TWAVES);
+            else if (need <= 8) SG_THREE(SG_PREC_BF16, 8, TWAVES);
+            else if (need <= 12) SG_ONE(SG_PREC_BF16, 12, TWAVES);
+            else if (need <= 16) SG_ONE(SG_PREC_BF16, 16, TWAVES);
+            else if (need <= 24) SG_ONE(SG_PREC_BF16, 24, 4);
+            else if (need <= 32) SG_ONE(SG_PREC_BF16, 32, 4);
+            else if (need <= 48) SG_ONE(SG_PREC_BF16, 48, 4);
+            else return false;
+            return true;
+        default:
+            if (need <= 1) SG_THREE(SG_PREC_FP8, 1, TWAVES);
+            else if (need <= 2) SG_THREE(SG_PREC_FP8, 2, TWAVES);
+            else if (need <= 4) SG_ONE(SG_PREC_FP8, 4, TWAVES);
+            else if (need <= 8) SG_ONE(SG_PREC_FP8, 8, 4);
+            else if (need <= 16) SG_ONE(SG_PREC_FP8, 16, 4);
+            else return false;
+            return true;
+    }
+#undef SG_ONE
+#undef SG_THREE
+}
+
+struct ResidentMaker {
+    int ksel;
+    std::vector<Kern> v;
+    template <int P, int NSTEP, int W, int QB, int CBQ, int BCR>
+    void add() { v.push_back(resident<P, NSTEP, W, QB, CBQ, BCR>(ksel)); }
+};
+
+inline Kern kstream_kernel(int d, int ksel) {
+    Kern k;
+    switch (ksel) {
+        case 32: k.ks = dist_topk_kstream_kernel<32>; break;
+        case 64: k.ks = dist_topk_kstream_kernel<64>; break;
+        case 128: k.ks = dist_topk_kstream_kernel<128>; break;
+        default: k.ks = dist_topk_kstream_kernel<256>; break;
+    }
+    k.DP = (d + KS_DC - 1) / KS_DC * KS_DC;
+    k.nq_block = KS_NQ;
+    k.threads = KS_WAVES * 64;
+    return k;
+}
+
+// Every distance kernel for (prec, d, ksel), default first (empty if none).
+inline std::vector<Kern> kernel_variants(int prec, int d, int ksel) {
+    ResidentMaker m{ksel, {}};
+    if (for_shapes(prec, d, m)) return m.v;
+    if (prec == SG_PREC_FP32 && d <= 1024) return {kstream_kernel(d, ksel)};
+    return {};
+}
+
+inline Kern pick_kernel(int prec, int d, int ksel) {
+    const std::vector<Kern> v = kernel_variants(prec, d, ksel);
+    return v.empty() ? Kern() : v[0];
+}
+
+// Process-wide record of the fastest launch shape per (precision, padded row
+// length, K selection width, power-of-two bucket of n), filled by
+// sg_knn_autotune; a per-thread override serves tests.  Defined in knn.hip.
+struct TuneKey {
+    int prec, DP, ksel, nlog;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(prec, DP, ksel, nlog) < std::tie(o.prec, o.DP, o.ksel, o.nlog);
+    }
+};
+extern std::mutex g_tune_mu;
+extern std::map<TuneKey, int> g_tune;
+extern thread_local int g_force_variant;
+
+inline int nlog_of(int64_t n) {
+    int b = 0;
+    while ((int64_t(1) << (b + 1)) <= n) ++b;
+    return b;
+}
+
+inline TuneKey tune_key(int prec, int d, int ksel, int64_t n) {
+    return TuneKey{prec, padded_d(prec, d), ksel, nlog_of(n)};
+}
+
+// Index into the shape table for a call of this shape (count entries).
+int chosen_variant(int prec, int d, int ksel, int64_t n, int count);
+
+inline Layout layout_k(int64_t n, int d, int k, int prec, int rerank) {
+    Layout L = layout(n, d, k, prec, rerank);
+    Kern kk = pick_kernel(prec, d, L.ksel);
+    if (kk.DP > 0) {
+        L.DP = kk.DP;
+        L.ops_bytes = (size_t)L.n_pad * L.DP * elem_bytes(prec);
+        L.total = align_up(L.ops_bytes, 256) + align_up(L.norms_bytes, 256) +
+                  align_up(L.sexp_bytes, 256) + align_up(L.state_bytes, 256) + 1024;
+    }
+    return L;
+}
+
+inline void check_args(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int k, int prec,
+                int rerank) {
+    SG_REQUIRE(n >= 0 && n < (1ll << 31) - PAD_ROWS, "n out of range");
+    SG_REQUIRE(d >= 1 && d <= 1024, "d must be in 1..1024");
+    SG_REQUIRE(ld >= d, "ld must be >= d");
+    SG_REQUIRE(k >= 1 && k <= 256, "k must be in 1..256");
+    SG_REQUIRE(metric == SG_L2 || metric == SG_IP, "unknown metric");
+    SG_REQUIRE(dtype >= SG_F32 && dtype <= SG_U8, "unknown dtype");
+    SG_REQUIRE(prec >= SG_PREC_FP32 && prec <= SG_PREC_FP8, "unknown precision");
+    SG_REQUIRE(rerank == 0 || (rerank >= k && rerank <= 256), "rerank must be 0 or in k..256");
+    SG_REQUIRE(!(prec == SG_PREC_F16 && dtype != SG_F16 && dtype != SG_U8),
+               "SG_PREC_F16 needs F16 or U8 input");
+    SG_REQUIRE(!(prec == SG_PREC_F16 && dtype == SG_U8 && d > 128),
+               "SG_PREC_F16 is exact on U8 input only for d <= 128");
+    SG_REQUIRE(n == 0 || X != nullptr, "X is NULL");
+}
+
+
+inline int64_t pad_rows(int64_t m) { return (m + PAD_ROWS - 1) / PAD_ROWS * PAD_ROWS; }
+
+// Locality order of a whole-shard build: rows are grouped by their nearest
+// of P evenly spaced pivot rows (about 256 rows per pivot), so that a
+// workgroup's queries and the candidates it scans first are close together.
+// (Register-resident kernels only; the k-streamed FP32 kernel keeps the input
+// order.)
+constexpr int64_t LOCAL_MIN_ROWS = 4096;   // smaller shards keep their order
+inline int64_t n_pivots(int64_t n) { return std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 8192); }
+inline bool use_locality(int64_t n, bool subset) { return !subset && n >= LOCAL_MIN_ROWS; }
+
+// Extra workspace of the locality order.
+inline size_t locality_bytes(const Layout& L, int64_t n, int prec) {
+    const int64_t P = n_pivots(n), Pp = pad_rows(P);
+    return align_up((size_t)L.n_pad * 8, 256) + 2 * align_up((size_t)L.n_pad * 4, 256) +
+           3 * align_up((size_t)(P + 1) * 8, 256) + align_up(exclusive_scan_tmp_bytes(P), 256) +
+           align_up((size_t)Pp * L.DP * elem_bytes(prec), 256) + 3 * align_up((size_t)Pp * 4, 256) +
+           align_up((size_t)P * 8, 256);
+}
+
+// Workspace of one call: candidate operands + side arrays for all n rows,
+// and, for a row subset, the query operands + side arrays of its nq rows.
+inline size_t total_bytes(const Layout& L, int64_t n, int64_t nq, int prec) {
+    size_t t = L.total;
+    if (nq >= 0) {
+        const int64_t nqp = pad_rows(nq);
+        t += align_up((size_t)nqp * L.DP * elem_bytes(prec), 256) + 2 * align_up((size_t)nqp * 4, 256) +
+             align_up((size_t)nqp * 4, 256) + align_up((size_t)nqp * 8, 256);
+        // the state then covers the query rows only
+        t -= align_up(L.state_bytes, 256);
+        t += align_up((size_t)nqp * L.ksel * 8, 256);
+    } else if (use_locality(n, false)) {
+        t += locality_bytes(L, n, prec);
+    }
+    return t;
+}
+
+static __global__ void pivot_rows_kernel(int64_t* __restrict__ piv, int64_t P, int64_t n) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < P) piv[p] = p * n / P;
+}
+
+static __global__ void label_count_kernel(const int32_t* __restrict__ lab, int64_t n, int64_t P,
+                                   int64_t* __restrict__ cnt) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t c = lab[i];
+        atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[c >= 0 && c < P ? c : 0]), 1ull);
+    }
+}
+
+// Rows grouped by label; within a label the order follows the atomics (any
+// order gives the same lists: keys carry the original row ids).  Padding rows
+// n..n_pad get id -1.
+static __global__ void label_scatter_kernel(const int32_t* __restrict__ lab, int64_t n, int64_t n_pad, int64_t P,
+                                     const int64_t* __restrict__ off, int64_t* __restrict__ cur,
+                                     int64_t* __restrict__ perm, int32_t* __restrict__ pid) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (i >= n) {
+            perm[i] = -1;
+            pid[i] = -1;
+            continue;
+        }
+        const int32_t c0 = lab[i];
+        const int32_t c = c0 >= 0 && c0 < P ? c0 : 0;
+        const int64_t pos = off[c] + (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&cur[c]), 1ull);
+        perm[pos] = i;
+        pid[pos] = (int32_t)i;
+    }
+}
+
+inline void launch_topk(const Kern& kern, const TopkArgs& A, int64_t nq_pad, int DP, hipStream_t s) {
+    const unsigned grid = (unsigned)(nq_pad / kern.nq_block);
+    if (kern.fn)
+        kern.fn<<<grid, kern.threads, 0, s>>>(A);
+    else
+        kern.ks<<<grid, kern.threads, 0, s>>>(A, DP);
+    SG_LAUNCH_CHECK();
+}
+
+}  // namespace knn
+}  // namespace sg
