@@ -279,9 +279,9 @@ Plan make_plan(const int64_t* off, int S, int d, int k, int R, int prec) {
 }
 
 // Enqueue the whole build on s (no host synchronisation, no memset: valid
-// inside a stream capture).
+// inside a stream capture; the profiling events only when eager).
 void enqueue(const Plan& p, const void* X, int dtype, int d, int64_t ld, int metric, int k, int R, int prec,
-             int32_t* graphs, int32_t* knn_out, void* ws, hipStream_t s) {
+             int32_t* graphs, int32_t* knn_out, void* ws, hipStream_t s, bool eager) {
     const int64_t pad = p.sh.pad0[p.S], ppad = p.sh.ppad0[p.S], piv = p.sh.piv0[p.S];
     Carver cv(ws);
     uint8_t* ops = cv.take<uint8_t>((size_t)pad * p.DP * p.eb);
@@ -355,8 +355,10 @@ void enqueue(const Plan& p, const void* X, int dtype, int d, int64_t ld, int met
     SG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(p.kern.fn),
                                                         p.kern.threads, 0));
     const int grid = std::max(1, std::min(p.nitems, cus * std::max(per_cu, 1)));
+    if (eager) profile_record(s, true);
     p.kern.fn<<<grid, p.kern.threads, 0, s>>>(A, p.sh, counter, p.nitems);
     SG_LAUNCH_CHECK();
+    if (eager) profile_record(s, false);
 
     const sg_status pr = sg_prune(knn, p.n_all, k, R, graphs, prune_ws, p.prune_bytes, s);
     if (pr != SG_OK) throw Fail{pr};
@@ -424,7 +426,7 @@ extern "C" sg_status sg_knn_graph_batched(const void* X, sg_dtype dtype, int32_t
         if (p.n_all == 0) return;
         hipStream_t s = as_stream(stream);
         if (plan == nullptr) {
-            batch::enqueue(p, X, dtype, d, ld, metric, k, R, prec, graphs, knn, ws, s);
+            batch::enqueue(p, X, dtype, d, ld, metric, k, R, prec, graphs, knn, ws, s, true);
             return;
         }
         SG_REQUIRE(s != nullptr, "capturing a plan needs a non-default stream");
@@ -441,7 +443,7 @@ extern "C" sg_status sg_knn_graph_batched(const void* X, sg_dtype dtype, int32_t
         SG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         hipGraph_t graph = nullptr;
         try {
-            batch::enqueue(p, X, dtype, d, ld, metric, k, R, prec, graphs, knn, ws, s);
+            batch::enqueue(p, X, dtype, d, ld, metric, k, R, prec, graphs, knn, ws, s, false);
         } catch (...) {
             (void)hipStreamEndCapture(s, &graph);
             if (graph) (void)hipGraphDestroy(graph);
