@@ -87,7 +87,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--queries", type=int, default=10_000)
-    ap.add_argument("--workload", default="sift1m", choices=["sift1m", "precision", "batched"])
+    ap.add_argument("--workload", default="sift1m", choices=["sift1m", "precision", "batched", "learned"])
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy 256 MiB device to device (scale for rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
@@ -101,6 +101,8 @@ def main():
         return run_precision(args)
     if args.workload == "batched":
         return run_batched(args)
+    if args.workload == "learned":
+        return run_learned(args)
 
     import torch
 
@@ -502,6 +504,134 @@ def run_batched(args):
         "recall_at_64_vs_fp64_oracle_32_rows": rec,
     }
     plan.close()
+    print(json.dumps(line), flush=True)
+
+
+def l1_nonneg_gpu(torch, N, d, n_comp, sigma, seed, dev):
+    """N rows |mu_c + sigma * N(0, I)| (centres N(0, I), n_comp components),
+    each scaled to unit L1 norm; drawn on the GPU with a seeded generator."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    mu = torch.randn((n_comp, d), generator=g, device=dev)
+    comp = torch.randint(0, n_comp, (N,), generator=g, device=dev)
+    X = torch.empty((N, d), dtype=torch.float32, device=dev)
+    for a in range(0, N, 1 << 19):
+        b = min(N, a + (1 << 19))
+        x = (mu[comp[a:b]] + sigma * torch.randn((b - a, d), generator=g, device=dev)).abs()
+        X[a:b] = x / x.sum(dim=1, keepdim=True)
+    return X
+
+
+def run_learned(args):
+    """Learned form: N = 2M FP32 rows, d = 960, |500-component mixture, std 0.2|
+    L1-normalised, L2.  Exact K = 64 lists of 200k anchors (FP32 plain kernel)
+    train an MLP 960 -> 256 -> 64 (GELU, BF16 products, FP32 masters) for 2000
+    Adam steps of 1024 in-batch pairs; every row is projected, FP8 scores on the
+    unit projections propose 256 candidates, an exact FP32 re-rank keeps 64,
+    prune to R = 32.  A 10k-row sample judged by exact lists gates the result
+    (recall@64 >= 0.95, else the plain build is used).  Gain test on the same
+    sample: trained vs untrained net vs a random projection at c = 256."""
+    import torch
+
+    import oracle
+    import paper_2605_10135_amd as sg
+
+    dev = torch.device("cuda:0")
+    N = args.n if args.n != 1_000_000 else 2_000_000
+    d, H, E, K, R, c = 960, 256, 64, 64, 32, 256
+    n_anchor, n_gate, steps_t, B = min(200_000, N // 4), min(10_000, N // 8), 2000, 1024
+    t = time.perf_counter()
+    X = l1_nonneg_gpu(torch, N, d, 500, 0.2, 1004, dev)
+    torch.cuda.synchronize()
+    log("data %.1fs" % (time.perf_counter() - t))
+    rng = np.random.default_rng(1004)
+    perm = rng.permutation(N)
+    anchors, sample = perm[:n_anchor], perm[n_anchor:n_anchor + n_gate]
+
+    def sync_time(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+
+    # 1. training labels: exact lists of the anchors
+    t_lab, (lab, _) = sync_time(lambda: sg.sg_knn_rows(X, anchors, K, "l2", "fp32"))
+    log("labels %.2fs" % t_lab)
+    # 2. training
+    gt = torch.Generator().manual_seed(1004)
+    W1 = torch.randn((H, d), generator=gt) * (2.0 / d) ** 0.5
+    W2 = torch.randn((E, H), generator=gt) * (1.0 / H) ** 0.5
+    b1 = torch.randn(H, generator=gt) * 0.01
+    b2 = torch.randn(E, generator=gt) * 0.01
+    mu, sigma = sg.sg_mlp_stats(X, anchors)
+    mk = lambda: sg.MLP(*(t_.to(dev) for t_ in (W1, b1, W2, b2)), mu, sigma)
+    net, net0 = mk(), mk()
+    a_idx = rng.integers(0, n_anchor, size=B * steps_t)
+    pos = lab.cpu().numpy()[a_idx, rng.integers(0, K, size=B * steps_t)]
+    t_train, losses = sync_time(lambda: sg.sg_mlp_train(X, net, anchors[a_idx], pos, B, steps_t, lr=1e-3))
+    lo = losses.cpu().numpy()
+    log("train %.2fs loss %.3f -> %.3f" % (t_train, lo[:20].mean(), lo[-20:].mean()))
+
+    # 3. the learned build (timed)
+    def learned_step():
+        F = sg.sg_mlp_project(X, net)
+        nbr, _ = sg.sg_knn_graph_learned(X, F, c, K, dist=False)
+        return nbr, sg.sg_prune(nbr, R)
+    for _ in range(args.warmup):
+        learned_step()
+    t_build, (nbr, graph) = sync_time(learned_step)
+    log("learned build %.2fs" % t_build)
+
+    # 4. gate on the sample
+    t_gate, (ex, _) = sync_time(lambda: sg.sg_knn_rows(X, sample, K, "l2", "fp32"))
+    exh = ex.cpu().numpy()
+    rec = lambda lists: float(np.mean([len(set(a) & set(b)) / K for a, b in zip(lists, exh)]))
+    r_learned = rec(nbr.cpu().numpy()[sample])
+    accepted = r_learned >= 0.95
+
+    # 5. gain test: candidate recall at the same budget c (equals recall after the exact re-rank)
+    def proposals(P):
+        cand, _ = sg.sg_knn_rows(P.contiguous(), sample, c, "ip", "fp8")
+        return rec_c(cand.cpu().numpy())
+    rec_c = lambda cand: float(np.mean([len(set(a) & set(b)) / K for a, b in zip(cand, exh)]))
+    G = torch.randn((d, E), generator=torch.Generator().manual_seed(7)).to(dev)
+    gain = {"trained": proposals(sg.sg_mlp_project(X, net)),
+            "untrained": proposals(sg.sg_mlp_project(X, net0)),
+            "random_projection": proposals(torch.nn.functional.normalize(X @ G, dim=1))}
+    log("gate recall %.4f gain %s" % (r_learned, gain))
+
+    # 6. the plain build: exact FP32 kNN + prune (fallback and comparator)
+    t_plain = None
+    plain_rec = None
+    if not args.no_plain or not accepted:
+        t_plain, (pn, pg) = sync_time(lambda: (lambda nb: (nb, sg.sg_prune(nb, R)))(
+            sg.sg_knn_graph(X, K, "l2", "fp32", dist=False)[0]))
+        plain_rec = rec(pn.cpu().numpy()[sample])
+        log("plain build %.2fs" % t_plain)
+    t_end = t_lab + t_train + t_build + t_gate
+    if not accepted:
+        t_end += t_plain
+    line = {
+        "metric": "kNN-graph build vectors/sec on 1 GPU at recall@k>=0.95; chosen vs plain",
+        "value": N / t_end, "unit": "vectors/s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
+        "ms_per_step": t_end * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 MLP, fp8 scoring, f32 re-rank", "data": "synthetic",
+        "config": {"workload": "N=%d x 960 FP32 (|500-component mixture, std 0.2|, L1-normalised), L2; "
+                               "MLP 960-256-64 trained 2000 x 1024 on exact lists of %d anchors; FP8 proposals "
+                               "c=256, FP32 re-rank K=64, prune R=32; %d-row recall gate" % (N, n_anchor, n_gate)},
+        "roofline": None,
+        "cpu_baseline": None,
+        "accepted": accepted,
+        "recall_at_64_gate_sample": r_learned,
+        "gain_candidate_recall_c256": gain,
+        "seconds": {"labels": t_lab, "train": t_train, "learned_build": t_build, "gate": t_gate,
+                    "plain_build": t_plain},
+        "learned_build_only_vectors_per_s": N / t_build,
+        "plain": {"value": N / t_plain if t_plain else None, "recall_gate_sample": plain_rec},
+        "chosen_vs_plain": (t_plain / t_end) if t_plain else None,
+        "train_loss_first_last": [float(lo[:20].mean()), float(lo[-20:].mean())],
+    }
     print(json.dumps(line), flush=True)
 
 

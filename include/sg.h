@@ -217,13 +217,35 @@ sg_status sg_knn_force_variant(int32_t variant);
  *
  * For each row i of X: the ids cand[i][0..c) (SG_NONE, out-of-range ids,
  * repeats and i itself skipped) are re-scored with the FP32 difference-form
- * distance (L2: sum_t (x_it - x_jt)^2 in ascending t; IP: -sum_t x_it x_jt)
- * and the best k by (delta, id) kept, padded with SG_NONE / +inf.  Used by
- * the learned form: candidates proposed on projected rows are re-ranked on
- * the original rows.  k <= c <= 256; d <= 4096.  No workspace.
+ * distance (L2: sum_t (x_it - x_jt)^2; IP: -sum_t x_it x_jt) and the best k by
+ * (delta, id) kept, padded with SG_NONE / +inf.  Summation order: ascending t
+ * for d <= 128; for wider rows each of 64 lanes sums the elements 4l..4l+3 of
+ * every 256-element chunk in ascending order and the 64 partial sums are
+ * combined by a fixed butterfly (deterministic).  Used by the learned form:
+ * candidates proposed on projected rows are re-ranked on the original rows.
+ * k <= c <= 256; d <= 1024.  No workspace.
  * ---------------------------------------------------------------------- */
 sg_status sg_rerank(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t ld, sg_metric metric,
                     const int32_t* cand, int32_t c, int32_t k, int32_t* nbr, float* dist, void* stream);
+
+/* ------------------------------------------------------------------------
+ * sg_knn_graph_learned -- kNN graph from proposals on projected rows
+ *
+ * The learned form of the shard build: each row's candidates come from
+ * low-dimensional projections P (n x e FP32 rows, stride ldp; e.g. the unit
+ * projections of sg_mlp_project) instead of all-pairs distances on X.  Row
+ * i's c candidates are the rows j != i with the largest P_i . P_j, ranked by
+ * the FP8 key of sg_knn_graph (prec FP8, metric IP) on P; they are then
+ * re-scored on X with the FP32 difference-form distance of `metric` (as
+ * sg_rerank) and the best k by (delta, id) kept.  nbr / dist as sg_knn_graph.
+ * With c >= n - 1 every row is a candidate and the result is the exact kNN
+ * graph under the FP32 re-rank distance.  k <= c <= 256, e <= 1024,
+ * d <= 1024.
+ * ---------------------------------------------------------------------- */
+sg_status sg_knn_graph_learned_workspace_size(int64_t n, int32_t e, int32_t c, size_t* bytes);
+sg_status sg_knn_graph_learned(const void* X, sg_dtype dtype, int32_t d, int64_t ld, sg_metric metric,
+                               const float* P, int64_t n, int32_t e, int64_t ldp, int32_t c, int32_t k,
+                               int32_t* nbr, float* dist, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * sg_prune -- rank-based edge prune + reverse-edge pass to out-degree R

@@ -75,6 +75,8 @@ _SIGS = {
     "sg_knn_graph_batched": (i32, [vp, i32, i32, i64, vp, i32, i32, i32, i32, i32, vp, vp, vp, sz, vp,
                                    C.POINTER(C.c_void_p)]),
     "sg_batch_plan_destroy": (None, [vp]),
+    "sg_knn_graph_learned_workspace_size": (i32, [i64, i32, i32, psz]),
+    "sg_knn_graph_learned": (i32, [vp, i32, i32, i64, i32, vp, i64, i32, i64, i32, i32, vp, vp, vp, sz, vp]),
     "sg_mlp_workspace_size": (i32, [i32, i32, i32, i32, psz]),
     "sg_mlp_project_workspace_size": (i32, [i32, i32, i32, psz]),
     "sg_mlp_stats": (i32, [vp, i64, i32, i64, vp, i64, vp, vp, vp, sz, vp]),
@@ -353,6 +355,27 @@ def sg_rerank(X, cand, k, metric="l2", stream=None):
     dd = torch.empty((n, k), dtype=torch.float32, device=X.device)
     _check("sg_rerank", L.sg_rerank(_ptr(X), dt, n, d, ld, METRICS[metric], _ptr(cand), c, k, _ptr(nbr),
                                     _ptr(dd), _stream(stream)))
+    return nbr, dd
+
+
+def sg_knn_graph_learned(X, P, c, k, metric="l2", dist=True, stream=None, out=None):
+    """kNN graph of X from the top-c FP8 proposals on projections P, re-ranked on X:
+    (nbr int32 [n, k], dist float32 [n, k] or None)."""
+    L = lib()
+    dt, n, d, ld = _rows(X)
+    _dev_tensor(P, "P")
+    if P.dtype != torch.float32 or P.shape[0] != n or P.stride(1) != 1:
+        raise ValueError("P must be an FP32 [n, e] tensor with unit column stride")
+    e, ldp = P.shape[1], P.stride(0)
+    ws = _ws.get(_size(L.sg_knn_graph_learned_workspace_size, n, e, c), X.device, "learned")
+    if out is not None:
+        nbr, dd = out
+    else:
+        nbr = torch.empty((n, k), dtype=torch.int32, device=X.device)
+        dd = torch.empty((n, k), dtype=torch.float32, device=X.device) if dist else None
+    _check("sg_knn_graph_learned", L.sg_knn_graph_learned(_ptr(X), dt, d, ld, METRICS[metric], _ptr(P), n, e, ldp,
+                                                          c, k, _ptr(nbr), _ptr(dd), _ptr(ws), ws.numel(),
+                                                          _stream(stream)))
     return nbr, dd
 
 

@@ -173,21 +173,9 @@ void run(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int
     profile_record(s, true);
     launch_topk(kern, A, nq_pad, L.DP, s);
     profile_record(s, false);
-    if (!final_here && nbr) {   // (no lists wanted when only timing the distance kernel)
-        const size_t shm = (size_t)4 * d * sizeof(float);
-        const unsigned grid = (unsigned)cdiv(nq_rows, 4);
-        const int64_t* qrows = subset ? rows : perm;
-        if (rerank <= 64)
-            rerank_kernel<1><<<grid, 256, shm, s>>>(X, dtype, nq_rows, d, ld, metric, qrows, n, state, L.ksel,
-                                                    rerank, k, nbr, dist, perm);
-        else if (rerank <= 128)
-            rerank_kernel<2><<<grid, 256, shm, s>>>(X, dtype, nq_rows, d, ld, metric, qrows, n, state, L.ksel,
-                                                    rerank, k, nbr, dist, perm);
-        else
-            rerank_kernel<4><<<grid, 256, shm, s>>>(X, dtype, nq_rows, d, ld, metric, qrows, n, state, L.ksel,
-                                                    rerank, k, nbr, dist, perm);
-        SG_LAUNCH_CHECK();
-    }
+    if (!final_here && nbr)   // (no lists wanted when only timing the distance kernel)
+        launch_rerank<uint64_t>(X, dtype, nq_rows, d, ld, metric, subset ? rows : perm, n, state, L.ksel, rerank, k,
+                                nbr, dist, perm, s);
 }
 
 }  // namespace knn
@@ -235,25 +223,14 @@ extern "C" sg_status sg_rerank(const void* X, sg_dtype dtype, int64_t n, int32_t
                                void* stream) {
     return guarded([&] {
         SG_REQUIRE(n >= 0 && n < (1ll << 31), "n out of range");
-        SG_REQUIRE(d >= 1 && d <= 4096 && ld >= d, "bad d / ld");
+        SG_REQUIRE(d >= 1 && d <= 1024 && ld >= d, "bad d / ld (d <= 1024)");
         SG_REQUIRE(c >= 1 && c <= 256 && k >= 1 && k <= c, "need 1 <= k <= c <= 256");
         SG_REQUIRE(metric == SG_L2 || metric == SG_IP, "unknown metric");
         SG_REQUIRE(dtype >= SG_F32 && dtype <= SG_U8, "unknown dtype");
         if (n == 0) return;
         SG_REQUIRE(X && cand && nbr, "NULL pointer");
-        hipStream_t s = as_stream(stream);
-        const size_t shm = (size_t)4 * d * sizeof(float);
-        const unsigned grid = (unsigned)cdiv(n, 4);
-        if (c <= 64)
-            knn::rerank_kernel<1, int32_t><<<grid, 256, shm, s>>>(X, dtype, n, d, ld, metric, nullptr, n, cand, c, c,
-                                                                  k, nbr, dist, nullptr);
-        else if (c <= 128)
-            knn::rerank_kernel<2, int32_t><<<grid, 256, shm, s>>>(X, dtype, n, d, ld, metric, nullptr, n, cand, c, c,
-                                                                  k, nbr, dist, nullptr);
-        else
-            knn::rerank_kernel<4, int32_t><<<grid, 256, shm, s>>>(X, dtype, n, d, ld, metric, nullptr, n, cand, c, c,
-                                                                  k, nbr, dist, nullptr);
-        SG_LAUNCH_CHECK();
+        knn::launch_rerank<int32_t>(X, dtype, n, d, ld, metric, nullptr, n, cand, c, c, k, nbr, dist, nullptr,
+                                    as_stream(stream));
     });
 }
 
@@ -319,5 +296,37 @@ extern "C" sg_status sg_knn_autotune(const void* X, sg_dtype dtype, int64_t n, i
         }
         if (chosen) *chosen = best;
         for (int v = 0; v < nv && v < max_times; ++v) times_ms[v] = ms[v];
+    });
+}
+
+extern "C" sg_status sg_knn_graph_learned_workspace_size(int64_t n, int32_t e, int32_t c, size_t* bytes) {
+    return guarded([&] {
+        SG_REQUIRE(bytes != nullptr, "bytes is NULL");
+        SG_REQUIRE(n >= 0 && e >= 1 && e <= 1024 && c >= 1 && c <= 256, "bad sizes");
+        if (n == 0) {
+            *bytes = 0;
+            return;
+        }
+        const knn::Layout L = knn::layout_k(n, e, c, SG_PREC_FP8, 0);
+        *bytes = align_up((size_t)n * c * 4, 256) + knn::total_bytes(L, n, -1, SG_PREC_FP8);
+    });
+}
+
+extern "C" sg_status sg_knn_graph_learned(const void* X, sg_dtype dtype, int32_t d, int64_t ld, sg_metric metric,
+                                          const float* P, int64_t n, int32_t e, int64_t ldp, int32_t c, int32_t k,
+                                          int32_t* nbr, float* dist, void* ws, size_t ws_bytes, void* stream) {
+    return guarded([&] {
+        knn::check_args(X, dtype, n, d, ld, metric, k, SG_PREC_FP32, 0);
+        SG_REQUIRE(e >= 1 && e <= 1024 && ldp >= e, "bad e / ldp");
+        SG_REQUIRE(c >= k && c <= 256, "need k <= c <= 256");
+        SG_REQUIRE(n == 0 || (P != nullptr && nbr != nullptr), "NULL pointer");
+        if (n == 0) return;
+        const size_t cbytes = align_up((size_t)n * c * 4, 256);
+        SG_REQUIRE(ws != nullptr && ws_bytes >= cbytes, "workspace too small");
+        hipStream_t s = as_stream(stream);
+        int32_t* cand = static_cast<int32_t*>(ws);
+        knn::run(P, SG_F32, n, e, ldp, SG_IP, c, SG_PREC_FP8, 0, nullptr, -1, cand, nullptr,
+                 static_cast<char*>(ws) + cbytes, ws_bytes - cbytes, s);
+        knn::launch_rerank<int32_t>(X, dtype, n, d, ld, metric, nullptr, n, cand, c, c, k, nbr, dist, nullptr, s);
     });
 }

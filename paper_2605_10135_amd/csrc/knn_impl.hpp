@@ -1038,6 +1038,41 @@ __device__ inline void wave_sort_multi(uint64_t (&v)[PER]) {
 __device__ inline int32_t cand_id(uint64_t key) { return key_id(key); }
 __device__ inline int32_t cand_id(int32_t id) { return id; }
 
+// Sort the candidate keys of row i (element p*64 + l in lane l of v[p]),
+// drop repeated ids, write the best k to output row o (SG_NONE / +inf pad).
+template <int PER>
+__device__ void rerank_finish(uint64_t (&v)[PER], int64_t o, int k, int32_t* __restrict__ nbr,
+                              float* __restrict__ dist) {
+    const int l = lane_id();
+    wave_sort_multi<PER>(v);
+    // a repeated candidate id gives equal adjacent keys: keep the first copy
+    // (every lane runs every shuffle: element p*64+l-1 is lane l-1 of v[p],
+    // or lane 63 of v[p-1] for l == 0)
+    uint64_t prev[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const uint64_t a = shfl_u64(v[p], (l + 63) & 63);
+        const uint64_t b = shfl_u64(v[p > 0 ? p - 1 : 0], 63);
+        prev[p] = l > 0 ? a : (p > 0 ? b : ~v[0]);
+    }
+    int kept = 0;
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const bool keep = v[p] != EMPTY_KEY && v[p] != prev[p];
+        const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
+        const int pos = kept + __builtin_popcountll(m & ((1ull << l) - 1));
+        if (keep && pos < k) {
+            nbr[o * k + pos] = key_id(v[p]);
+            if (dist) dist[o * k + pos] = key_dist(v[p]);
+        }
+        kept += __builtin_popcountll(m);
+    }
+    for (int e = kept + l; e < k; e += 64) {
+        nbr[o * k + e] = SG_NONE;
+        if (dist) dist[o * k + e] = __builtin_inff();
+    }
+}
+
 template <int PER, typename CT = uint64_t>
 __global__ __launch_bounds__(256) void rerank_kernel(const void* __restrict__ X, int dtype, int64_t n,
                                                      int d, int64_t ld, int metric,
@@ -1081,34 +1116,122 @@ __global__ __launch_bounds__(256) void rerank_kernel(const void* __restrict__ X,
         }
         v[p] = make_key(s, j);
     }
-    wave_sort_multi<PER>(v);
-    // a repeated candidate id gives equal adjacent keys: keep the first copy
-    // (every lane runs every shuffle: element p*64+l-1 is lane l-1 of v[p],
-    // or lane 63 of v[p-1] for l == 0)
-    uint64_t prev[PER];
+    rerank_finish<PER>(v, orow ? orow[i] : i, k, nbr, dist);
+}
+
+// Re-rank for wide rows (d > 128): one wave per query row; each candidate row
+// is read with coalesced loads (lane l takes elements 4l..4l+3 of every
+// 256-element chunk), each lane sums its elements in ascending order and the
+// 64 partial sums are combined by a fixed butterfly, so the distance is
+// deterministic.  Four candidates are in flight at a time.
+template <int PER, typename CT, bool F32V>
+__global__ __launch_bounds__(256) void rerank_wide_kernel(const void* __restrict__ X, int dtype, int64_t n, int d,
+                                                          int64_t ld, int metric, const int64_t* __restrict__ rowmap,
+                                                          int64_t n_src, const CT* __restrict__ cand, int kstate,
+                                                          int c, int k, int32_t* __restrict__ nbr,
+                                                          float* __restrict__ dist, const int64_t* __restrict__ orow) {
+    constexpr int UMAX = 4;   // d <= 1024
+    const int l = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const int U = (d + 255) / 256;
+    int64_t self = rowmap ? rowmap[i] : i;
+    const bool have_q = self >= 0 && self < n_src;
+    auto load4 = [&](int64_t row, int u) {
+        floatx4 r = {0.f, 0.f, 0.f, 0.f};
+        const int t = u * 256 + 4 * l;
+        if (F32V) {
+            if (t < d) r = *reinterpret_cast<const floatx4*>(static_cast<const float*>(X) + row * ld + t);
+        } else {
 #pragma unroll
-    for (int p = 0; p < PER; ++p) {
-        const uint64_t a = shfl_u64(v[p], (l + 63) & 63);
-        const uint64_t b = shfl_u64(v[p > 0 ? p - 1 : 0], 63);
-        prev[p] = l > 0 ? a : (p > 0 ? b : ~v[0]);
-    }
-    int kept = 0;
-    const int64_t o = orow ? orow[i] : i;
-#pragma unroll
-    for (int p = 0; p < PER; ++p) {
-        const bool keep = v[p] != EMPTY_KEY && v[p] != prev[p];
-        const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
-        const int pos = kept + __builtin_popcountll(m & ((1ull << l) - 1));
-        if (keep && pos < k) {
-            nbr[o * k + pos] = key_id(v[p]);
-            if (dist) dist[o * k + pos] = key_dist(v[p]);
+            for (int e = 0; e < 4; ++e)
+                if (t + e < d) r[e] = load_elem(X, dtype, row * ld + t + e);
         }
-        kept += __builtin_popcountll(m);
+        return r;
+    };
+    floatx4 q[UMAX];
+#pragma unroll
+    for (int u = 0; u < UMAX; ++u) q[u] = (u < U && have_q) ? load4(self, u) : floatx4{0.f, 0.f, 0.f, 0.f};
+    uint64_t v[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) v[p] = EMPTY_KEY;
+    for (int e0 = 0; e0 < c; e0 += 4) {
+        int32_t j[4];
+        bool ok[4];
+        floatx4 x[4][UMAX];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int e = e0 + a;
+            const int32_t jj = e < c ? cand_id(cand[i * kstate + e]) : SG_NONE;
+            j[a] = __builtin_amdgcn_readfirstlane(jj);
+            ok[a] = j[a] >= 0 && j[a] < n_src && j[a] != self;
+#pragma unroll
+            for (int u = 0; u < UMAX; ++u)
+                x[a][u] = (u < U && ok[a]) ? load4(j[a], u) : floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            float sum = 0.f;
+#pragma unroll
+            for (int u = 0; u < UMAX; ++u) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (metric == SG_L2) {
+                        const float df = q[u][e] - x[a][u][e];
+                        sum = fmaf(df, df, sum);
+                    } else {
+                        sum = fmaf(q[u][e], x[a][u][e], sum);
+                    }
+                }
+            }
+#pragma unroll
+            for (int m = 32; m > 0; m >>= 1)
+                sum += __builtin_bit_cast(float, lane_xor(__builtin_bit_cast(uint32_t, sum), m));
+            if (metric != SG_L2) sum = -sum;
+            const int e = e0 + a;
+            const uint64_t key = ok[a] ? make_key(sum, j[a]) : EMPTY_KEY;
+#pragma unroll
+            for (int p = 0; p < PER; ++p)
+                if (e < c && (e >> 6) == p && l == (e & 63)) v[p] = key;
+        }
     }
-    for (int e = kept + l; e < k; e += 64) {
-        nbr[o * k + e] = SG_NONE;
-        if (dist) dist[o * k + e] = __builtin_inff();
+    rerank_finish<PER>(v, orow ? orow[i] : i, k, nbr, dist);
+}
+
+// Launch the re-rank of n rows (rerank kernel by width and candidate count).
+template <typename CT>
+inline void launch_rerank(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, const int64_t* rowmap,
+                          int64_t n_src, const CT* cand, int kstate, int c, int k, int32_t* nbr, float* dist,
+                          const int64_t* orow, hipStream_t s) {
+    const unsigned grid = (unsigned)cdiv(n, 4);
+    if (d > 128) {
+        const bool vec = dtype == SG_F32 && d % 4 == 0 && ld % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+#define SG_WIDE(PER)                                                                                                  \
+        do {                                                                                                          \
+            if (vec)                                                                                                  \
+                rerank_wide_kernel<PER, CT, true><<<grid, 256, 0, s>>>(X, dtype, n, d, ld, metric, rowmap, n_src,     \
+                                                                        cand, kstate, c, k, nbr, dist, orow);        \
+            else                                                                                                      \
+                rerank_wide_kernel<PER, CT, false><<<grid, 256, 0, s>>>(X, dtype, n, d, ld, metric, rowmap, n_src,    \
+                                                                         cand, kstate, c, k, nbr, dist, orow);       \
+        } while (0)
+        if (c <= 64) SG_WIDE(1);
+        else if (c <= 128) SG_WIDE(2);
+        else SG_WIDE(4);
+#undef SG_WIDE
+    } else {
+        const size_t shm = (size_t)4 * d * sizeof(float);
+        if (c <= 64)
+            rerank_kernel<1, CT><<<grid, 256, shm, s>>>(X, dtype, n, d, ld, metric, rowmap, n_src, cand, kstate, c, k,
+                                                        nbr, dist, orow);
+        else if (c <= 128)
+            rerank_kernel<2, CT><<<grid, 256, shm, s>>>(X, dtype, n, d, ld, metric, rowmap, n_src, cand, kstate, c, k,
+                                                        nbr, dist, orow);
+        else
+            rerank_kernel<4, CT><<<grid, 256, shm, s>>>(X, dtype, n, d, ld, metric, rowmap, n_src, cand, kstate, c, k,
+                                                        nbr, dist, orow);
     }
+    SG_LAUNCH_CHECK();
 }
 
 // ---------------------------------------------------------------------------

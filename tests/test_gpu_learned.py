@@ -121,3 +121,68 @@ def test_rerank_exact_on_integer_rows():
     onbr, odist = oracle.rerank(oracle.widen(X), cand, 32)
     np.testing.assert_array_equal(nbr.cpu().numpy(), onbr)
     np.testing.assert_array_equal(dist.cpu().numpy(), odist.astype(np.float32))
+
+
+@pytest.mark.parametrize("d,dtype", [(300, np.float32), (301, np.float32), (960, np.float32), (200, np.float16)])
+def test_rerank_wide_rows_exact_on_integer_rows(d, dtype):
+    """Rows wider than 128 use the wave-per-row re-rank (coalesced loads,
+    butterfly sum); on integer-valued rows every order is exact."""
+    rng = np.random.default_rng(d)
+    n, c = 700, 130
+    X = rng.integers(0, 8, size=(n, d)).astype(dtype)
+    cand = np.stack([rng.choice(n, size=c, replace=False) for _ in range(n)]).astype(np.int32)
+    cand[::5, 3:7] = -1
+    cand[::9, 20] = cand[::9, 21]
+    nbr, dist = sg.sg_rerank(torch.from_numpy(X).to(DEV), torch.from_numpy(cand).to(DEV), 40)
+    onbr, odist = oracle.rerank(oracle.widen(X), cand, 40)
+    np.testing.assert_array_equal(nbr.cpu().numpy(), onbr)
+    np.testing.assert_array_equal(dist.cpu().numpy(), odist.astype(np.float32))
+
+
+@pytest.mark.parametrize("d", [64, 200])
+def test_learned_graph_with_all_candidates_is_exact(d):
+    """c >= n - 1 proposes every row, so the re-ranked lists are the exact kNN."""
+    X = synthdata.sift_like_u8(n=250, d=d, seed=d, n_comp=8).astype(np.float32)
+    Xg = torch.from_numpy(X).to(DEV)
+    P = torch.nn.functional.normalize(torch.from_numpy(X[:, :48].copy()).to(DEV) + 1.0, dim=1)
+    nbr, dist = sg.sg_knn_graph_learned(Xg, P.contiguous(), 256, 32)
+    onbr, odist = oracle.knn(oracle.widen(X), 32)
+    np.testing.assert_array_equal(nbr.cpu().numpy(), onbr)
+    np.testing.assert_array_equal(dist.cpu().numpy(), odist.astype(np.float32))
+
+
+def test_learned_graph_trained_projection_gain():
+    """A short training run on clustered data: the learned lists are valid
+    (no self, distinct, ascending FP32 distances equal to FP64 ones within
+    1e-5), and at the same candidate budget the trained net recovers more exact
+    neighbours than the same net untrained and than a random projection."""
+    D, H, E, K, c = 96, 64, 16, 16, 64
+    X = synthdata.l1_nonneg(3000, d=D, seed=12, n_comp=30)
+    Xg = torch.from_numpy(X).to(DEV)
+    knn, _ = oracle.knn(oracle.widen(X), K)
+    rng = np.random.default_rng(1)
+    steps, B = 300, 256
+    anchors = rng.integers(0, 3000, size=B * steps)
+    positives = knn[anchors, rng.integers(0, K, size=B * steps)]
+    W1, b1, W2, b2 = _net(D, H, E, seed=3)
+    mu, sigma = sg.sg_mlp_stats(Xg, np.arange(3000))
+    mk = lambda: sg.MLP(*(torch.from_numpy(a).to(DEV) for a in (W1, b1, W2, b2)), mu, sigma)
+    net, net0 = mk(), mk()
+    sg.sg_mlp_train(Xg, net, anchors, positives, B, steps, lr=3e-3)
+    F = sg.sg_mlp_project(Xg, net)
+    nbr, dist = sg.sg_knn_graph_learned(Xg, F, c, K)
+    g, gd = nbr.cpu().numpy(), dist.cpu().numpy()
+    assert (g != np.arange(3000)[:, None]).all()
+    assert all(len(set(r[r >= 0])) == len(r[r >= 0]) for r in g)
+    assert (np.diff(gd, axis=1) >= 0).all()
+    d64 = oracle.pair_dist(oracle.widen(X), np.repeat(np.arange(3000)[:, None], K, 1), g, oracle.L2)
+    np.testing.assert_allclose(gd, d64, rtol=1e-5, atol=1e-9)
+    rec = lambda lists: float(np.mean([len(set(a) & set(b)) / K for a, b in zip(lists, knn)]))
+    r_trained = rec(g)
+    r_untrained = rec(sg.sg_knn_graph_learned(Xg, sg.sg_mlp_project(Xg, net0), c, K)[0].cpu().numpy())
+    G = torch.randn((D, E), generator=torch.Generator().manual_seed(4)).to(DEV)
+    Prand = torch.nn.functional.normalize(Xg @ G, dim=1).contiguous()
+    r_random = rec(sg.sg_knn_graph_learned(Xg, Prand, c, K)[0].cpu().numpy())
+    assert r_trained > 0.85, (r_trained, r_untrained, r_random)
+    assert r_trained > r_untrained + 0.05, (r_trained, r_untrained)
+    assert r_trained > r_random + 0.05, (r_trained, r_random)
