@@ -137,9 +137,16 @@ def main():
     flops = float(sum(2.0 * d * float(n) * float(n) for n in sizes))
 
     forms = [args.chosen] + ([] if args.no_plain or args.chosen == "fp32" else ["fp32"])
-    # launch-shape autotuning on the largest shard (outside the timed region)
-    big = int(np.argmax(sizes))
-    tuned = {f: sg.sg_knn_autotune(shards[big], K, "l2", f) for f in forms}
+    # launch-shape autotuning (outside the timed region): the choice is recorded
+    # per power-of-two bucket of shard size, so tune the largest shard of each
+    # bucket present
+    buckets = {}
+    for i_, n_ in enumerate(sizes):
+        b_ = int(n_).bit_length() - 1
+        if b_ not in buckets or n_ > sizes[buckets[b_]]:
+            buckets[b_] = i_
+    tuned = {f: {b_: sg.sg_knn_autotune(shards[i_], K, "l2", f) for b_, i_ in sorted(buckets.items())}
+             for f in forms}
     log("autotune %s" % tuned)
     res = {}
     graph_of = {}
@@ -265,7 +272,8 @@ def main():
                    "search_recall_at_10_L64": recall10},
         "shard_rows_per_s": ch["shard_rows_ps"],
         "stages_ms": stages,
-        "autotune": {f: {"chosen": c, "variant_ms": t} for f, (c, t) in tuned.items()},
+        "autotune": {f: {"2^%d" % b_: {"chosen": c, "variant_ms": t} for b_, (c, t) in v.items()}
+                     for f, v in tuned.items()},
         "partition_s": t_part,
         "search_s_10k_queries_L64": t_search,
     }

@@ -24,7 +24,7 @@ import os
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/knn.hip", "csrc/common.hpp")
+KERNEL_SOURCES = ("csrc/knn.hip", "csrc/knn_impl.hpp", "csrc/common.hpp")
 CALIB_BYTES = 256 << 20          # bytes read and bytes written by the calibration copy
 DIST_KERNEL = "dist_topk"
 
@@ -42,48 +42,53 @@ def _short(name: str) -> str:
     return name.split("(")[0].replace("void ", "")[:110]
 
 
-def counter_avgs(path: str, counter: str) -> dict:
-    """kernel name -> (dispatches, mean counter value per dispatch)."""
+def counter_values(path: str, counter: str) -> dict:
+    """kernel name -> list of per-dispatch counter values."""
     acc = {}
     with open(path) as f:
         for r in csv.DictReader(f):
             if r["Counter_Name"] != counter:
                 continue
-            k = _short(r["Kernel_Name"])
-            n, s = acc.get(k, (0, 0.0))
-            acc[k] = (n + 1, s + float(r["Counter_Value"]))
-    return {k: (n, s / n) for k, (n, s) in acc.items()}
+            acc.setdefault(_short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+    return acc
 
 
-def _find(avgs: dict, key: str):
-    hits = [(k, v) for k, v in avgs.items() if key in k]
-    if not hits:
-        raise SystemExit("no dispatch of a kernel matching %r" % key)
-    return max(hits, key=lambda kv: kv[1][0])
+def _dist(vals: dict):
+    """(names, dispatches, mean per dispatch) over every distance-kernel variant."""
+    names = [k for k in vals if DIST_KERNEL in k]
+    if not names:
+        raise SystemExit("no distance-kernel dispatch in the counter file")
+    allv = [v for k in names for v in vals[k]]
+    return names, len(allv), sum(allv) / len(allv)
 
 
-def _calib(avgs: dict):
-    for key in ("copyBuffer", "CopyFunctor", "copy_kernel"):
-        hits = [(k, v) for k, v in avgs.items() if key in k]
-        if hits:
-            return hits[0]
-    raise SystemExit("no calibration copy dispatch found (run the program with --calib-copy)")
+def _calib(vals: dict):
+    """The calibration copy: the largest dispatch of a copy kernel."""
+    best = None
+    for k, v in vals.items():
+        if any(key in k for key in ("copyBuffer", "CopyFunctor", "copy_kernel")):
+            m = max(v)
+            if best is None or m > best[1]:
+                best = (k, m)
+    if best is None:
+        raise SystemExit("no calibration copy dispatch found (run the program with --calib-copy)")
+    return best
 
 
 def traffic(fetch_csv: str, write_csv: str, out: str, fetch_cmd: str, write_cmd: str) -> None:
-    f, w = counter_avgs(fetch_csv, "FETCH_SIZE"), counter_avgs(write_csv, "WRITE_SIZE")
-    (ck, (_, cf)), (_, (_, cw)) = _calib(f), _calib(w)
+    f, w = counter_values(fetch_csv, "FETCH_SIZE"), counter_values(write_csv, "WRITE_SIZE")
+    (ck, cf), (_, cw) = _calib(f), _calib(w)
     ffac = CALIB_BYTES / (cf * 1024.0)
     wfac = CALIB_BYTES / (cw * 1024.0)
-    dk, (dn, dfetch) = _find(f, DIST_KERNEL)
-    _, (_, dwrite) = _find(w, DIST_KERNEL)
+    names, dn, dfetch = _dist(f)
+    _, _, dwrite = _dist(w)
     fetch_b = dfetch * 1024.0 * ffac
     write_b = dwrite * 1024.0 * wfac
     lines = [
-        "# HBM traffic of the distance kernel (rocprofv3 --pmc, per dispatch)",
-        "kernel: %s" % dk,
+        "# HBM traffic of the distance kernel (rocprofv3 --pmc, mean per dispatch over all its launch shapes)",
+        "kernels: %s" % "; ".join(names),
         "dispatches: %d" % dn,
-        "calibration_kernel: %s (%d bytes read, %d written)" % (ck, CALIB_BYTES, CALIB_BYTES),
+        "calibration_kernel: %s (largest dispatch; %d bytes read, %d written)" % (ck, CALIB_BYTES, CALIB_BYTES),
         "fetch_kib_raw: %.1f" % dfetch,
         "write_kib_raw: %.1f" % dwrite,
         "calib_fetch_kib_raw: %.1f" % cf,
