@@ -35,12 +35,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_step(sg, torch, shards, K, R, prec, graphs, nbrs, mem_d, offs, N):
+def build_step(sg, torch, shards, K, R, prec, graphs, nbrs, orders, mem_d, offs, N):
     def step():
         for s, Xs in enumerate(shards):
             nb = nbrs[s]
-            sg.sg_knn_graph(Xs, K, "l2", prec, out=(nb, None))
-            sg.sg_prune(nb, R, out=graphs[offs[s]:offs[s + 1]])
+            sg.sg_knn_graph(Xs, K, "l2", prec, out=(nb, None), order_out=orders[s])
+            sg.sg_prune(nb, R, out=graphs[offs[s]:offs[s + 1]], order=orders[s])
         return sg.sg_merge(offs, mem_d, graphs, R, N, 2 * R)
     return step
 
@@ -134,6 +134,7 @@ def main():
     total = offs[-1]
     graphs = torch.empty((total, R), dtype=torch.int32, device=dev)
     nbrs = [torch.empty((int(n), K), dtype=torch.int32, device=dev) for n in sizes]
+    orders = [torch.empty(int(n), dtype=torch.int32, device=dev) for n in sizes]
     flops = float(sum(2.0 * d * float(n) * float(n) for n in sizes))
 
     forms = [args.chosen] + ([] if args.no_plain or args.chosen == "fp32" else ["fp32"])
@@ -151,7 +152,7 @@ def main():
     res = {}
     graph_of = {}
     for form in forms:
-        step = build_step(sg, torch, shards, K, R, form, graphs, nbrs, mem, offs, N)
+        step = build_step(sg, torch, shards, K, R, form, graphs, nbrs, orders, mem, offs, N)
         sec, kms, launches, (mg, deg) = timed(torch, sg, step, args.steps, args.warmup)
         kavg = kms / max(launches, 1)
         ach = flops * args.steps / (kms / 1e3) / 1e12
@@ -165,10 +166,10 @@ def main():
     e0, e1, e2, e3 = ev(), ev(), ev(), ev()
     e0.record()
     for s, Xs in enumerate(shards):
-        sg.sg_knn_graph(Xs, K, "l2", args.chosen, out=(nbrs[s], None))
+        sg.sg_knn_graph(Xs, K, "l2", args.chosen, out=(nbrs[s], None), order_out=orders[s])
     e1.record()
     for s in range(S):
-        sg.sg_prune(nbrs[s], R, out=graphs[offs[s]:offs[s + 1]])
+        sg.sg_prune(nbrs[s], R, out=graphs[offs[s]:offs[s + 1]], order=orders[s])
     e2.record()
     mg, deg = sg.sg_merge(offs, mem, graphs, R, N, 2 * R)
     e3.record()

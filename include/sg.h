@@ -125,6 +125,10 @@ sg_status sg_partition(const void* X, sg_dtype dtype, int64_t n, int32_t d, int6
  *           are re-scored with the exact FP32 difference-form distance and
  *           the best k by (delta, id) kept.
  *  nbr    : out, n x k int32.   dist: out, n x k FP32, may be NULL.
+ *  order  : out, n int32, may be NULL: the rows in the order the build
+ *           visited them (its locality order: rows grouped by nearest of
+ *           about n/256 pivot rows; the identity for small n), a permutation
+ *           of 0..n-1 to pass to sg_prune.
  *  d      : 1..1024 for FP32 and FP8, 1..768 for FP16 / BF16 (larger d returns
  *           SG_ERR_UNSUPPORTED).  Queries are register resident up to FP32
  *           d <= 128 and 16-bit / FP8 d <= 768 / 1024; wider FP32 rows use a
@@ -134,7 +138,7 @@ sg_status sg_knn_graph_workspace_size(int64_t n, int32_t d, int32_t k, sg_prec p
                                       int32_t rerank, size_t* bytes);
 sg_status sg_knn_graph(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t ld,
                        sg_metric metric, int32_t k, sg_prec prec, int32_t rerank, int32_t* nbr,
-                       float* dist, void* ws, size_t ws_bytes, void* stream);
+                       float* dist, int32_t* order, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * sg_knn_rows -- exact (or re-ranked) kNN of listed rows against all rows
@@ -263,10 +267,15 @@ sg_status sg_knn_graph_learned(const void* X, sg_dtype dtype, int32_t d, int64_t
  *        followed by any SG_NONE padding (as sg_knn_graph writes it).
  *  K   : 1..256;  R: 1..min(K, 64).   out: n x R int32 (SG_NONE padded).
  *  Ids outside [0, n) in knn are treated as SG_NONE.
+ *  order: NULL, or a permutation of 0..n-1 (device int32) giving the order in
+ *        which rows are processed, e.g. the order sg_knn_graph returns, so
+ *        that rows processed together share neighbour lists in cache.  The
+ *        result does not depend on it; entries outside [0, n) are skipped
+ *        and rows missing from a non-permutation are left unwritten.
  * ---------------------------------------------------------------------- */
 sg_status sg_prune_workspace_size(int64_t n, int32_t K, int32_t R, size_t* bytes);
-sg_status sg_prune(const int32_t* knn, int64_t n, int32_t K, int32_t R, int32_t* out, void* ws,
-                   size_t ws_bytes, void* stream);
+sg_status sg_prune(const int32_t* knn, int64_t n, int32_t K, int32_t R, const int32_t* order,
+                   int32_t* out, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * sg_merge -- edge-union merge of shard graphs (Sec. II-A, Sec. IV step 3)

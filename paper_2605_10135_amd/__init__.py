@@ -59,11 +59,11 @@ _SIGS = {
     "sg_partition": (i32, [vp, i32, i64, i32, i64, i32, i32, i32, f32, f32, vp, vp, vp, vp, vp,
                            i64, vp, sz, vp]),
     "sg_knn_graph_workspace_size": (i32, [i64, i32, i32, i32, i32, psz]),
-    "sg_knn_graph": (i32, [vp, i32, i64, i32, i64, i32, i32, i32, i32, vp, vp, vp, sz, vp]),
+    "sg_knn_graph": (i32, [vp, i32, i64, i32, i64, i32, i32, i32, i32, vp, vp, vp, vp, sz, vp]),
     "sg_knn_rows_workspace_size": (i32, [i64, i32, i64, i32, i32, i32, psz]),
     "sg_knn_rows": (i32, [vp, i32, i64, i32, i64, i32, vp, i64, i32, i32, i32, vp, vp, vp, sz, vp]),
     "sg_prune_workspace_size": (i32, [i64, i32, i32, psz]),
-    "sg_prune": (i32, [vp, i64, i32, i32, vp, vp, sz, vp]),
+    "sg_prune": (i32, [vp, i64, i32, i32, vp, vp, vp, sz, vp]),
     "sg_merge_workspace_size": (i32, [i32, vp, i64, psz]),
     "sg_merge": (i32, [i32, vp, vp, vp, i32, i64, i32, vp, vp, vp, sz, vp]),
     "sg_search_workspace_size": (i32, [i64, i32, i64, psz]),
@@ -164,8 +164,10 @@ def _size(fn, *args):
 # calls
 # ---------------------------------------------------------------------------
 
-def sg_knn_graph(X, k, metric="l2", prec="fp32", rerank=0, dist=True, stream=None, out=None):
-    """kNN graph of one shard: (nbr int32 [n,k], dist float32 [n,k] or None)."""
+def sg_knn_graph(X, k, metric="l2", prec="fp32", rerank=0, dist=True, stream=None, out=None, order_out=None):
+    """kNN graph of one shard: (nbr int32 [n,k], dist float32 [n,k] or None).
+    order_out (optional int32 [n] tensor) receives the row order the build used,
+    to pass to sg_prune."""
     L = lib()
     dt, n, d, ld = _rows(X)
     m, p = METRICS[metric], PRECS[prec]
@@ -176,8 +178,10 @@ def sg_knn_graph(X, k, metric="l2", prec="fp32", rerank=0, dist=True, stream=Non
     else:
         nbr = torch.empty((n, k), dtype=torch.int32, device=X.device)
         dd = torch.empty((n, k), dtype=torch.float32, device=X.device) if dist else None
+    if order_out is not None and (order_out.dtype != torch.int32 or order_out.numel() < n):
+        raise ValueError("order_out must be an int32 tensor of n entries")
     _check("sg_knn_graph", L.sg_knn_graph(_ptr(X), dt, n, d, ld, m, k, p, rerank, _ptr(nbr), _ptr(dd),
-                                          _ptr(ws), ws.numel(), _stream(stream)))
+                                          _ptr(order_out), _ptr(ws), ws.numel(), _stream(stream)))
     return nbr, dd
 
 
@@ -265,8 +269,9 @@ def sg_knn_rows(X, rows, k, metric="l2", prec="fp32", rerank=0, stream=None):
     return nbr, dd
 
 
-def sg_prune(knn, R, stream=None, out=None):
-    """Detour-count prune + reverse-edge pass: int32 [n, R]."""
+def sg_prune(knn, R, stream=None, out=None, order=None):
+    """Detour-count prune + reverse-edge pass: int32 [n, R].  order: optional
+    int32 [n] row permutation to process in (e.g. from sg_knn_graph)."""
     L = lib()
     _dev_tensor(knn, "knn")
     if knn.dtype != torch.int32 or not knn.is_contiguous():
@@ -274,7 +279,12 @@ def sg_prune(knn, R, stream=None, out=None):
     n, K = knn.shape
     ws = _ws.get(_size(L.sg_prune_workspace_size, n, K, R), knn.device, "prune")
     o = out if out is not None else torch.empty((n, R), dtype=torch.int32, device=knn.device)
-    _check("sg_prune", L.sg_prune(_ptr(knn), n, K, R, _ptr(o), _ptr(ws), ws.numel(), _stream(stream)))
+    if order is not None:
+        _dev_tensor(order, "order")
+        if order.dtype != torch.int32 or order.numel() != n:
+            raise ValueError("order must be an int32 tensor of n entries")
+    _check("sg_prune", L.sg_prune(_ptr(knn), n, K, R, _ptr(order), _ptr(o), _ptr(ws), ws.numel(),
+                                  _stream(stream)))
     return o
 
 

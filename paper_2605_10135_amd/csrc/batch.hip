@@ -360,7 +360,7 @@ void enqueue(const Plan& p, const void* X, int dtype, int d, int64_t ld, int met
     SG_LAUNCH_CHECK();
     if (eager) profile_record(s, false);
 
-    const sg_status pr = sg_prune(knn, p.n_all, k, R, graphs, prune_ws, p.prune_bytes, s);
+    const sg_status pr = sg_prune(knn, p.n_all, k, R, nullptr, graphs, prune_ws, p.prune_bytes, s);
     if (pr != SG_OK) throw Fail{pr};
     const unsigned lg = (unsigned)std::min<int64_t>(cdiv(p.n_all * R, 256), 8192);
     localize_kernel<<<lg, 256, 0, s>>>(p.sh, graphs, R);

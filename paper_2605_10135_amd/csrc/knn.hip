@@ -73,7 +73,7 @@ namespace knn {
 // kNN of rows (nq >= 0: the listed rows; nq < 0: every row) against all n rows.
 void run(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int k, int prec,
          int rerank, const int64_t* rows, int64_t nq, int32_t* nbr, float* dist, void* ws,
-         size_t ws_bytes, hipStream_t s) {
+         size_t ws_bytes, hipStream_t s, int32_t* order_out = nullptr) {
     if (rerank == k) rerank = 0;
     Layout L = layout_k(n, d, k, prec, rerank);
     const Kern kern = choose_kernel(prec, d, L.ksel, n);
@@ -158,6 +158,13 @@ void run(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int
     prep_kernel<<<prep_grid, 256, 0, s>>>(X, dtype, n, d, ld, perm, n, L.n_pad, L.DP, prec, metric, ops, ninit,
                                           nout, sexp);
     SG_LAUNCH_CHECK();
+    if (order_out && !subset) {   // the rows in the order the build visits them
+        if (pid)
+            SG_HIP(hipMemcpyAsync(order_out, pid, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        else
+            iota32_kernel<<<(unsigned)std::min<int64_t>(cdiv(n, 256), 4096), 256, 0, s>>>(order_out, n);
+        SG_LAUNCH_CHECK();
+    }
     if (subset) {
         prep_kernel<<<(unsigned)cdiv(nq_pad, 4), 256, 0, s>>>(X, dtype, nq, d, ld, rows, n, nq_pad, L.DP, prec,
                                                                metric, qops, qninit, qnout, qsexp);
@@ -183,13 +190,14 @@ void run(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int
 
 extern "C" sg_status sg_knn_graph(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t ld,
                                   sg_metric metric, int32_t k, sg_prec prec, int32_t rerank,
-                                  int32_t* nbr, float* dist, void* ws, size_t ws_bytes, void* stream) {
+                                  int32_t* nbr, float* dist, int32_t* order, void* ws, size_t ws_bytes,
+                                  void* stream) {
     return guarded([&] {
         knn::check_args(X, dtype, n, d, ld, metric, k, prec, rerank);
         SG_REQUIRE(nbr != nullptr || n == 0, "nbr is NULL");
         if (n == 0) return;
         knn::run(X, dtype, n, d, ld, metric, k, prec, rerank, nullptr, -1, nbr, dist, ws, ws_bytes,
-                 as_stream(stream));
+                 as_stream(stream), order);
     });
 }
 

@@ -1499,6 +1499,11 @@ inline size_t total_bytes(const Layout& L, int64_t n, int64_t nq, int prec) {
     return t;
 }
 
+static __global__ void iota32_kernel(int32_t* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (int32_t)i;
+}
+
 static __global__ void pivot_rows_kernel(int64_t* __restrict__ piv, int64_t P, int64_t n) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p < P) piv[p] = p * n / P;

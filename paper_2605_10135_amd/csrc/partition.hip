@@ -2,7 +2,9 @@
 // (Sec. IV step 1; Sec. V-B and Algorithm 1 for one in-memory block).
 //
 //  * assign_kernel: nearest centroid per row (FP32 squared L2 against FP32
-//    copies of the FP64 centroids, ties to the lower index).
+//    copies of the FP64 centroids, summed per centroid in ascending dimension
+//    order, ties to the lower index); rows are staged through LDS, one thread
+//    per row, every centroid's sum in a register.
 //  * sum_kernel / finalize_kernel: FP64 centroid sums in a fixed-order
 //    two-level reduction.  A block owns a contiguous row range and a 128-wide
 //    slice of dimensions; thread t alone accumulates dimension t of every
@@ -56,29 +58,6 @@ __global__ void to_f32(const double* __restrict__ C, float* __restrict__ Cf, int
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gridDim.x * blockDim.x) Cf[e] = (float)C[e];
 }
 
-// squared FP32 distance of row i to every centroid, nearest (ties lower) -> label
-__global__ void assign_kernel(const void* __restrict__ X, int dtype, int64_t n, int d, int64_t ld,
-                              const float* __restrict__ Cf, int S, int32_t* __restrict__ label) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        float best = __builtin_inff();
-        int bi = 0;
-        for (int c = 0; c < S; ++c) {
-            const float* cc = Cf + (int64_t)c * d;
-            float s = 0.f;
-            for (int t = 0; t < d; ++t) {
-                float u = load_elem(X, dtype, i * ld + t) - cc[t];
-                s = fmaf(u, u, s);
-            }
-            if (s < best) {
-                best = s;
-                bi = c;
-            }
-        }
-        label[i] = bi;
-    }
-}
-
 // grid: (row blocks, dimension slices); block: DSLICE threads
 __global__ __launch_bounds__(DSLICE) void sum_kernel(const void* __restrict__ X, int dtype, int64_t n,
                                                      int d, int64_t ld, const int32_t* __restrict__ label,
@@ -119,64 +98,142 @@ __global__ void finalize_kernel(const double* __restrict__ part, const int64_t* 
     }
 }
 
-__global__ void radius_kernel(const void* __restrict__ X, int dtype, int64_t n, int d, int64_t ld,
-                              const float* __restrict__ Cf, const int32_t* __restrict__ label,
-                              unsigned int* __restrict__ radius_bits) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int c = label[i];
-        const float* cc = Cf + (int64_t)c * d;
-        float s = 0.f;
-        for (int t = 0; t < d; ++t) {
-            float u = load_elem(X, dtype, i * ld + t) - cc[t];
-            s = fmaf(u, u, s);
+// Squared FP32 distances of each thread's row (row0 + threadIdx.x) to every
+// centroid, in the order of the plain per-row loop: for each centroid,
+// s = fmaf(x_t - c_t, x_t - c_t, s) for t ascending from s = 0.  Rows are
+// staged through LDS in chunks of ADC dimensions, transposed (xs[t][row]) so
+// that the global loads are coalesced along rows and the LDS reads are
+// conflict-free; the centroids' chunk is staged beside them.
+constexpr int AR = 256;    // rows per block, one per thread
+constexpr int ADC = 32;    // dimensions per staged chunk
+
+template <int SMAX>
+struct DistSmem {
+    float xs[ADC][AR + 1];
+    float cs[SMAX][ADC];
+};
+
+template <int SMAX>
+__device__ void row_dists(DistSmem<SMAX>& sm, const void* __restrict__ X, int dtype, int64_t n, int d, int64_t ld,
+                          const float* __restrict__ Cf, int S, int64_t row0, float (&acc)[SMAX]) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < SMAX; ++c) acc[c] = 0.f;
+    for (int t0 = 0; t0 < d; t0 += ADC) {
+        const int dc = d - t0 < ADC ? d - t0 : ADC;
+        __syncthreads();
+        for (int e = tid; e < AR * ADC; e += AR) {
+            const int r = e / ADC, col = e % ADC;
+            const int64_t row = row0 + r;
+            sm.xs[col][r] = (row < n && col < dc) ? load_elem(X, dtype, row * ld + t0 + col) : 0.f;
         }
-        // non-negative floats order like their bit patterns
-        atomicMax(&radius_bits[c], __builtin_bit_cast(unsigned int, sqrtf(s)));
+        for (int e = tid; e < S * ADC; e += AR) {
+            const int c = e / ADC, col = e % ADC;
+            sm.cs[c][col] = col < dc ? Cf[(int64_t)c * d + t0 + col] : 0.f;
+        }
+        __syncthreads();
+        for (int col = 0; col < dc; ++col) {
+            const float x = sm.xs[col][tid];
+#pragma unroll
+            for (int c = 0; c < SMAX; ++c) {
+                if (c < S) {
+                    const float u = x - sm.cs[c][col];
+                    acc[c] = fmaf(u, u, acc[c]);
+                }
+            }
+        }
     }
 }
 
-// assign: n x omega shard ids (primary first, -1 padded)
-__global__ void replica_kernel(const void* __restrict__ X, int dtype, int64_t n, int d, int64_t ld,
-                               const float* __restrict__ Cf, int S, const int32_t* __restrict__ label,
-                               const unsigned int* __restrict__ radius_bits, int omega, float eps,
-                               float tau, int accept_all, int32_t* __restrict__ assign) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        float dist[MAX_S];
-        for (int c = 0; c < S; ++c) {
-            const float* cc = Cf + (int64_t)c * d;
-            float s = 0.f;
-            for (int t = 0; t < d; ++t) {
-                float u = load_elem(X, dtype, i * ld + t) - cc[t];
-                s = fmaf(u, u, s);
-            }
-            dist[c] = sqrtf(s);
+// nearest centroid (ties to the lower index) -> label
+template <int SMAX>
+__global__ __launch_bounds__(AR) void assign_kernel(const void* __restrict__ X, int dtype, int64_t n, int d,
+                                                    int64_t ld, const float* __restrict__ Cf, int S,
+                                                    int32_t* __restrict__ label) {
+    __shared__ DistSmem<SMAX> sm;
+    const int64_t row0 = (int64_t)blockIdx.x * AR;
+    float acc[SMAX];
+    row_dists<SMAX>(sm, X, dtype, n, d, ld, Cf, S, row0, acc);
+    const int64_t i = row0 + threadIdx.x;
+    if (i >= n) return;
+    float best = __builtin_inff();
+    int bi = 0;
+#pragma unroll
+    for (int c = 0; c < SMAX; ++c) {
+        if (c < S && acc[c] < best) {
+            best = acc[c];
+            bi = c;
         }
-        const int prim = label[i];
-        const float dc = dist[prim];
-        int32_t* a = assign + i * omega;
-        a[0] = prim;
-        int assigned = 1;
-        uint64_t visited = 0;
-        // visit centroids in ascending (distance, index) order
-        for (int step = 0; step < S && assigned < omega; ++step) {
-            int bi = -1;
-            float bd = 0.f;
-            for (int c = 0; c < S; ++c) {
-                if (visited >> c & 1ull) continue;
-                if (bi < 0 || dist[c] < bd) {
-                    bi = c;
-                    bd = dist[c];
-                }
-            }
-            visited |= 1ull << bi;
-            if (bi == prim) continue;
-            const float r = __builtin_bit_cast(float, radius_bits[bi]);
-            if (accept_all || (bd < eps * dc && bd < eps * tau * r)) a[assigned++] = bi;
-        }
-        for (int k = assigned; k < omega; ++k) a[k] = SG_NONE;
     }
+    label[i] = bi;
+}
+
+// radius of each cluster: largest Euclidean distance of a primary member
+// (a max of non-negative floats, ordered like their bit patterns: order-free)
+template <int SMAX>
+__global__ __launch_bounds__(AR) void radius_kernel(const void* __restrict__ X, int dtype, int64_t n, int d,
+                                                    int64_t ld, const float* __restrict__ Cf, int S,
+                                                    const int32_t* __restrict__ label,
+                                                    unsigned int* __restrict__ radius_bits) {
+    __shared__ DistSmem<SMAX> sm;
+    const int64_t row0 = (int64_t)blockIdx.x * AR;
+    float acc[SMAX];
+    row_dists<SMAX>(sm, X, dtype, n, d, ld, Cf, S, row0, acc);
+    const int64_t i = row0 + threadIdx.x;
+    if (i >= n) return;
+    const int c0 = label[i];
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < SMAX; ++c)
+        if (c == c0) s = acc[c];
+    atomicMax(&radius_bits[c0], __builtin_bit_cast(unsigned int, sqrtf(s)));
+}
+
+// assign: n x omega shard ids (primary first, -1 padded).  Algorithm 1 for
+// one block: visit centroids by ascending (distance, index); join c' when
+// d' < eps * d and d' < eps * tau * r[c'] (or always when eps = inf), until
+// omega shards.
+template <int SMAX>
+__global__ __launch_bounds__(AR) void replica_kernel(const void* __restrict__ X, int dtype, int64_t n, int d,
+                                                     int64_t ld, const float* __restrict__ Cf, int S,
+                                                     const int32_t* __restrict__ label,
+                                                     const unsigned int* __restrict__ radius_bits, int omega,
+                                                     float eps, float tau, int accept_all,
+                                                     int32_t* __restrict__ assign) {
+    __shared__ DistSmem<SMAX> sm;
+    const int64_t row0 = (int64_t)blockIdx.x * AR;
+    float dist[SMAX];
+    row_dists<SMAX>(sm, X, dtype, n, d, ld, Cf, S, row0, dist);
+    const int64_t i = row0 + threadIdx.x;
+    if (i >= n) return;
+#pragma unroll
+    for (int c = 0; c < SMAX; ++c) dist[c] = sqrtf(dist[c]);
+    const int prim = label[i];
+    float dc = 0.f;
+#pragma unroll
+    for (int c = 0; c < SMAX; ++c)
+        if (c == prim) dc = dist[c];
+    int32_t* a = assign + i * omega;
+    a[0] = prim;
+    int assigned = 1;
+    uint64_t visited = 0;
+    for (int step = 0; step < S && assigned < omega; ++step) {
+        int bi = -1;
+        float bd = 0.f;
+#pragma unroll
+        for (int c = 0; c < SMAX; ++c) {
+            if (c >= S || (visited >> c & 1ull)) continue;
+            if (bi < 0 || dist[c] < bd) {
+                bi = c;
+                bd = dist[c];
+            }
+        }
+        visited |= 1ull << bi;
+        if (bi == prim) continue;
+        const float r = __builtin_bit_cast(float, radius_bits[bi]);
+        if (accept_all || (bd < eps * dc && bd < eps * tau * r)) a[assigned++] = bi;
+    }
+    for (int k = assigned; k < omega; ++k) a[k] = SG_NONE;
 }
 
 // per (shard, block) member counts, written shard-major: cm[s * nb + b]
@@ -299,24 +356,35 @@ extern "C" sg_status sg_partition(const void* X, sg_dtype dtype, int64_t n, int3
         SG_HIP(hipMemcpyAsync(init_d, init_idx_h, S * sizeof(int64_t), hipMemcpyHostToDevice, s));
         part::init_centroids<<<cdiv((int64_t)S * d, 256), 256, 0, s>>>(X, dtype, ld, d, S, init_d, centroids);
         SG_LAUNCH_CHECK();
-        const unsigned rg = (unsigned)std::min<int64_t>(cdiv(n, 256), 65535);
+        const unsigned rg = (unsigned)cdiv(n, part::AR);
         const unsigned cg = (unsigned)cdiv((int64_t)S * d, 256);
+        const int smax = S <= 8 ? 8 : S <= 16 ? 16 : S <= 32 ? 32 : 64;
+#define SG_BY_SMAX(KERNEL, ...)                                                        \
+        do {                                                                           \
+            switch (smax) {                                                            \
+                case 8: part::KERNEL<8><<<rg, part::AR, 0, s>>>(__VA_ARGS__); break;   \
+                case 16: part::KERNEL<16><<<rg, part::AR, 0, s>>>(__VA_ARGS__); break; \
+                case 32: part::KERNEL<32><<<rg, part::AR, 0, s>>>(__VA_ARGS__); break; \
+                default: part::KERNEL<64><<<rg, part::AR, 0, s>>>(__VA_ARGS__); break; \
+            }                                                                          \
+            SG_LAUNCH_CHECK();                                                         \
+        } while (0)
         for (int it = 0; it < iters; ++it) {
             part::to_f32<<<cg, 256, 0, s>>>(centroids, Cf, S * d);
-            part::assign_kernel<<<rg, 256, 0, s>>>(X, dtype, n, d, ld, Cf, S, label);
+            SG_BY_SMAX(assign_kernel, X, dtype, n, d, ld, Cf, S, label);
             dim3 sgrid((unsigned)L.nb_sum, (unsigned)cdiv(d, part::DSLICE));
             part::sum_kernel<<<sgrid, part::DSLICE, 0, s>>>(X, dtype, n, d, ld, label, S, partial, pcount);
             part::finalize_kernel<<<cg, 256, 0, s>>>(partial, pcount, L.nb_sum, S, d, centroids);
             SG_LAUNCH_CHECK();
         }
         part::to_f32<<<cg, 256, 0, s>>>(centroids, Cf, S * d);
-        part::assign_kernel<<<rg, 256, 0, s>>>(X, dtype, n, d, ld, Cf, S, label);
+        SG_BY_SMAX(assign_kernel, X, dtype, n, d, ld, Cf, S, label);
         fill<unsigned int>(rbits, 0u, S, s);
-        part::radius_kernel<<<rg, 256, 0, s>>>(X, dtype, n, d, ld, Cf, label, rbits);
+        SG_BY_SMAX(radius_kernel, X, dtype, n, d, ld, Cf, S, label, rbits);
         const int accept_all = std::isinf(epsilon) && epsilon > 0;
-        part::replica_kernel<<<rg, 256, 0, s>>>(X, dtype, n, d, ld, Cf, S, label, rbits, omega, epsilon,
-                                                tau, accept_all, assign);
-        SG_LAUNCH_CHECK();
+        SG_BY_SMAX(replica_kernel, X, dtype, n, d, ld, Cf, S, label, rbits, omega, epsilon, tau, accept_all,
+                   assign);
+#undef SG_BY_SMAX
         part::member_count_kernel<<<(unsigned)L.nb_mem, part::MEM_BLOCK, 0, s>>>(assign, n, omega, S,
                                                                                  L.nb_mem, cm);
         SG_LAUNCH_CHECK();

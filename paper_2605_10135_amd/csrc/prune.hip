@@ -2,6 +2,10 @@
 //
 // The graph-optimisation stage of the CAGRA-style shard build (Sec. II-A,
 // Sec. IV step 2), as integer passes:
+//  * Rows are visited in the caller's order (a permutation of the rows, e.g.
+//    the locality order of the kNN build, so that concurrently processed rows
+//    share neighbour lists in L2) or in row order; the results do not depend
+//    on it.
 //  * detour_kernel: one wave per row x.  N(x) goes into a per-wave LDS hash
 //    (id -> position); the wave then streams the lists N(y_i) (one coalesced
 //    row read per i, lists stay cache resident) and counts, for every
@@ -36,15 +40,18 @@ __device__ inline int hash_find(const int32_t* hid, const int32_t* hpos, int32_t
 // KP: list entries per lane (ceil(K/64)); HS: hash slots (power of two >= 2K)
 template <int KP, int HS>
 __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__ knn, int64_t n,
-                                                     int K, int R, int32_t* __restrict__ P) {
+                                                     int K, int R, const int32_t* __restrict__ order,
+                                                     int32_t* __restrict__ P) {
     __shared__ int32_t s_hid[WAVES][HS];
     __shared__ int32_t s_hpos[WAVES][HS];
     __shared__ int32_t s_det[WAVES][64 * KP];
     __shared__ int32_t s_nx[WAVES][64 * KP];
     const int l = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int64_t x = (int64_t)blockIdx.x * WAVES + w;
-    if (x >= n) return;
+    const int64_t slot = (int64_t)blockIdx.x * WAVES + w;
+    if (slot >= n) return;
+    const int64_t x = order ? order[slot] : slot;
+    if (x < 0 || x >= n) return;
     int32_t* hid = s_hid[w];
     int32_t* hpos = s_hpos[w];
     int32_t* det = s_det[w];
@@ -160,13 +167,16 @@ __device__ inline void append_unique(int32_t v, int32_t* kl, int* kc, int cap, i
 __global__ __launch_bounds__(256) void combine_kernel(const int32_t* __restrict__ P, int64_t n, int R,
                                                       const int64_t* __restrict__ off,
                                                       const uint64_t* __restrict__ rev,
+                                                      const int32_t* __restrict__ order,
                                                       int32_t* __restrict__ F) {
     __shared__ int32_t s_kl[WAVES][64];
     __shared__ int32_t s_chunk[WAVES][64];
     const int l = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int64_t y = (int64_t)blockIdx.x * WAVES + w;
-    if (y >= n) return;
+    const int64_t slot = (int64_t)blockIdx.x * WAVES + w;
+    if (slot >= n) return;
+    const int64_t y = order ? order[slot] : slot;
+    if (y < 0 || y >= n) return;
     const int h = (R + 1) / 2;
     const int64_t b = off[y], cnt = off[y + 1] - off[y];
     // the R smallest reverse keys, ascending, one per lane
@@ -220,8 +230,8 @@ extern "C" sg_status sg_prune_workspace_size(int64_t n, int32_t K, int32_t R, si
     });
 }
 
-extern "C" sg_status sg_prune(const int32_t* knn, int64_t n, int32_t K, int32_t R, int32_t* out,
-                              void* ws, size_t ws_bytes, void* stream) {
+extern "C" sg_status sg_prune(const int32_t* knn, int64_t n, int32_t K, int32_t R, const int32_t* order,
+                              int32_t* out, void* ws, size_t ws_bytes, void* stream) {
     return guarded([&] {
         SG_REQUIRE(n >= 0 && n < (1ll << 31), "n out of range");
         SG_REQUIRE(K >= 1 && K <= 256, "K must be in 1..256");
@@ -244,11 +254,11 @@ extern "C" sg_status sg_prune(const int32_t* knn, int64_t n, int32_t K, int32_t 
 
         unsigned grid = (unsigned)cdiv(n, prune::WAVES);
         if (K <= 64)
-            prune::detour_kernel<1, 256><<<grid, 256, 0, s>>>(knn, n, K, R, P);
+            prune::detour_kernel<1, 256><<<grid, 256, 0, s>>>(knn, n, K, R, order, P);
         else if (K <= 128)
-            prune::detour_kernel<2, 512><<<grid, 256, 0, s>>>(knn, n, K, R, P);
+            prune::detour_kernel<2, 512><<<grid, 256, 0, s>>>(knn, n, K, R, order, P);
         else
-            prune::detour_kernel<4, 1024><<<grid, 256, 0, s>>>(knn, n, K, R, P);
+            prune::detour_kernel<4, 1024><<<grid, 256, 0, s>>>(knn, n, K, R, order, P);
         SG_LAUNCH_CHECK();
         fill<int64_t>(cnt, 0, n + 1, s);
         fill<int64_t>(fillc, 0, n + 1, s);
@@ -259,7 +269,7 @@ extern "C" sg_status sg_prune(const int32_t* knn, int64_t n, int32_t K, int32_t 
         exclusive_scan_i64(cnt, off, n, scan_tmp, s);
         prune::scatter_kernel<<<eg, 256, 0, s>>>(P, total, R, off, fillc, rev);
         SG_LAUNCH_CHECK();
-        prune::combine_kernel<<<grid, 256, 0, s>>>(P, n, R, off, rev, out);
+        prune::combine_kernel<<<grid, 256, 0, s>>>(P, n, R, off, rev, order, out);
         SG_LAUNCH_CHECK();
     });
 }

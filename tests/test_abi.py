@@ -38,14 +38,14 @@ def test_status_strings_and_version():
 def test_argument_errors_are_reported_without_launching():
     L = sg.lib()
     # k = 0 is rejected on the host before anything touches a device
-    rc = L.sg_knn_graph(C.c_void_p(1), 0, 10, 8, 8, 0, 0, 0, 0, C.c_void_p(1), None, None, 0, None)
+    rc = L.sg_knn_graph(C.c_void_p(1), 0, 10, 8, 8, 0, 0, 0, 0, C.c_void_p(1), None, None, None, 0, None)
     assert rc == -1
     assert b"k must be" in L.sg_last_error()
-    rc = L.sg_prune(C.c_void_p(1), 10, 8, 9, C.c_void_p(1), None, 0, None)
+    rc = L.sg_prune(C.c_void_p(1), 10, 8, 9, None, C.c_void_p(1), None, 0, None)
     assert rc == -1
     assert b"R must be" in L.sg_last_error()
     # too-small workspace
-    rc = L.sg_prune(C.c_void_p(1), 10, 8, 4, C.c_void_p(1), None, 0, None)
+    rc = L.sg_prune(C.c_void_p(1), 10, 8, 4, None, C.c_void_p(1), None, 0, None)
     assert rc == -3
     off = (C.c_int64 * 3)(0, 5, 4)
     rc = L.sg_merge(2, off, C.c_void_p(1), C.c_void_p(1), 4, 10, 8, C.c_void_p(1), C.c_void_p(1), None,

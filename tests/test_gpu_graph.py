@@ -117,3 +117,22 @@ def test_prune_merge_deterministic():
     a = _prune_gpu(knn, 16)
     b = _prune_gpu(knn, 16)
     np.testing.assert_array_equal(a, b)
+
+
+def test_knn_order_is_permutation_and_prune_order_free():
+    """sg_knn_graph's row order is a permutation (the locality order for large
+    shards); pruning in that order gives the same graph as in row order."""
+    import synthdata
+    X = synthdata.sift_like_u8(n=6000, d=32, seed=77, n_comp=40)
+    Xg = torch.from_numpy(X).to(DEV)
+    order = torch.empty(6000, dtype=torch.int32, device=DEV)
+    nbr, _ = sg.sg_knn_graph(Xg, 32, "l2", "f16", dist=False, order_out=order)
+    o = order.cpu().numpy()
+    assert np.array_equal(np.sort(o), np.arange(6000))
+    assert not np.array_equal(o, np.arange(6000))      # >= 4096 rows: reordered
+    g0 = sg.sg_prune(nbr, 16)
+    g1 = sg.sg_prune(nbr, 16, order=order)
+    assert torch.equal(g0, g1)
+    small = torch.empty(500, dtype=torch.int32, device=DEV)
+    sg.sg_knn_graph(Xg[:500], 16, "l2", "f16", dist=False, order_out=small)
+    assert np.array_equal(small.cpu().numpy(), np.arange(500))
