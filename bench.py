@@ -35,7 +35,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_step(sg, torch, shards, K, R, prec, graphs, nbrs, orders, mem_d, offs, N):
+def build_step(sg, torch, Xcat, offs, K, R, prec, graphs, knn_all, mem_d, N):
+    """One step of the headline: every shard's kNN graph and prune in one batched
+    pass (persistent distance kernel over all shards' query blocks, largest
+    shards first), then the merge over replicated vectors."""
+    def step():
+        sg.sg_knn_graph_batched(Xcat, offs, K, R, "l2", prec, out=(graphs, knn_all))
+        return sg.sg_merge(offs, mem_d, graphs, R, N, 2 * R)
+    return step
+
+
+def build_per_shard_step(sg, shards, K, R, prec, graphs, nbrs, orders, mem_d, offs, N):
+    """The same build as one distance launch and one prune per shard."""
     def step():
         for s, Xs in enumerate(shards):
             nb = nbrs[s]
@@ -131,16 +142,16 @@ def main():
     sizes = np.diff(offs)
     log("partition %.3fs sizes %s" % (t_part, sizes.tolist()))
     shards = [Xd[mem[offs[s]:offs[s + 1]].long()].contiguous() for s in range(S)]
+    Xcat = Xd[mem.long()].contiguous()      # shard rows back to back (offsets offs)
     total = offs[-1]
     graphs = torch.empty((total, R), dtype=torch.int32, device=dev)
-    nbrs = [torch.empty((int(n), K), dtype=torch.int32, device=dev) for n in sizes]
-    orders = [torch.empty(int(n), dtype=torch.int32, device=dev) for n in sizes]
+    knn_all = torch.empty((total, K), dtype=torch.int32, device=dev)
     flops = float(sum(2.0 * d * float(n) * float(n) for n in sizes))
 
     forms = [args.chosen] + ([] if args.no_plain or args.chosen == "fp32" else ["fp32"])
     # launch-shape autotuning (outside the timed region): the choice is recorded
     # per power-of-two bucket of shard size, so tune the largest shard of each
-    # bucket present
+    # bucket present (the batched pass takes the choice of its largest shard)
     buckets = {}
     for i_, n_ in enumerate(sizes):
         b_ = int(n_).bit_length() - 1
@@ -152,36 +163,45 @@ def main():
     res = {}
     graph_of = {}
     for form in forms:
-        step = build_step(sg, torch, shards, K, R, form, graphs, nbrs, orders, mem, offs, N)
+        step = build_step(sg, torch, Xcat, offs, K, R, form, graphs, knn_all, mem, N)
         sec, kms, launches, (mg, deg) = timed(torch, sg, step, args.steps, args.warmup)
         kavg = kms / max(launches, 1)
         ach = flops * args.steps / (kms / 1e3) / 1e12
         res[form] = dict(sec=sec, kernel_ms_total=kms, launches=launches, kernel_ms_avg=kavg,
                          tflops=ach, vps=N / sec, shard_rows_ps=total / sec)
-        graph_of[form] = (mg.clone(), deg.clone(), [nb.clone() for nb in nbrs[:2]])
-        log("%s: %.3f s/step, dist kernel %.3f ms avg, %.1f TFLOP/s" % (form, sec, kavg, ach))
+        graph_of[form] = (mg.clone(), deg.clone(), knn_all.clone())
+        log("%s: %.3f s/step, dist kernel %d launches, %.3f ms avg, %.1f TFLOP/s" % (
+            form, sec, launches, kavg, ach))
 
     # stage breakdown of one chosen step (outside the timed region)
     ev = lambda: torch.cuda.Event(enable_timing=True)
-    e0, e1, e2, e3 = ev(), ev(), ev(), ev()
+    e0, e1, e2 = ev(), ev(), ev()
     e0.record()
-    for s, Xs in enumerate(shards):
-        sg.sg_knn_graph(Xs, K, "l2", args.chosen, out=(nbrs[s], None), order_out=orders[s])
+    sg.sg_knn_graph_batched(Xcat, offs, K, R, "l2", args.chosen, out=(graphs, knn_all))
     e1.record()
-    for s in range(S):
-        sg.sg_prune(nbrs[s], R, out=graphs[offs[s]:offs[s + 1]], order=orders[s])
-    e2.record()
     mg, deg = sg.sg_merge(offs, mem, graphs, R, N, 2 * R)
-    e3.record()
+    e2.record()
     torch.cuda.synchronize()
-    stages = {"knn_ms": e0.elapsed_time(e1), "prune_ms": e1.elapsed_time(e2),
-              "merge_ms": e2.elapsed_time(e3)}
+    stages = {"knn_and_prune_ms": e0.elapsed_time(e1), "merge_ms": e1.elapsed_time(e2)}
+
+    # the same build with one distance launch and one prune per shard (same lists)
+    nbrs = [torch.empty((int(n), K), dtype=torch.int32, device=dev) for n in sizes]
+    orders = [torch.empty(int(n), dtype=torch.int32, device=dev) for n in sizes]
+    g1 = torch.empty_like(graphs)
+    ps = build_per_shard_step(sg, shards, K, R, args.chosen, g1, nbrs, orders, mem, offs, N)
+    ps_sec, ps_kms, ps_launches, (pmg, pdeg) = timed(torch, sg, ps, 2, 1)
+    per_shard = {"ms_per_step": ps_sec * 1e3, "dist_launches_per_step": ps_launches // 2,
+                 "dist_kernel_ms_per_step": ps_kms / 2,
+                 "graph_identical_to_batched": bool(torch.equal(torch.cat(nbrs), graph_of[args.chosen][2])
+                                                    and torch.equal(pmg, graph_of[args.chosen][0])
+                                                    and torch.equal(pdeg, graph_of[args.chosen][1]))}
+    log("per-shard launches: %.1f ms/step, identical %s" % (ps_sec * 1e3, per_shard["graph_identical_to_batched"]))
+    del nbrs, orders, g1
 
     same = None
     if "fp32" in graph_of and args.chosen != "fp32":
         a, b = graph_of[args.chosen], graph_of["fp32"]
-        same = bool(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and
-                    all(torch.equal(x, y) for x, y in zip(a[2], b[2])))
+        same = bool(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2]))
 
     # search recall@10 on held-out queries (outside the step)
     t = time.perf_counter()
@@ -210,7 +230,7 @@ def main():
     X0_64 = oracle.widen(X0)
     rows = rng.choice(X0.shape[0], size=64, replace=False)
     onbr, _ = oracle.knn(X0_64, K, rows=rows)
-    gnbr = graph_of[args.chosen][2][0].cpu().numpy()[rows]
+    gnbr = graph_of[args.chosen][2][offs[s0]:offs[s0 + 1]].cpu().numpy()[rows]
     knn_recall = float(np.mean([len(set(a) & set(b)) / K for a, b in zip(gnbr, onbr)]))
     knn_exact = bool(np.array_equal(gnbr, onbr))
 
@@ -265,14 +285,16 @@ def main():
                      "unit": "TFLOP/s", "frac": ch["tflops"] / PEAK[prec],
                      "traffic": traf["bytes"] if traf else None,
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "kernel": "dist_topk", "kernel_ms_avg": ch["kernel_ms_avg"],
-                     "flops_per_launch_avg": flops / S,
-                     "algorithmic_bytes_per_launch_avg": alg_bytes / S},
+                     "kernel": "dist_topk_batched_kernel (all 16 shards in one launch)",
+                     "kernel_ms_avg": ch["kernel_ms_avg"],
+                     "flops_per_launch_avg": flops * args.steps / max(ch["launches"], 1),
+                     "algorithmic_bytes_per_launch_avg": alg_bytes * args.steps / max(ch["launches"], 1)},
         "cpu_baseline": cpu,
         "recall": {"knn_at_64_sampled": knn_recall, "knn_rows_identical_to_oracle": knn_exact,
                    "search_recall_at_10_L64": recall10},
         "shard_rows_per_s": ch["shard_rows_ps"],
         "stages_ms": stages,
+        "per_shard_launches": per_shard,
         "autotune": {f: {"2^%d" % b_: {"chosen": c, "variant_ms": t} for b_, (c, t) in v.items()}
                      for f, v in tuned.items()},
         "partition_s": t_part,

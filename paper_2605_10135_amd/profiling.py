@@ -14,7 +14,7 @@ Two records are kept as short text files:
 Usage::
 
     python -m paper_2605_10135_amd.profiling stats  <kernel_stats.csv> <out.md> "<command>"
-    python -m paper_2605_10135_amd.profiling traffic <fetch.csv> <write.csv> <out.txt> "<fetch cmd>" "<write cmd>"
+    python -m paper_2605_10135_amd.profiling traffic <fetch.csv> <write.csv> <out.txt> "<fetch cmd>" "<write cmd>" [kernel filter]
 """
 from __future__ import annotations
 
@@ -24,9 +24,9 @@ import os
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/knn.hip", "csrc/knn_impl.hpp", "csrc/common.hpp")
+KERNEL_SOURCES = ("csrc/knn.hip", "csrc/knn_impl.hpp", "csrc/common.hpp", "csrc/batch.hip")
 CALIB_BYTES = 256 << 20          # bytes read and bytes written by the calibration copy
-DIST_KERNEL = "dist_topk"
+DIST_KERNEL = "dist_topk"        # default kernel-name filter
 
 
 def kernel_sha() -> str:
@@ -53,9 +53,10 @@ def counter_values(path: str, counter: str) -> dict:
     return acc
 
 
-def _dist(vals: dict):
-    """(names, dispatches, mean per dispatch) over every distance-kernel variant."""
-    names = [k for k in vals if DIST_KERNEL in k]
+def _dist(vals: dict, kernel: str = DIST_KERNEL):
+    """(names, dispatches, mean per dispatch) over every kernel whose name holds
+    the filter (all launch shapes of the distance kernel by default)."""
+    names = [k for k in vals if kernel in k]
     if not names:
         raise SystemExit("no distance-kernel dispatch in the counter file")
     allv = [v for k in names for v in vals[k]]
@@ -75,17 +76,19 @@ def _calib(vals: dict):
     return best
 
 
-def traffic(fetch_csv: str, write_csv: str, out: str, fetch_cmd: str, write_cmd: str) -> None:
+def traffic(fetch_csv: str, write_csv: str, out: str, fetch_cmd: str, write_cmd: str,
+            kernel: str = DIST_KERNEL) -> None:
     f, w = counter_values(fetch_csv, "FETCH_SIZE"), counter_values(write_csv, "WRITE_SIZE")
     (ck, cf), (_, cw) = _calib(f), _calib(w)
     ffac = CALIB_BYTES / (cf * 1024.0)
     wfac = CALIB_BYTES / (cw * 1024.0)
-    names, dn, dfetch = _dist(f)
-    _, _, dwrite = _dist(w)
+    names, dn, dfetch = _dist(f, kernel)
+    _, _, dwrite = _dist(w, kernel)
     fetch_b = dfetch * 1024.0 * ffac
     write_b = dwrite * 1024.0 * wfac
     lines = [
-        "# HBM traffic of the distance kernel (rocprofv3 --pmc, mean per dispatch over all its launch shapes)",
+        "# HBM traffic of the distance kernel (rocprofv3 --pmc, mean per dispatch of the kernels named below)",
+        "kernel_filter: %s" % kernel,
         "kernels: %s" % "; ".join(names),
         "dispatches: %d" % dn,
         "calibration_kernel: %s (largest dispatch; %d bytes read, %d written)" % (ck, CALIB_BYTES, CALIB_BYTES),
@@ -151,7 +154,7 @@ if __name__ == "__main__":
     if len(sys.argv) >= 5 and sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif len(sys.argv) >= 7 and sys.argv[1] == "traffic":
-        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6])
+        traffic(*sys.argv[2:8])
     else:
         print(__doc__)
         sys.exit(2)
