@@ -106,9 +106,11 @@ __global__ void count_batched_kernel(Shards sh, const int32_t* __restrict__ lab,
 // Rows of each shard grouped by label (labels of shard s follow those of
 // shard s-1, so the scan of the counts starts shard s at row0[s]).  Any order
 // within a label gives the same lists: keys carry the row ids.
+// Also writes the locality order over all rows (position -> row, positions
+// of shard s from row0[s]), the order the prune visits the rows in.
 __global__ void scatter_batched_kernel(Shards sh, const int32_t* __restrict__ lab, const int64_t* __restrict__ off,
                                        int64_t* __restrict__ cur, int64_t* __restrict__ perm,
-                                       int32_t* __restrict__ pid) {
+                                       int32_t* __restrict__ pid, int32_t* __restrict__ order) {
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < sh.pad0[sh.S];
          j += (int64_t)gridDim.x * blockDim.x) {
         const int s = shard_of(sh.pad0, sh.S, j);
@@ -120,6 +122,7 @@ __global__ void scatter_batched_kernel(Shards sh, const int32_t* __restrict__ la
         const int64_t o = pos - sh.row0[s] + sh.pad0[s];
         perm[o] = sh.row0[s] + loc;
         pid[o] = (int32_t)(sh.row0[s] + loc);
+        order[pos] = (int32_t)(sh.row0[s] + loc);
     }
 }
 
@@ -274,6 +277,7 @@ Plan make_plan(const int64_t* off, int S, int d, int k, int R, int prec) {
               + align_up((size_t)pad * p.ksel * 8, 256)               // state
               + 256                                                   // counter
               + align_up((size_t)p.n_all * k * 4, 256)                // kNN lists (when not returned)
+              + align_up((size_t)p.n_all * 4, 256)                    // locality order of the rows
               + align_up(p.prune_bytes, 256) + 1024;
     return p;
 }
@@ -304,6 +308,7 @@ void enqueue(const Plan& p, const void* X, int dtype, int d, int64_t ld, int met
     uint64_t* state = cv.take<uint64_t>((size_t)pad * p.ksel);
     unsigned int* counter = cv.take<unsigned int>(64);
     int32_t* knn_ws = cv.take<int32_t>((size_t)p.n_all * k);
+    int32_t* order = cv.take<int32_t>(p.n_all);
     void* prune_ws = cv.take<char>(p.prune_bytes);
     int32_t* knn = knn_out ? knn_out : knn_ws;
     const bool fp8 = prec == SG_PREC_FP8;
@@ -328,7 +333,7 @@ void enqueue(const Plan& p, const void* X, int dtype, int d, int64_t ld, int met
     count_batched_kernel<<<eg, 256, 0, s>>>(p.sh, lab, cnt);
     SG_LAUNCH_CHECK();
     exclusive_scan_i64(cnt, loff, piv, scan_tmp, s);
-    scatter_batched_kernel<<<eg, 256, 0, s>>>(p.sh, lab, loff, cur, perm, pid);
+    scatter_batched_kernel<<<eg, 256, 0, s>>>(p.sh, lab, loff, cur, perm, pid, order);
     SG_LAUNCH_CHECK();
     prep_kernel<<<(unsigned)cdiv(pad, 4), 256, 0, s>>>(X, dtype, pad, d, ld, perm, p.n_all, pad, p.DP, prec, metric,
                                                       ops, ninit, nout, fp8 ? sexp : nullptr);
@@ -360,7 +365,7 @@ void enqueue(const Plan& p, const void* X, int dtype, int d, int64_t ld, int met
     SG_LAUNCH_CHECK();
     if (eager) profile_record(s, false);
 
-    const sg_status pr = sg_prune(knn, p.n_all, k, R, nullptr, graphs, prune_ws, p.prune_bytes, s);
+    const sg_status pr = sg_prune(knn, p.n_all, k, R, order, graphs, prune_ws, p.prune_bytes, s);
     if (pr != SG_OK) throw Fail{pr};
     const unsigned lg = (unsigned)std::min<int64_t>(cdiv(p.n_all * R, 256), 8192);
     localize_kernel<<<lg, 256, 0, s>>>(p.sh, graphs, R);

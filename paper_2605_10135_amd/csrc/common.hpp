@@ -209,6 +209,17 @@ __device__ inline int lower_bound_u64(const uint64_t* a, int len, uint64_t v) {
 
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// Workgroups are dispatched to the 8 XCDs of the chip round robin (block b
+// on XCD b % 8), each XCD with its own L2.  This bijection of [0, G) hands
+// each XCD one contiguous range of block indices, so that blocks working on
+// neighbouring data share an L2 (any bijection gives the same results).
+constexpr int NUM_XCD = 8;
+__device__ inline int64_t xcd_contiguous(int64_t b, int64_t G) {
+    const int64_t q = G / NUM_XCD, r = G % NUM_XCD;
+    const int64_t x = b % NUM_XCD, i = b / NUM_XCD;
+    return x * q + (x < r ? x : r) + i;
+}
+
 // Grid-stride fill (used instead of hipMemsetAsync so that every clear is a
 // kernel and stays valid inside captured graphs).
 template <class T>

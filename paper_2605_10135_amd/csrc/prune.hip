@@ -3,20 +3,25 @@
 // The graph-optimisation stage of the CAGRA-style shard build (Sec. II-A,
 // Sec. IV step 2), as integer passes:
 //  * Rows are visited in the caller's order (a permutation of the rows, e.g.
-//    the locality order of the kNN build, so that concurrently processed rows
-//    share neighbour lists in L2) or in row order; the results do not depend
-//    on it.
+//    the locality order of the kNN build) or in row order, and each XCD takes
+//    one contiguous range of that order, so that the rows one L2 serves at a
+//    time are neighbours and share neighbour lists; the results do not depend
+//    on the order.
 //  * detour_kernel: one wave per row x.  N(x) goes into a per-wave LDS hash
-//    (id -> position); the wave then streams the lists N(y_i) (one coalesced
-//    row read per i, lists stay cache resident) and counts, for every
-//    position j, the i < j whose list holds y_j before position j.  Positions
-//    are ranked by (detour, j) and the first R written: P(x).
-//  * count / scatter: in-degree histogram of P, exclusive scan, scatter of the
-//    64-bit reverse keys (p << 32 | x) per target (slot order is arbitrary;
-//    the next pass sorts, so the output does not depend on it).
+//    (id -> position, one 64-bit slot per entry, at most 1/8 full for
+//    K <= 64); the wave then streams the lists N(y_i) (one coalesced row read
+//    per i, the next 16/KP lists in flight while the current ones are probed)
+//    and counts, for every position j, the i < j whose list holds y_j before
+//    position j.  Positions are ranked by (detour, j) (a wave sort of the
+//    keys) and the first R written: P(x); the in-degree histogram of P is
+//    counted as they are written.
+//  * exclusive scan of the in-degrees, scatter of the 64-bit reverse keys
+//    (p << 32 | x) per target (slot order is arbitrary; the next pass sorts,
+//    so the output does not depend on it).
 //  * combine_kernel: one wave per row y: the R smallest reverse keys (wave
 //    bitonic sort, chunked for high in-degree), then the list
-//    P(y)[0:h] ++ Rev(y) ++ P(y)[h:R] is deduplicated in order and cut at R.
+//    P(y)[0:h] ++ Rev(y) ++ P(y)[h:R] is deduplicated in order (values
+//    compared by lane broadcasts) and cut at R.
 #include "common.hpp"
 
 namespace sg {
@@ -26,37 +31,49 @@ constexpr int WAVES = 4;
 
 __device__ inline uint32_t hash_id(uint32_t v) { return v * 2654435761u; }
 
+// A row's hash table (open addressing, linear probing) maps a neighbour id to
+// its list position; each slot holds (position << 32) | id, so one 64-bit LDS
+// read answers a probe.  All ones marks an empty slot.
+constexpr uint64_t EMPTY_SLOT = ~0ull;
+
 template <int HS>
-__device__ inline int hash_find(const int32_t* hid, const int32_t* hpos, int32_t z) {
-    uint32_t hsh = hash_id((uint32_t)z) >> (32 - __builtin_ctz(HS));
-    while (true) {
-        int32_t k = hid[hsh];
-        if (k == z) return hpos[hsh];
-        if (k == SG_NONE) return -1;
-        hsh = (hsh + 1) & (HS - 1);
-    }
+__device__ inline uint32_t slot_of(int32_t z) {
+    return hash_id((uint32_t)z) >> (32 - __builtin_ctz(HS));
 }
 
-// KP: list entries per lane (ceil(K/64)); HS: hash slots (power of two >= 2K)
+// Position of id z (not SG_NONE) in the row's list, -1 if absent; v is the
+// value already read from z's first slot.
+template <int HS>
+__device__ inline int resolve(const uint64_t* h, int32_t z, uint64_t v) {
+    uint32_t s = slot_of<HS>(z);
+    while ((int32_t)(uint32_t)v != z) {
+        if (v == EMPTY_SLOT) return -1;
+        s = (s + 1) & (HS - 1);
+        v = h[s];
+    }
+    return (int)(v >> 32);
+}
+
+// KP: list entries per lane (ceil(K/64)); HS: hash slots (power of two, at
+// least 4K so that most probes end at the first slot)
+// Also counts the in-degree of every row in P (cnt, zeroed by the caller).
 template <int KP, int HS>
 __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__ knn, int64_t n,
                                                      int K, int R, const int32_t* __restrict__ order,
-                                                     int32_t* __restrict__ P) {
-    __shared__ int32_t s_hid[WAVES][HS];
-    __shared__ int32_t s_hpos[WAVES][HS];
+                                                     int32_t* __restrict__ P, int64_t* __restrict__ cnt) {
+    __shared__ uint64_t s_h[WAVES][HS];
     __shared__ int32_t s_det[WAVES][64 * KP];
     __shared__ int32_t s_nx[WAVES][64 * KP];
     const int l = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int64_t slot = (int64_t)blockIdx.x * WAVES + w;
+    const int64_t slot = xcd_contiguous(blockIdx.x, gridDim.x) * WAVES + w;
     if (slot >= n) return;
     const int64_t x = order ? order[slot] : slot;
     if (x < 0 || x >= n) return;
-    int32_t* hid = s_hid[w];
-    int32_t* hpos = s_hpos[w];
+    uint64_t* h = s_h[w];
     int32_t* det = s_det[w];
     int32_t* nx = s_nx[w];
-    for (int t = l; t < HS; t += 64) hid[t] = SG_NONE;
+    for (int t = l; t < HS; t += 64) h[t] = EMPTY_SLOT;
     int32_t y[KP];
 #pragma unroll
     for (int t = 0; t < KP; ++t) {
@@ -71,17 +88,20 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
 #pragma unroll
     for (int t = 0; t < KP; ++t) {
         if (y[t] != SG_NONE) {
-            uint32_t hsh = hash_id((uint32_t)y[t]) >> (32 - __builtin_ctz(HS));
-            while (atomicCAS(&hid[hsh], SG_NONE, y[t]) != SG_NONE) hsh = (hsh + 1) & (HS - 1);
-            hpos[hsh] = l + 64 * t;
+            const uint64_t e = ((uint64_t)(uint32_t)(l + 64 * t) << 32) | (uint32_t)y[t];
+            uint32_t s2 = slot_of<HS>(y[t]);
+            while (atomicCAS(reinterpret_cast<unsigned long long*>(&h[s2]), (unsigned long long)EMPTY_SLOT,
+                             (unsigned long long)e) != EMPTY_SLOT)
+                s2 = (s2 + 1) & (HS - 1);
         }
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    // detour counts: for each i, lane p reads z = N(y_i)[p]; 16 lists are
-    // loaded per round so that their memory latencies overlap
-    constexpr int UB = 16;
-    for (int i0 = 0; i0 < K - 1; i0 += UB) {
-        int32_t z[UB][KP];
+    // detour counts: for each i, lane p reads z = N(y_i)[p] and looks it up;
+    // UB lists per round, the next round's lists loading while this round's
+    // first probes (all issued together) are resolved
+    constexpr int UB = 16 / KP;
+    int32_t z[UB][KP], zn[UB][KP];
+    auto load = [&](int32_t (&dst)[UB][KP], int i0) {
 #pragma unroll
         for (int u = 0; u < UB; ++u) {
             const int i = i0 + u;
@@ -89,9 +109,18 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
 #pragma unroll
             for (int t = 0; t < KP; ++t) {
                 const int p = l + 64 * t;
-                z[u][t] = (yi != SG_NONE && p < K) ? knn[(int64_t)yi * K + p] : SG_NONE;
+                dst[u][t] = (yi != SG_NONE && p < K) ? knn[(int64_t)yi * K + p] : SG_NONE;
             }
         }
+    };
+    load(z, 0);
+    for (int i0 = 0; i0 < K - 1; i0 += UB) {
+        if (i0 + UB < K - 1) load(zn, i0 + UB);
+        uint64_t hv[UB][KP];
+#pragma unroll
+        for (int u = 0; u < UB; ++u)
+#pragma unroll
+            for (int t = 0; t < KP; ++t) hv[u][t] = z[u][t] != SG_NONE ? h[slot_of<HS>(z[u][t])] : EMPTY_SLOT;
 #pragma unroll
         for (int u = 0; u < UB; ++u) {
             const int i = i0 + u;
@@ -99,36 +128,45 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
             for (int t = 0; t < KP; ++t) {
                 const int p = l + 64 * t;
                 if (z[u][t] != SG_NONE) {
-                    int j = hash_find<HS>(hid, hpos, z[u][t]);
+                    const int j = resolve<HS>(h, z[u][t], hv[u][t]);
                     if (j > i && p < j) atomicAdd(&det[j], 1);
                 }
             }
         }
+#pragma unroll
+        for (int u = 0; u < UB; ++u)
+#pragma unroll
+            for (int t = 0; t < KP; ++t) z[u][t] = zn[u][t];
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     // rank valid positions by (detour, j); keys are unique
-    int nvalid = 0;
-#pragma unroll
-    for (int t = 0; t < KP; ++t) nvalid += __builtin_popcountll(__builtin_amdgcn_ballot_w64(y[t] != SG_NONE));
-#pragma unroll
-    for (int t = 0; t < KP; ++t) {
-        int j = l + 64 * t;
-        if (y[t] == SG_NONE) continue;
-        int kj = det[j] * 1024 + j;
-        int rank = 0;
-        for (int u = 0; u < K; ++u) {
-            if (nx[u] != SG_NONE && det[u] * 1024 + u < kj) ++rank;
+    if constexpr (KP == 1) {
+        uint64_t key = y[0] != SG_NONE ? ((uint64_t)(uint32_t)det[l] << 10) | (uint32_t)l : EMPTY_KEY;
+        key = wave_sort_u64(key);
+        if (l < R) {
+            const int32_t v = key == EMPTY_KEY ? SG_NONE : nx[key & 1023];
+            P[x * R + l] = v;
+            if (v != SG_NONE) atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[v]), 1ull);
         }
-        if (rank < R) P[x * R + rank] = y[t];
-    }
-    for (int r = nvalid + l; r < R; r += 64) P[x * R + r] = SG_NONE;
-}
-
-__global__ void count_kernel(const int32_t* __restrict__ P, int64_t total, int64_t* __restrict__ cnt) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        int32_t y = P[e];
-        if (y != SG_NONE) atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[y]), 1ull);   // P is ours: ids in range
+    } else {
+        int nvalid = 0;
+#pragma unroll
+        for (int t = 0; t < KP; ++t) nvalid += __builtin_popcountll(__builtin_amdgcn_ballot_w64(y[t] != SG_NONE));
+#pragma unroll
+        for (int t = 0; t < KP; ++t) {
+            int j = l + 64 * t;
+            if (y[t] == SG_NONE) continue;
+            int kj = det[j] * 1024 + j;
+            int rank = 0;
+            for (int u = 0; u < K; ++u) {
+                if (nx[u] != SG_NONE && det[u] * 1024 + u < kj) ++rank;
+            }
+            if (rank < R) {
+                P[x * R + rank] = y[t];
+                atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[y[t]]), 1ull);
+            }
+        }
+        for (int r = nvalid + l; r < R; r += 64) P[x * R + r] = SG_NONE;
     }
 }
 
@@ -146,22 +184,23 @@ __global__ void scatter_kernel(const int32_t* __restrict__ P, int64_t total, int
     }
 }
 
-// Appends the chunk's values (one per lane, SG_NONE = absent) in lane order to
-// the list kl[0..*kc), skipping values already present; stops at cap.
-__device__ inline void append_unique(int32_t v, int32_t* kl, int* kc, int cap, int32_t* chunk) {
+// Keeps, of one value per lane (SG_NONE = absent), those that neither an
+// earlier lane of the same segment nor any lane of the earlier segments
+// e0[0..n0) / e1[0..n1) holds: the in-order deduplication of a segment, by
+// broadcasting each compared value from its lane (no LDS round trips).
+__device__ inline bool first_occurrence(int32_t v, int nv, int32_t e0, int n0, int32_t e1, int n1) {
     const int l = lane_id();
-    chunk[l] = v;
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     bool keep = v != SG_NONE;
-    const int c0 = *kc;
-    for (int t = 0; t < c0 && keep; ++t) keep = kl[t] != v;
-    for (int t = 0; t < l && keep; ++t) keep = chunk[t] != v;
-    uint64_t m = __builtin_amdgcn_ballot_w64(keep);
-    int pos = c0 + __builtin_popcountll(m & ((1ull << l) - 1));
-    if (keep && pos < cap) kl[pos] = v;
-    int nc = c0 + __builtin_popcountll(m);
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    *kc = nc < cap ? nc : cap;
+    for (int t = 0; t < n0; ++t) keep &= v != __builtin_amdgcn_readlane(e0, t);
+    for (int t = 0; t < n1; ++t) keep &= v != __builtin_amdgcn_readlane(e1, t);
+    for (int t = 0; t < nv; ++t) keep &= !(t < l && v == __builtin_amdgcn_readlane(v, t));
+    return keep;
+}
+
+// Lanes below the highest lane holding a value (0 when none).
+__device__ inline int span_of(int32_t v) {
+    const uint64_t m = __builtin_amdgcn_ballot_w64(v != SG_NONE);
+    return m ? 64 - __builtin_clzll(m) : 0;
 }
 
 __global__ __launch_bounds__(256) void combine_kernel(const int32_t* __restrict__ P, int64_t n, int R,
@@ -169,11 +208,9 @@ __global__ __launch_bounds__(256) void combine_kernel(const int32_t* __restrict_
                                                       const uint64_t* __restrict__ rev,
                                                       const int32_t* __restrict__ order,
                                                       int32_t* __restrict__ F) {
-    __shared__ int32_t s_kl[WAVES][64];
-    __shared__ int32_t s_chunk[WAVES][64];
     const int l = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int64_t slot = (int64_t)blockIdx.x * WAVES + w;
+    const int64_t slot = xcd_contiguous(blockIdx.x, gridDim.x) * WAVES + w;
     if (slot >= n) return;
     const int64_t y = order ? order[slot] : slot;
     if (y < 0 || y >= n) return;
@@ -189,16 +226,32 @@ __global__ __launch_bounds__(256) void combine_kernel(const int32_t* __restrict_
         uint64_t vr = shfl_u64(v, 63 - l);
         best = wave_sort_u64(best < vr ? best : vr);
     }
-    int32_t* kl = s_kl[w];
-    int32_t* chunk = s_chunk[w];
-    int kc = 0;
-    // P(y)[0:h]
-    append_unique(l < h ? P[y * R + l] : SG_NONE, kl, &kc, R, chunk);
-    // reverse entries by (p, x)
-    if (kc < R) append_unique(best == EMPTY_KEY ? SG_NONE : (int32_t)(uint32_t)best, kl, &kc, R, chunk);
-    // P(y)[h:R]
-    if (kc < R) append_unique(l < R - h ? P[y * R + h + l] : SG_NONE, kl, &kc, R, chunk);
-    if (l < R) F[y * R + l] = l < kc ? kl[l] : SG_NONE;
+    // the sequence P(y)[0:h] ++ Rev(y) ++ P(y)[h:R], deduplicated in order
+    // and cut at R: segment A in lanes 0..h-1, B (the 64 smallest reverse
+    // keys' sources, by (p, x)) in lanes 0..63, C in lanes 0..R-h-1
+    const int32_t va = l < h ? P[y * R + l] : SG_NONE;
+    const int32_t vb = best != EMPTY_KEY ? (int32_t)(uint32_t)best : SG_NONE;
+    const int32_t vc = l < R - h ? P[y * R + h + l] : SG_NONE;
+    const int na = span_of(va), nb = span_of(vb), nc = span_of(vc);
+    const bool ka = first_occurrence(va, na, SG_NONE, 0, SG_NONE, 0);
+    const bool kb = first_occurrence(vb, nb, va, na, SG_NONE, 0);
+    const bool kc = first_occurrence(vc, nc, va, na, vb, nb);
+    const uint64_t below = (1ull << l) - 1;
+    const uint64_t ma = __builtin_amdgcn_ballot_w64(ka), mb = __builtin_amdgcn_ballot_w64(kb),
+                   mc = __builtin_amdgcn_ballot_w64(kc);
+    const int ca = __builtin_popcountll(ma), cb = __builtin_popcountll(mb), cc = __builtin_popcountll(mc);
+    int32_t* row = F + y * R;
+    if (ka) row[__builtin_popcountll(ma & below)] = va;              // ca <= h <= R
+    if (kb) {
+        const int pos = ca + __builtin_popcountll(mb & below);
+        if (pos < R) row[pos] = vb;
+    }
+    if (kc) {
+        const int pos = ca + cb + __builtin_popcountll(mc & below);
+        if (pos < R) row[pos] = vc;
+    }
+    const int total = ca + cb + cc;
+    if (l >= total && l < R) row[l] = SG_NONE;
 }
 
 struct Layout {
@@ -253,19 +306,17 @@ extern "C" sg_status sg_prune(const int32_t* knn, int64_t n, int32_t K, int32_t 
         void* scan_tmp = cv.take<char>(exclusive_scan_tmp_bytes(n));
 
         unsigned grid = (unsigned)cdiv(n, prune::WAVES);
-        if (K <= 64)
-            prune::detour_kernel<1, 256><<<grid, 256, 0, s>>>(knn, n, K, R, order, P);
-        else if (K <= 128)
-            prune::detour_kernel<2, 512><<<grid, 256, 0, s>>>(knn, n, K, R, order, P);
-        else
-            prune::detour_kernel<4, 1024><<<grid, 256, 0, s>>>(knn, n, K, R, order, P);
-        SG_LAUNCH_CHECK();
         fill<int64_t>(cnt, 0, n + 1, s);
         fill<int64_t>(fillc, 0, n + 1, s);
+        if (K <= 64)
+            prune::detour_kernel<1, 512><<<grid, 256, 0, s>>>(knn, n, K, R, order, P, cnt);
+        else if (K <= 128)
+            prune::detour_kernel<2, 1024><<<grid, 256, 0, s>>>(knn, n, K, R, order, P, cnt);
+        else
+            prune::detour_kernel<4, 1024><<<grid, 256, 0, s>>>(knn, n, K, R, order, P, cnt);
+        SG_LAUNCH_CHECK();
         int64_t total = n * (int64_t)R;
         unsigned eg = (unsigned)std::min<int64_t>(cdiv(total, 256), 8192);
-        prune::count_kernel<<<eg, 256, 0, s>>>(P, total, cnt);
-        SG_LAUNCH_CHECK();
         exclusive_scan_i64(cnt, off, n, scan_tmp, s);
         prune::scatter_kernel<<<eg, 256, 0, s>>>(P, total, R, off, fillc, rev);
         SG_LAUNCH_CHECK();
