@@ -29,40 +29,33 @@ namespace prune {
 
 constexpr int WAVES = 4;
 
-__device__ inline uint32_t hash_id(uint32_t v) { return v * 2654435761u; }
-
-// A row's hash table (open addressing, linear probing) maps a neighbour id to
-// its list position; each slot holds (position << 32) | id, so one 64-bit LDS
-// read answers a probe.  All ones marks an empty slot.
+// A row's neighbour table, id -> list position, by cuckoo hashing over two
+// tables of CT slots (together one eighth full): every id sits in T0[h0(id)]
+// or in T1[h1(id)], so a lookup is two independent 64-bit LDS reads with no
+// probe loop.  A slot holds (position << 32) | id; all ones marks an empty
+// slot (its id field is SG_NONE, whose position field, -1, never counts).
 constexpr uint64_t EMPTY_SLOT = ~0ull;
 
-template <int HS>
-__device__ inline uint32_t slot_of(int32_t z) {
-    return hash_id((uint32_t)z) >> (32 - __builtin_ctz(HS));
+// The low 24 bits of the id with the high bits folded in; the two hashes are
+// bits of two 24-bit products (one full-rate multiply each).
+__device__ inline uint32_t mix_id(int32_t z) {
+    const uint32_t u = (uint32_t)z;
+    return (u ^ (u >> 15)) & 0xFFFFFFu;
 }
+template <int CT>
+__device__ inline uint32_t cuckoo_h0(uint32_t m) { return ((m * 0x9E3779u) >> 8) & (CT - 1); }
+template <int CT>
+__device__ inline uint32_t cuckoo_h1(uint32_t m) { return ((m * 0x85EBCBu) >> 16) & (CT - 1); }
 
-// Position of id z (not SG_NONE) in the row's list, -1 if absent; v is the
-// value already read from z's first slot.
-template <int HS>
-__device__ inline int resolve(const uint64_t* h, int32_t z, uint64_t v) {
-    uint32_t s = slot_of<HS>(z);
-    while ((int32_t)(uint32_t)v != z) {
-        if (v == EMPTY_SLOT) return -1;
-        s = (s + 1) & (HS - 1);
-        v = h[s];
-    }
-    return (int)(v >> 32);
-}
-
-// KP: list entries per lane (ceil(K/64)); HS: hash slots (power of two, at
-// least 4K so that most probes end at the first slot)
-// Also counts the in-degree of every row in P (cnt, zeroed by the caller).
-template <int KP, int HS>
+// KP: list entries per lane (ceil(K/64)); CT: slots per cuckoo table (power of
+// two, 4 * 64 * KP).  Also counts the in-degree of every row in P (cnt,
+// zeroed by the caller).
+template <int KP, int CT>
 __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__ knn, int64_t n,
                                                      int K, int R, const int32_t* __restrict__ order,
                                                      int32_t* __restrict__ P, int64_t* __restrict__ cnt) {
-    __shared__ uint64_t s_h[WAVES][HS];
-    __shared__ int32_t s_det[WAVES][64 * KP];
+    __shared__ uint64_t s_t[WAVES][2 * CT];
+    __shared__ int32_t s_det[WAVES][64 * KP + 64];   // + one discard slot per lane
     __shared__ int32_t s_nx[WAVES][64 * KP];
     const int l = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
@@ -70,10 +63,11 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
     if (slot >= n) return;
     const int64_t x = order ? order[slot] : slot;
     if (x < 0 || x >= n) return;
-    uint64_t* h = s_h[w];
+    uint64_t* T0 = s_t[w];
+    uint64_t* T1 = s_t[w] + CT;
     int32_t* det = s_det[w];
     int32_t* nx = s_nx[w];
-    for (int t = l; t < HS; t += 64) h[t] = EMPTY_SLOT;
+    for (int t = l; t < 2 * CT; t += 64) T0[t] = EMPTY_SLOT;
     int32_t y[KP];
 #pragma unroll
     for (int t = 0; t < KP; ++t) {
@@ -84,59 +78,91 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
         det[j] = 0;
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    // insert id -> position (ids of a row are distinct)
+    // insert (ids of a row are distinct): every lane carries an entry until it
+    // lands in an empty slot, evicting the occupant to its other table
+    bool failed = false;
 #pragma unroll
     for (int t = 0; t < KP; ++t) {
-        if (y[t] != SG_NONE) {
-            const uint64_t e = ((uint64_t)(uint32_t)(l + 64 * t) << 32) | (uint32_t)y[t];
-            uint32_t s2 = slot_of<HS>(y[t]);
-            while (atomicCAS(reinterpret_cast<unsigned long long*>(&h[s2]), (unsigned long long)EMPTY_SLOT,
-                             (unsigned long long)e) != EMPTY_SLOT)
-                s2 = (s2 + 1) & (HS - 1);
+        bool active = y[t] != SG_NONE;
+        uint64_t e = ((uint64_t)(uint32_t)(l + 64 * t) << 32) | (uint32_t)y[t];
+        int tb = 0;
+        for (int it = 0; it < 128 && __builtin_amdgcn_ballot_w64(active); ++it) {
+            if (active) {
+                const uint32_t m = mix_id((int32_t)(uint32_t)e);
+                unsigned long long* a = reinterpret_cast<unsigned long long*>(
+                    tb ? &T1[cuckoo_h1<CT>(m)] : &T0[cuckoo_h0<CT>(m)]);
+                const uint64_t old = atomicExch(a, (unsigned long long)e);
+                if (old == EMPTY_SLOT) {
+                    active = false;
+                } else {
+                    e = old;        // the evicted entry moves to its slot in the other table
+                    tb ^= 1;
+                }
+            }
         }
+        failed |= __builtin_amdgcn_ballot_w64(active) != 0;
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     // detour counts: for each i, lane p reads z = N(y_i)[p] and looks it up;
     // UB lists per round, the next round's lists loading while this round's
-    // first probes (all issued together) are resolved
+    // are probed
     constexpr int UB = 16 / KP;
-    int32_t z[UB][KP], zn[UB][KP];
+    int32_t zA[UB][KP], zB[UB][KP];
     auto load = [&](int32_t (&dst)[UB][KP], int i0) {
 #pragma unroll
         for (int u = 0; u < UB; ++u) {
             const int i = i0 + u;
-            const int32_t yi = i < K - 1 ? nx[i] : SG_NONE;
+            const int32_t yi = __builtin_amdgcn_readfirstlane(i < K - 1 ? nx[i] : SG_NONE);
+            const int32_t* row = knn + (int64_t)(yi < 0 ? 0 : yi) * K;
 #pragma unroll
             for (int t = 0; t < KP; ++t) {
                 const int p = l + 64 * t;
-                dst[u][t] = (yi != SG_NONE && p < K) ? knn[(int64_t)yi * K + p] : SG_NONE;
+                dst[u][t] = (yi != SG_NONE && p < K) ? row[p] : SG_NONE;
             }
         }
     };
-    load(z, 0);
-    for (int i0 = 0; i0 < K - 1; i0 += UB) {
-        if (i0 + UB < K - 1) load(zn, i0 + UB);
-        uint64_t hv[UB][KP];
+    // count the detour of position j via i: i < j and y_j before position j
+    // in N(y_i) (other lanes add to their discard slot)
+    auto count = [&](int j, int i, int p) { atomicAdd(&det[(j > i && p < j) ? j : 64 * KP + l], 1); };
+    auto probe = [&](const int32_t (&z)[UB][KP], int i0) {
+        uint64_t v0[UB][KP], v1[UB][KP];
 #pragma unroll
         for (int u = 0; u < UB; ++u)
-#pragma unroll
-            for (int t = 0; t < KP; ++t) hv[u][t] = z[u][t] != SG_NONE ? h[slot_of<HS>(z[u][t])] : EMPTY_SLOT;
-#pragma unroll
-        for (int u = 0; u < UB; ++u) {
-            const int i = i0 + u;
 #pragma unroll
             for (int t = 0; t < KP; ++t) {
-                const int p = l + 64 * t;
-                if (z[u][t] != SG_NONE) {
-                    const int j = resolve<HS>(h, z[u][t], hv[u][t]);
-                    if (j > i && p < j) atomicAdd(&det[j], 1);
-                }
+                const uint32_t m = mix_id(z[u][t]);
+                v0[u][t] = T0[cuckoo_h0<CT>(m)];
+                v1[u][t] = T1[cuckoo_h1<CT>(m)];
             }
-        }
 #pragma unroll
         for (int u = 0; u < UB; ++u)
 #pragma unroll
-            for (int t = 0; t < KP; ++t) z[u][t] = zn[u][t];
+            for (int t = 0; t < KP; ++t) {
+                const int32_t zz = z[u][t];
+                const uint64_t a = v0[u][t], b = v1[u][t];
+                const int j = (int32_t)(uint32_t)a == zz ? (int)(a >> 32) : (int32_t)(uint32_t)b == zz ? (int)(b >> 32) : -1;
+                count(j, i0 + u, l + 64 * t);
+            }
+    };
+    // a row whose insertion did not settle (never for distinct ids in
+    // practice) finds positions by comparing with every entry
+    auto probe_scan = [&](const int32_t (&z)[UB][KP], int i0) {
+        for (int u = 0; u < UB; ++u)
+#pragma unroll
+            for (int t = 0; t < KP; ++t) {
+                int j = -1;
+                for (int v = K - 1; v >= 0; --v)
+                    if (z[u][t] != SG_NONE && nx[v] == z[u][t]) j = v;
+                count(j, i0 + u, l + 64 * t);
+            }
+    };
+    load(zA, 0);
+    for (int i0 = 0; i0 < K - 1; i0 += 2 * UB) {
+        if (i0 + UB < K - 1) load(zB, i0 + UB);
+        if (!failed) probe(zA, i0); else probe_scan(zA, i0);
+        if (i0 + UB >= K - 1) break;
+        if (i0 + 2 * UB < K - 1) load(zA, i0 + 2 * UB);
+        if (!failed) probe(zB, i0 + UB); else probe_scan(zB, i0 + UB);
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     // rank valid positions by (detour, j); keys are unique
@@ -309,9 +335,9 @@ extern "C" sg_status sg_prune(const int32_t* knn, int64_t n, int32_t K, int32_t 
         fill<int64_t>(cnt, 0, n + 1, s);
         fill<int64_t>(fillc, 0, n + 1, s);
         if (K <= 64)
-            prune::detour_kernel<1, 512><<<grid, 256, 0, s>>>(knn, n, K, R, order, P, cnt);
+            prune::detour_kernel<1, 256><<<grid, 256, 0, s>>>(knn, n, K, R, order, P, cnt);
         else if (K <= 128)
-            prune::detour_kernel<2, 1024><<<grid, 256, 0, s>>>(knn, n, K, R, order, P, cnt);
+            prune::detour_kernel<2, 512><<<grid, 256, 0, s>>>(knn, n, K, R, order, P, cnt);
         else
             prune::detour_kernel<4, 1024><<<grid, 256, 0, s>>>(knn, n, K, R, order, P, cnt);
         SG_LAUNCH_CHECK();

@@ -74,6 +74,37 @@ def test_prune_hub_in_degree():
     np.testing.assert_array_equal(_prune_gpu(knn, 8), oracle.prune(knn, 8))
 
 
+def _cuckoo_slots(z, ct=256):
+    """The two table slots the detour kernel's row hash gives id z (K <= 64)."""
+    z = np.asarray(z, np.uint64)
+    m = (z ^ (z >> np.uint64(15))) & np.uint64(0xFFFFFF)
+    return (((m * np.uint64(0x9E3779)) >> np.uint64(8)) & np.uint64(ct - 1),
+            ((m * np.uint64(0x85EBCB)) >> np.uint64(16)) & np.uint64(ct - 1))
+
+
+def test_prune_rows_whose_table_cannot_settle():
+    # four ids that share both table slots cannot all be placed: rows holding
+    # them take the kernel's compare-with-every-entry path, with the same result
+    n, K, R = 300_000, 32, 12
+    h0, h1 = _cuckoo_slots(np.arange(n))
+    key = h0 * np.uint64(256) + h1
+    vals, first, counts = np.unique(key, return_index=True, return_counts=True)
+    clash = np.nonzero(key == vals[np.argmax(counts >= 4)])[0][:4]
+    assert len(clash) == 4
+    rng = np.random.default_rng(11)
+    active = np.unique(np.concatenate([clash, rng.choice(n, 600, replace=False)]))
+    knn = np.full((n, K), -1, np.int32)
+    for x in active:
+        pool = active[active != x]
+        if rng.random() < 0.5:           # rows holding the clashing ids (distinct ids per row)
+            c = clash[clash != x]
+            pick = np.concatenate([c, rng.choice(pool[~np.isin(pool, c)], K - len(c), replace=False)])
+        else:
+            pick = rng.choice(pool, K, replace=False)
+        knn[x] = pick
+    np.testing.assert_array_equal(_prune_gpu(knn, R), oracle.prune(knn, R))
+
+
 def _merge_gpu(off, mem, graphs, R, n_global, cap):
     out, deg = sg.sg_merge(off, torch.from_numpy(np.asarray(mem, np.int32)).to(DEV),
                            torch.from_numpy(np.asarray(graphs, np.int32)).to(DEV), R, n_global, cap)
