@@ -665,8 +665,8 @@ struct ScanOrder {
 // One block of NQ = 32*QB*WAVES queries (query rows qb*NQ.. of A.qops)
 // against all A.n candidate rows: the fused distance tile + top-k with
 // register-resident queries.  Candidate tiles (BC rows) are staged in LDS,
-// double buffered, the next tile already in flight in registers while the
-// current one is computed.  Within a tile the MFMAs of subtile s+1 are
+// double buffered, the next one or two tiles already in flight in registers
+// while the current one is computed.  Within a tile the MFMAs of subtile s+1 are
 // issued before the selection epilogue of subtile s so that both run at once.
 // Tiles are visited in ScanOrder.
 template <int P, int NSTEP, int KSEL, int WAVES, int QB, int CBQ, int BCR>
@@ -707,36 +707,40 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
     const ScanOrder order(qb * NQ, BC, ntiles);
     auto tile_row = [&](int t) { return order.tile(t) * BC; };
 
-    // tile staging: global -> registers (prefetch) -> LDS
-    intx4 pre[CPT];
-    float pre_norm = 0.f;
-    int32_t pre_pid = 0, pre_sexp = 0;
-    auto prefetch = [&](int j0) {
+    // tile staging: global -> registers -> LDS (two buffers).  4-wave shapes
+    // keep two register sets, so that a tile's loads are issued two tiles
+    // before it is committed (their tiles are short); 8-wave shapes, whose
+    // registers are fuller, keep one (loads issued one tile ahead).
+    constexpr int DEPTH = WAVES == 4 ? 2 : 1;
+    intx4 pre[DEPTH][CPT];
+    float pre_norm[DEPTH] = {};
+    int32_t pre_pid[DEPTH] = {}, pre_sexp[DEPTH] = {};
+    auto prefetch = [&](int r, int j0) {
         const uint8_t* src = A.ops + (int64_t)j0 * RB;
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
             const int c = tid + u * NT;
-            if (c < CHUNKS) pre[u] = *reinterpret_cast<const intx4*>(src + (int64_t)c * 16);
+            if (c < CHUNKS) pre[r][u] = *reinterpret_cast<const intx4*>(src + (int64_t)c * 16);
         }
         if (tid < BC) {
-            pre_norm = A.ninit[j0 + tid];
-            if (A.cpid) pre_pid = A.cpid[j0 + tid];
-            if constexpr (P == SG_PREC_FP8) pre_sexp = A.sexp[j0 + tid];
+            pre_norm[r] = A.ninit[j0 + tid];
+            if (A.cpid) pre_pid[r] = A.cpid[j0 + tid];
+            if constexpr (P == SG_PREC_FP8) pre_sexp[r] = A.sexp[j0 + tid];
         }
     };
-    auto commit = [&](int buf) {
+    auto commit = [&](int r, int buf) {
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
             const int c = tid + u * NT;
             if (c < CHUNKS) {
-                const int r = c / (RB / 16), o = c % (RB / 16);
-                *reinterpret_cast<intx4*>(&sm.tile[buf][r * RS + o * 16]) = pre[u];
+                const int row = c / (RB / 16), o = c % (RB / 16);
+                *reinterpret_cast<intx4*>(&sm.tile[buf][row * RS + o * 16]) = pre[r][u];
             }
         }
         if (tid < BC) {
-            sm.norm[buf][tid] = pre_norm;
-            sm.pid[buf][tid] = pre_pid;
-            if constexpr (P == SG_PREC_FP8) sm.sexp[buf][tid] = pre_sexp;
+            sm.norm[buf][tid] = pre_norm[r];
+            sm.pid[buf][tid] = pre_pid[r];
+            if constexpr (P == SG_PREC_FP8) sm.sexp[buf][tid] = pre_sexp[r];
         }
     };
     auto compute = [&](floatx16 (&acc)[QB], int buf, int sub) {
@@ -756,12 +760,7 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
         for (int b = 0; b < QB; ++b) acc[b] = mfma_tile<P, NSTEP>(arow, qf[b], acc[b], a_scale, q_scale[b]);
     };
 
-    prefetch(tile_row(0));
-    commit(0);
-    __syncthreads();
-    if (ntiles > 1) prefetch(tile_row(1));
-    for (int t = 0; t < ntiles; ++t) {
-        const int buf = t & 1;
+    auto body = [&](int t, int buf) {
         const int j0 = tile_row(t);
         const int32_t* tp = A.cpid ? sm.pid[buf] : nullptr;
         floatx16 accA[QB], accB[QB];
@@ -776,11 +775,44 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
                 sel.admit(accB, j0 + sub * 32, tp ? tp + sub * 32 : nullptr);
             }
         }
-        if (t + 1 < ntiles) {
-            commit(buf ^ 1);
-            if (t + 2 < ntiles) prefetch(tile_row(t + 2));
-        }
+    };
+    if constexpr (DEPTH == 2) {
+        // tile t sits in LDS buffer t % 2 and register set t % 2; the loop
+        // takes tiles in pairs so that both indices are compile-time constants
+        prefetch(0, tile_row(0));
+        if (ntiles > 1) prefetch(1, tile_row(1));
+        commit(0, 0);
         __syncthreads();
+        if (ntiles > 2) prefetch(0, tile_row(2));
+        for (int t = 0; t < ntiles; t += 2) {
+            body(t, 0);
+            if (t + 1 < ntiles) {
+                commit(1, 1);
+                if (t + 3 < ntiles) prefetch(1, tile_row(t + 3));
+            }
+            __syncthreads();
+            if (t + 1 >= ntiles) break;
+            body(t + 1, 1);
+            if (t + 2 < ntiles) {
+                commit(0, 0);
+                if (t + 4 < ntiles) prefetch(0, tile_row(t + 4));
+            }
+            __syncthreads();
+        }
+    } else {
+        prefetch(0, tile_row(0));
+        commit(0, 0);
+        __syncthreads();
+        if (ntiles > 1) prefetch(0, tile_row(1));
+        for (int t = 0; t < ntiles; ++t) {
+            const int buf = t & 1;
+            body(t, buf);
+            if (t + 1 < ntiles) {
+                commit(0, buf ^ 1);
+                if (t + 2 < ntiles) prefetch(0, tile_row(t + 2));
+            }
+            __syncthreads();
+        }
     }
     sel.drain();
     if (A.nbr) write_lists(A, KSEL, qblk0, 32 * QB);
