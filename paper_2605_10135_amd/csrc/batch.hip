@@ -131,7 +131,7 @@ __global__ void scatter_batched_kernel(Shards sh, const int32_t* __restrict__ la
 // narrows them to one shard.  Candidate ids and output rows are batch rows
 // (row0-based); every workgroup leaves once the counter passes the last item.
 template <int P, int NSTEP, int KSEL, int WAVES, int QB, int CBQ, int BCR>
-__global__ __launch_bounds__(WAVES * 64, min_waves_per_simd(WAVES, BCR)) void dist_topk_batched_kernel(
+__global__ __launch_bounds__(WAVES * 64, min_waves_per_simd(WAVES, BCR, CBQ)) void dist_topk_batched_kernel(
     TopkArgs A, Shards sh, unsigned int* __restrict__ counter, int nitems) {
     __shared__ TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR> sm;
     __shared__ int s_item;

@@ -308,8 +308,9 @@ constexpr int group_of(int n, int m) {
 
 // acc += A(32 candidate rows at arow, LDS) x Q(32 queries) over the padded
 // row, in groups of steps whose A fragments are all requested before the
-// group's MFMA chain starts, so that one LDS round trip covers the group.
-template <int P, int NSTEP>
+// group's MFMA chain starts, so that one LDS round trip covers the group
+// (16-bit groups of at most GMAX steps: fewer keep fewer registers live).
+template <int P, int NSTEP, int GMAX = 8>
 __device__ inline floatx16 mfma_tile(const uint8_t* arow, const Frag<P, NSTEP>& q, floatx16 acc,
                                      int sa, int sb) {
     if constexpr (P == SG_PREC_FP32) {
@@ -326,7 +327,7 @@ __device__ inline floatx16 mfma_tile(const uint8_t* arow, const Frag<P, NSTEP>& 
                 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s / 4][s % 4], q.v[g + s], acc, 0, 0, 0);
         }
     } else if constexpr (P == SG_PREC_F16 || P == SG_PREC_BF16) {
-        constexpr int G = group_of(NSTEP, 8);
+        constexpr int G = group_of(NSTEP, GMAX);
 #pragma unroll
         for (int g = 0; g < NSTEP; g += G) {
             intx4 a[G];
@@ -477,17 +478,19 @@ struct Selector {
     // <= the threshold, one accumulator element at a time: from the element's
     // ballot the two lanes of a query see each other's hit, so they write
     // their keys at known slots (no atomics) and both keep the query's buffer
-    // fill in a register.  Round 1 stops at the first element some buffer
-    // cannot take; then every query whose buffer could not take two keys per
-    // remaining element is merged, and round 2 finishes the subtile without
-    // checks (CBQ = 32 guarantees the room).  A merged query's lowered
-    // threshold takes effect at the next subtile.  Admission is exact in any
+    // fill in a register.  The 16 elements go in chunks of CBQ/2 (one chunk
+    // for CBQ = 32, two for CBQ = 16): round 1 stops at the first element some
+    // buffer cannot take; then every query whose buffer could not take two
+    // keys per remaining element of the chunk is merged, and round 2 finishes
+    // the chunk without checks (an emptied buffer holds the 2 x CBQ/2 keys a
+    // chunk can add).  A merged query's lowered threshold takes effect at the
+    // next chunk.  Admission is exact in any
     // candidate order: a candidate whose distance exceeds the K-th distance of
     // a subset already seen cannot be in the top K, and one that equals it is
     // admitted and ranked by (distance, id) in the merge.  The query itself
     // and padding rows are NaN, which no comparison admits.
     __device__ void admit(floatx16 (&acc)[QB], int64_t cbase, const int32_t* tpid) {
-        static_assert(CBQ == 32, "round 2 relies on room for 32 keys after a merge");
+        static_assert(CBQ == 16 || CBQ == 32, "a chunk of CBQ/2 elements must fit an emptied buffer");
         const int l = lane_id();
         const int ql = l & 31;
         const int h = l >> 5;
@@ -518,55 +521,61 @@ struct Selector {
 #pragma unroll
             for (int i = 0; i < 16; ++i) ids[i] = (int32_t)(cbase + out_row(i, l));
         }
+        // chunks of E elements: a chunk adds at most 2E = CBQ keys per query
+        constexpr int E = CBQ / 2;
 #pragma unroll
         for (int b = 0; b < QB; ++b) {
-            const float t = thr[b];
+            float t = thr[b];
             int c = fill[b];
             uint64_t* qbuf = buf + (b * 32 + ql) * CBQ;
-            int stop = 16;   // wave-uniform: first element round 1 left
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                if (i >= stop) continue;
-                const bool hit = acc[b][i] <= t;
-                const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
-                if (m == 0) continue;
-                const int pa = (int)(((uint32_t)m >> ql) & 1u);
-                const int pb = (int)(((uint32_t)(m >> 32) >> ql) & 1u);
-                if (__builtin_amdgcn_ballot_w64(c + pa + pb > CBQ)) {
-                    stop = i;
-                    continue;
-                }
-                if (hit) qbuf[c + (h ? pa : 0)] = make_key(acc[b][i], ids[i]);
-                c += pa + pb;
-            }
-            if (stop < 16) {
-                const int room = 2 * (16 - stop);
-                uint32_t need = (uint32_t)__builtin_amdgcn_ballot_w64(h == 0 && c + room > CBQ);
-                float tnext = t;
-                while (need) {
-                    const int qi = __builtin_ctz(need);
-                    need &= need - 1;
-                    const int q2 = b * 32 + qi;
-                    const float tq = merge_query<KSEL>(state + (int64_t)q2 * KSEL, buf + q2 * CBQ,
-                                                       __builtin_amdgcn_readlane(c, qi));
-                    if (ql == qi) {
-                        c = 0;
-                        tnext = tq;
-                    }
-                }
+            for (int c0 = 0; c0 < 16; c0 += E) {
+                int stop = c0 + E;   // wave-uniform: first element round 1 left
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    if (i < stop) continue;
+                for (int i = c0; i < c0 + E; ++i) {
+                    if (i >= stop) continue;
                     const bool hit = acc[b][i] <= t;
                     const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
                     if (m == 0) continue;
                     const int pa = (int)(((uint32_t)m >> ql) & 1u);
                     const int pb = (int)(((uint32_t)(m >> 32) >> ql) & 1u);
+                    if (__builtin_amdgcn_ballot_w64(c + pa + pb > CBQ)) {
+                        stop = i;
+                        continue;
+                    }
                     if (hit) qbuf[c + (h ? pa : 0)] = make_key(acc[b][i], ids[i]);
                     c += pa + pb;
                 }
-                thr[b] = tnext;
+                if (stop < c0 + E) {
+                    const int room = 2 * (c0 + E - stop);
+                    uint32_t need = (uint32_t)__builtin_amdgcn_ballot_w64(h == 0 && c + room > CBQ);
+                    float tnext = t;
+                    while (need) {
+                        const int qi = __builtin_ctz(need);
+                        need &= need - 1;
+                        const int q2 = b * 32 + qi;
+                        const float tq = merge_query<KSEL>(state + (int64_t)q2 * KSEL, buf + q2 * CBQ,
+                                                           __builtin_amdgcn_readlane(c, qi));
+                        if (ql == qi) {
+                            c = 0;
+                            tnext = tq;
+                        }
+                    }
+#pragma unroll
+                    for (int i = c0; i < c0 + E; ++i) {
+                        if (i < stop) continue;
+                        const bool hit = acc[b][i] <= t;
+                        const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+                        if (m == 0) continue;
+                        const int pa = (int)(((uint32_t)m >> ql) & 1u);
+                        const int pb = (int)(((uint32_t)(m >> 32) >> ql) & 1u);
+                        if (hit) qbuf[c + (h ? pa : 0)] = make_key(acc[b][i], ids[i]);
+                        c += pa + pb;
+                    }
+                    t = tnext;   // a merged query's lowered threshold applies from the next chunk
+                }
             }
+            thr[b] = t;
             fill[b] = c;
         }
     }
@@ -677,6 +686,7 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
     constexpr int NQ = 32 * QB * WAVES;
     constexpr int CHUNKS = BC * RB / 16;                        // 16-byte chunks per tile
     constexpr int CPT = (CHUNKS + NT - 1) / NT;                 // chunks per thread
+    constexpr int GMAX = CBQ == 16 ? 4 : 8;                     // A-fragment group (registers)
 
     const int tid = threadIdx.x;
     const int l = tid & 63;
@@ -708,10 +718,10 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
     auto tile_row = [&](int t) { return order.tile(t) * BC; };
 
     // tile staging: global -> registers -> LDS (two buffers).  4-wave shapes
-    // keep two register sets, so that a tile's loads are issued two tiles
-    // before it is committed (their tiles are short); 8-wave shapes, whose
-    // registers are fuller, keep one (loads issued one tile ahead).
-    constexpr int DEPTH = WAVES == 4 ? 2 : 1;
+    // with 32-entry buffers keep two register sets, so that a tile's loads are
+    // issued two tiles before it is committed (their tiles are short); the
+    // others, whose registers are fuller, keep one (loads one tile ahead).
+    constexpr int DEPTH = WAVES == 4 && CBQ == 32 ? 2 : 1;
     intx4 pre[DEPTH][CPT];
     float pre_norm[DEPTH] = {};
     int32_t pre_pid[DEPTH] = {}, pre_sexp[DEPTH] = {};
@@ -756,8 +766,8 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[b][i] = nv[i >> 2][i & 3];
         }
-#pragma unroll
-        for (int b = 0; b < QB; ++b) acc[b] = mfma_tile<P, NSTEP>(arow, qf[b], acc[b], a_scale, q_scale[b]);
+        for (int b = 0; b < QB; ++b)
+            acc[b] = mfma_tile<P, NSTEP, GMAX>(arow, qf[b], acc[b], a_scale, q_scale[b]);
     };
 
     auto body = [&](int t, int buf) {
@@ -820,12 +830,15 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
 }
 
 // Workgroups per CU a launch shape aims for: 32-row tiles keep the LDS of a
-// 4-wave workgroup near 50 KB, so three fit (12 waves; at most 168 VGPRs).
-constexpr int min_waves_per_simd(int waves, int bcr) { return waves == 4 && bcr == 32 ? 3 : 1; }
+// 4-wave workgroup near 50 KB, so three fit (12 waves; at most 168 VGPRs);
+// with 16-entry buffers it is 34 KB and four fit (16 waves; 128 VGPRs).
+constexpr int min_waves_per_simd(int waves, int bcr, int cbq = CB) {
+    return waves == 4 && bcr == 32 ? (cbq == 16 ? 4 : 3) : 1;
+}
 
 // One query block per workgroup (blockIdx.x).
 template <int P, int NSTEP, int KSEL, int WAVES, int QB, int CBQ, int BCR>
-__global__ __launch_bounds__(WAVES * 64, min_waves_per_simd(WAVES, BCR)) void dist_topk_kernel(TopkArgs A) {
+__global__ __launch_bounds__(WAVES * 64, min_waves_per_simd(WAVES, BCR, CBQ)) void dist_topk_kernel(TopkArgs A) {
     __shared__ TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR> sm;
     topk_block<P, NSTEP, KSEL, WAVES, QB, CBQ, BCR>(sm, blockIdx.x, A);
 }
@@ -1359,6 +1372,13 @@ bool for_shapes(int prec, int d, M& m) {
         m.template add<PR, NS, 4, 1, CB, 64>();  \
         m.template add<PR, NS, 4, 1, CB, 32>();  \
     } while (0)
+// ... and, for short 16-bit / FP8 rows, 32-row tiles with 16-entry buffers
+// (four workgroups per CU)
+#define SG_FOUR(PR, NS, W0)                      \
+    do {                                         \
+        SG_THREE(PR, NS, W0);                    \
+        m.template add<PR, NS, 4, 1, 16, 32>();  \
+    } while (0)
     switch (prec) {
         case SG_PREC_FP32:
             if (need <= 16) SG_THREE(SG_PREC_FP32, 16, TWAVES);
@@ -1369,9 +1389,9 @@ bool for_shapes(int prec, int d, M& m) {
             return true;
         case SG_PREC_F16:
             if (need <= 2) SG_ONE(SG_PREC_F16, 2, TWAVES);
-            else if (need <= 4) SG_THREE(SG_PREC_F16, 4, TWAVES);
-            else if (need <= 6) SG_THREE(SG_PREC_F16, 6, TWAVES);
-            else if (need <= 8) SG_THREE(SG_PREC_F16, 8, TWAVES);
+            else if (need <= 4) SG_FOUR(SG_PREC_F16, 4, TWAVES);
+            else if (need <= 6) SG_FOUR(SG_PREC_F16, 6, TWAVES);
+            else if (need <= 8) SG_FOUR(SG_PREC_F16, 8, TWAVES);
             else if (need <= 12) SG_ONE(SG_PREC_F16, 12, TWAVES);
             else if (need <= 16) SG_ONE(SG_PREC_F16, 16, TWAVES);
             else if (need <= 24) SG_ONE(SG_PREC_F16, 24, 4);
@@ -1381,9 +1401,9 @@ bool for_shapes(int prec, int d, M& m) {
             return true;
         case SG_PREC_BF16:
             if (need <= 2) SG_ONE(SG_PREC_BF16, 2, TWAVES);
-            else if (need <= 4) SG_THREE(SG_PREC_BF16, 4, TWAVES);
-            else if (need <= 6) SG_THREE(SG_PREC_BF16, 6, TWAVES);
-            else if (need <= 8) SG_THREE(SG_PREC_BF16, 8, TWAVES);
+            else if (need <= 4) SG_FOUR(SG_PREC_BF16, 4, TWAVES);
+            else if (need <= 6) SG_FOUR(SG_PREC_BF16, 6, TWAVES);
+            else if (need <= 8) SG_FOUR(SG_PREC_BF16, 8, TWAVES);
             else if (need <= 12) SG_ONE(SG_PREC_BF16, 12, TWAVES);
             else if (need <= 16) SG_ONE(SG_PREC_BF16, 16, TWAVES);
             else if (need <= 24) SG_ONE(SG_PREC_BF16, 24, 4);
@@ -1392,8 +1412,8 @@ bool for_shapes(int prec, int d, M& m) {
             else return false;
             return true;
         default:
-            if (need <= 1) SG_THREE(SG_PREC_FP8, 1, TWAVES);
-            else if (need <= 2) SG_THREE(SG_PREC_FP8, 2, TWAVES);
+            if (need <= 1) SG_FOUR(SG_PREC_FP8, 1, TWAVES);
+            else if (need <= 2) SG_FOUR(SG_PREC_FP8, 2, TWAVES);
             else if (need <= 4) SG_ONE(SG_PREC_FP8, 4, TWAVES);
             else if (need <= 8) SG_ONE(SG_PREC_FP8, 8, 4);
             else if (need <= 16) SG_ONE(SG_PREC_FP8, 16, 4);
