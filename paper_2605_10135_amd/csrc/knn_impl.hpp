@@ -725,24 +725,26 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
     intx4 pre[DEPTH][CPT];
     float pre_norm[DEPTH] = {};
     int32_t pre_pid[DEPTH] = {}, pre_sexp[DEPTH] = {};
+    // Every thread issues the same loads (the per-row values are read by all
+    // threads, thread t taking row t % BC), so that the compiler can count the
+    // loads still in flight when a register set is committed.
     auto prefetch = [&](int r, int j0) {
         const uint8_t* src = A.ops + (int64_t)j0 * RB;
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
             const int c = tid + u * NT;
-            if (c < CHUNKS) pre[r][u] = *reinterpret_cast<const intx4*>(src + (int64_t)c * 16);
+            if (CHUNKS % NT == 0 || c < CHUNKS) pre[r][u] = *reinterpret_cast<const intx4*>(src + (int64_t)c * 16);
         }
-        if (tid < BC) {
-            pre_norm[r] = A.ninit[j0 + tid];
-            if (A.cpid) pre_pid[r] = A.cpid[j0 + tid];
-            if constexpr (P == SG_PREC_FP8) pre_sexp[r] = A.sexp[j0 + tid];
-        }
+        const int rr = tid % BC;
+        pre_norm[r] = A.ninit[j0 + rr];
+        pre_pid[r] = A.cpid ? A.cpid[j0 + rr] : 0;
+        if constexpr (P == SG_PREC_FP8) pre_sexp[r] = A.sexp[j0 + rr];
     };
     auto commit = [&](int r, int buf) {
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
             const int c = tid + u * NT;
-            if (c < CHUNKS) {
+            if (CHUNKS % NT == 0 || c < CHUNKS) {
                 const int row = c / (RB / 16), o = c % (RB / 16);
                 *reinterpret_cast<intx4*>(&sm.tile[buf][row * RS + o * 16]) = pre[r][u];
             }
@@ -1372,7 +1374,7 @@ bool for_shapes(int prec, int d, M& m) {
         m.template add<PR, NS, 4, 1, CB, 64>();  \
         m.template add<PR, NS, 4, 1, CB, 32>();  \
     } while (0)
-// ... and, for short 16-bit / FP8 rows, 32-row tiles with 16-entry buffers
+// ... and, for short 16-bit / FP8 rows, 16-entry buffers with 32-row tiles
 // (four workgroups per CU)
 #define SG_FOUR(PR, NS, W0)                      \
     do {                                         \
