@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--shards", type=int, default=16)
     ap.add_argument("--chosen", default="f16", choices=["f16", "fp32"])
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-per-shard", action="store_true",
+                    help="skip the comparison with one distance launch and one prune per shard")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--queries", type=int, default=10_000)
@@ -184,19 +186,48 @@ def main():
     torch.cuda.synchronize()
     stages = {"knn_and_prune_ms": e0.elapsed_time(e1), "merge_ms": e1.elapsed_time(e2)}
 
+    # the integer passes on their own: the prune of all 2M shard rows as the
+    # batched pass runs it (batch-row ids), and the merge; algorithmic bytes:
+    # prune reads the K ids of a row and gathers K lists of K ids, then moves
+    # about R x 20 B per row in the reverse pass; merge reads the shard graphs
+    # and writes the merged one
+    row0 = torch.repeat_interleave(torch.tensor(offs[:-1], dtype=torch.int32, device=dev),
+                                   torch.tensor(sizes.tolist(), device=dev))
+    knn_batch = (knn_all + row0[:, None]).contiguous()
+    sg.sg_prune(knn_batch, R)
+    e3, e4 = ev(), ev()
+    e3.record()
+    sg.sg_prune(knn_batch, R)
+    e4.record()
+    torch.cuda.synchronize()
+    prune_ms = e3.elapsed_time(e4)
+    prune_bytes = float(total) * (4 * K + 4 * K * K + 20 * R)
+    merge_bytes = float(total) * R * 4 + float(N) * 2 * R * 4
+    integer_passes = {
+        "prune": {"rows": total, "ms": prune_ms, "algorithmic_bytes": prune_bytes,
+                  "achieved_GBps": prune_bytes / (prune_ms / 1e3) / 1e9},
+        "merge": {"rows": total, "ms": stages["merge_ms"], "algorithmic_bytes": merge_bytes,
+                  "achieved_GBps": merge_bytes / (stages["merge_ms"] / 1e3) / 1e9},
+    }
+    log("integer passes %s" % integer_passes)
+    del knn_batch, row0
+
     # the same build with one distance launch and one prune per shard (same lists)
-    nbrs = [torch.empty((int(n), K), dtype=torch.int32, device=dev) for n in sizes]
-    orders = [torch.empty(int(n), dtype=torch.int32, device=dev) for n in sizes]
-    g1 = torch.empty_like(graphs)
-    ps = build_per_shard_step(sg, shards, K, R, args.chosen, g1, nbrs, orders, mem, offs, N)
-    ps_sec, ps_kms, ps_launches, (pmg, pdeg) = timed(torch, sg, ps, 2, 1)
-    per_shard = {"ms_per_step": ps_sec * 1e3, "dist_launches_per_step": ps_launches // 2,
-                 "dist_kernel_ms_per_step": ps_kms / 2,
-                 "graph_identical_to_batched": bool(torch.equal(torch.cat(nbrs), graph_of[args.chosen][2])
-                                                    and torch.equal(pmg, graph_of[args.chosen][0])
-                                                    and torch.equal(pdeg, graph_of[args.chosen][1]))}
-    log("per-shard launches: %.1f ms/step, identical %s" % (ps_sec * 1e3, per_shard["graph_identical_to_batched"]))
-    del nbrs, orders, g1
+    per_shard = None
+    if not args.no_per_shard:
+        nbrs = [torch.empty((int(n), K), dtype=torch.int32, device=dev) for n in sizes]
+        orders = [torch.empty(int(n), dtype=torch.int32, device=dev) for n in sizes]
+        g1 = torch.empty_like(graphs)
+        ps = build_per_shard_step(sg, shards, K, R, args.chosen, g1, nbrs, orders, mem, offs, N)
+        ps_sec, ps_kms, ps_launches, (pmg, pdeg) = timed(torch, sg, ps, 2, 1)
+        per_shard = {"ms_per_step": ps_sec * 1e3, "dist_launches_per_step": ps_launches // 2,
+                     "dist_kernel_ms_per_step": ps_kms / 2,
+                     "graph_identical_to_batched": bool(torch.equal(torch.cat(nbrs), graph_of[args.chosen][2])
+                                                        and torch.equal(pmg, graph_of[args.chosen][0])
+                                                        and torch.equal(pdeg, graph_of[args.chosen][1]))}
+        log("per-shard launches: %.1f ms/step, identical %s" % (ps_sec * 1e3,
+                                                                per_shard["graph_identical_to_batched"]))
+        del nbrs, orders, g1
 
     same = None
     if "fp32" in graph_of and args.chosen != "fp32":
@@ -294,6 +325,7 @@ def main():
                    "search_recall_at_10_L64": recall10},
         "shard_rows_per_s": ch["shard_rows_ps"],
         "stages_ms": stages,
+        "integer_passes": integer_passes,
         "per_shard_launches": per_shard,
         "autotune": {f: {"2^%d" % b_: {"chosen": c, "variant_ms": t} for b_, (c, t) in v.items()}
                      for f, v in tuned.items()},

@@ -15,6 +15,7 @@ Usage::
 
     python -m paper_2605_10135_amd.profiling stats  <kernel_stats.csv> <out.md> "<command>"
     python -m paper_2605_10135_amd.profiling traffic <fetch.csv> <write.csv> <out.txt> "<fetch cmd>" "<write cmd>" [kernel filter]
+    python -m paper_2605_10135_amd.profiling integer <fetch.csv> <write.csv> <out.md> "<fetch cmd>" "<write cmd>" <filter,filter,...>
 """
 from __future__ import annotations
 
@@ -110,6 +111,44 @@ def traffic(fetch_csv: str, write_csv: str, out: str, fetch_cmd: str, write_cmd:
     print("\n".join(lines))
 
 
+def _dispatches(path: str, counter: str) -> dict:
+    """kernel name -> list of (counter value, duration ns) per dispatch."""
+    acc = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            dur = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            acc.setdefault(_short(r["Kernel_Name"]), []).append((float(r["Counter_Value"]), dur))
+    return acc
+
+
+def integer_table(fetch_csv: str, write_csv: str, out: str, fetch_cmd: str, write_cmd: str,
+                  filters: str) -> None:
+    """HBM-side bytes per dispatch (copy-calibrated) of the kernels whose names
+    hold one of the comma-separated filters, as a markdown table."""
+    fv, wv = counter_values(fetch_csv, "FETCH_SIZE"), counter_values(write_csv, "WRITE_SIZE")
+    (ck, cf), (_, cw) = _calib(fv), _calib(wv)
+    ffac, wfac = CALIB_BYTES / (cf * 1024.0), CALIB_BYTES / (cw * 1024.0)
+    fd, wd = _dispatches(fetch_csv, "FETCH_SIZE"), _dispatches(write_csv, "WRITE_SIZE")
+    lines = ["# HBM traffic of the integer passes (rocprofv3 --pmc, copy-calibrated)", "",
+             "Fetch command: `%s`" % fetch_cmd, "", "Write command: `%s`" % write_cmd, "",
+             "Calibration: %s, fetch factor %.4f, write factor %.4f." % (ck, ffac, wfac), "",
+             "| kernel | dispatches | fetch MB / dispatch | write MB / dispatch | ms / dispatch (counter run) |",
+             "|---|---:|---:|---:|---:|"]
+    for filt in filters.split(","):
+        for name in sorted(k for k in fd if filt in k):
+            f = fd[name]
+            w = wd.get(name, [])
+            fb = sum(v for v, _ in f) / len(f) * 1024.0 * ffac
+            wb = (sum(v for v, _ in w) / len(w) * 1024.0 * wfac) if w else float("nan")
+            ms = sum(d for _, d in f) / len(f) / 1e6
+            lines.append("| `%s` | %d | %.1f | %.1f | %.3f |" % (name, len(f), fb / 1e6, wb / 1e6, ms))
+    with open(out, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def read_traffic(path: str):
     """Bytes per distance-kernel launch from a traffic record, or None when the
     record is missing or was taken on other kernel sources."""
@@ -155,6 +194,8 @@ if __name__ == "__main__":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif len(sys.argv) >= 7 and sys.argv[1] == "traffic":
         traffic(*sys.argv[2:8])
+    elif len(sys.argv) >= 8 and sys.argv[1] == "integer":
+        integer_table(*sys.argv[2:8])
     else:
         print(__doc__)
         sys.exit(2)
