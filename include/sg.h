@@ -26,6 +26,10 @@
  *    workspace memory must be ordered by the caller.
  *  * Every kernel is deterministic: the same call on the same inputs writes
  *    the same bytes.
+ *  * One call takes at most 2^26 - 1024 rows (n, nq, n_global, the rows of a
+ *    batch with each shard padded to 256): kernels that give every row a
+ *    wavefront launch 64 work-items per row, and a dispatch holds fewer than
+ *    2^32 work-items.  Larger counts return SG_ERR_ARG.
  */
 #ifndef SG_H
 #define SG_H

@@ -224,7 +224,7 @@ Plan make_plan(const int64_t* off, int S, int d, int k, int R, int prec) {
         SG_REQUIRE(off[s + 1] >= off[s], "offsets_h must be non-decreasing");
         SG_REQUIRE(off[s + 1] - off[s] < (int64_t(1) << 31), "shard too large");
     }
-    SG_REQUIRE(off[S] < (int64_t(1) << 31), "more than 2^31 rows in the batch");
+    SG_REQUIRE(off[S] + (int64_t)S * PAD_ROWS <= MAX_ROWS, "too many rows in the batch (at most 2^26 - 1024 with padding)");
     BatchedMaker m{p.ksel, {}};
     SG_REQUIRE(for_shapes(prec, d, m), "no register-resident distance kernel for this precision and d");
     int64_t pad = 0, piv = 0, ppad = 0;

@@ -183,6 +183,20 @@ __device__ inline uint64_t wave_sort_u64(uint64_t x) {
     return x;
 }
 
+// Ascending bitonic sort of one 32-bit key per lane across the wave.
+__device__ inline uint32_t wave_sort_u32(uint32_t x) {
+    const int l = lane_id();
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t o = lane_xor(x, j);
+            x = (o < x) == (((l & k) == 0) == ((l & j) == 0)) ? o : x;
+        }
+    }
+    return x;
+}
+
 // Each 32-lane half sorted on its own: lanes 0..31 descending, 32..63 ascending.
 __device__ inline uint64_t half_sort_desc_u64(uint64_t x) {
     const int l = lane_id();
@@ -208,6 +222,11 @@ __device__ inline int lower_bound_u64(const uint64_t* a, int len, uint64_t v) {
 }
 
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Largest row count one call takes: kernels that give every row a wavefront
+// launch 64 work-items per row, and a dispatch holds fewer than 2^32
+// work-items per dimension.
+constexpr int64_t MAX_ROWS = (int64_t(1) << 26) - 1024;
 
 // Workgroups are dispatched to the 8 XCDs of the chip round robin (block b
 // on XCD b % 8), each XCD with its own L2.  This bijection of [0, G) hands

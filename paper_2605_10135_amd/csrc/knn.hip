@@ -218,7 +218,7 @@ extern "C" sg_status sg_knn_rows(const void* X, sg_dtype dtype, int64_t n, int32
                                  size_t ws_bytes, void* stream) {
     return guarded([&] {
         knn::check_args(X, dtype, n, d, ld, metric, k, prec, rerank);
-        SG_REQUIRE(nq >= 0 && nq < (1ll << 31), "nq out of range");
+        SG_REQUIRE(nq >= 0 && nq <= MAX_ROWS, "nq out of range (at most 2^26 - 1024 rows)");
         if (n == 0 || nq == 0) return;
         SG_REQUIRE(rows != nullptr && nbr != nullptr, "NULL pointer");
         knn::run(X, dtype, n, d, ld, metric, k, prec, rerank, rows, nq, nbr, dist, ws, ws_bytes,
@@ -230,7 +230,7 @@ extern "C" sg_status sg_rerank(const void* X, sg_dtype dtype, int64_t n, int32_t
                                const int32_t* cand, int32_t c, int32_t k, int32_t* nbr, float* dist,
                                void* stream) {
     return guarded([&] {
-        SG_REQUIRE(n >= 0 && n < (1ll << 31), "n out of range");
+        SG_REQUIRE(n >= 0 && n <= MAX_ROWS, "n out of range (at most 2^26 - 1024 rows)");
         SG_REQUIRE(d >= 1 && d <= 1024 && ld >= d, "bad d / ld (d <= 1024)");
         SG_REQUIRE(c >= 1 && c <= 256 && k >= 1 && k <= c, "need 1 <= k <= c <= 256");
         SG_REQUIRE(metric == SG_L2 || metric == SG_IP, "unknown metric");

@@ -1500,7 +1500,7 @@ inline Layout layout_k(int64_t n, int d, int k, int prec, int rerank) {
 
 inline void check_args(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int k, int prec,
                 int rerank) {
-    SG_REQUIRE(n >= 0 && n < (1ll << 31) - PAD_ROWS, "n out of range");
+    SG_REQUIRE(n >= 0 && n <= MAX_ROWS, "n out of range (at most 2^26 - 1024 rows)");
     SG_REQUIRE(d >= 1 && d <= 1024, "d must be in 1..1024");
     SG_REQUIRE(ld >= d, "ld must be >= d");
     SG_REQUIRE(k >= 1 && k <= 256, "k must be in 1..256");

@@ -134,11 +134,11 @@ extern "C" sg_status sg_merge(int32_t S, const int64_t* shard_offsets_h, const i
                        "shard offsets must be non-decreasing");
         SG_REQUIRE(R >= 1 && R <= 256, "R must be in 1..256");
         SG_REQUIRE(max_degree >= 1 && max_degree <= merge::MAX_DEG, "max_degree must be in 1..1024");
-        SG_REQUIRE(n_global >= 0 && n_global < (1ll << 31), "n_global out of range");
+        SG_REQUIRE(n_global >= 0 && n_global <= MAX_ROWS, "n_global out of range (at most 2^26 - 1024)");
         if (n_global == 0) return;
         SG_REQUIRE(out != nullptr && degree != nullptr, "NULL output");
         const int64_t total = shard_offsets_h[S];
-        SG_REQUIRE(total < (1ll << 31), "too many shard rows");
+        SG_REQUIRE(total <= MAX_ROWS, "too many shard rows (at most 2^26 - 1024)");
         SG_REQUIRE(total == 0 || (member_ids != nullptr && graphs != nullptr), "NULL input");
         merge::Layout L = merge::layout(total, n_global);
         if (ws == nullptr || ws_bytes < L.total) {

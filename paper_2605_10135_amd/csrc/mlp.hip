@@ -533,7 +533,7 @@ extern "C" sg_status sg_mlp_project(const float* X, int64_t n, int32_t D, int64_
                                     void* stream) {
     return guarded([&] {
         check_net(D, H, E);
-        SG_REQUIRE(n >= 0 && ld >= D, "bad sizes");
+        SG_REQUIRE(n >= 0 && n <= MAX_ROWS && ld >= D, "bad sizes (at most 2^26 - 1024 rows)");
         if (n == 0) return;
         SG_REQUIRE(X && F && W1 && b1 && W2 && b2 && mu && sigma, "NULL pointer");
         const int64_t CH = mlp::PROJ_CHUNK;

@@ -15,8 +15,8 @@
 //    position j.  Positions are ranked by (detour, j) (a wave sort of the
 //    keys) and the first R written: P(x); the in-degree histogram of P is
 //    counted as they are written.
-//  * exclusive scan of the in-degrees, scatter of the 64-bit reverse keys
-//    (p << 32 | x) per target (slot order is arbitrary; the next pass sorts,
+//  * exclusive scan of the in-degrees, scatter of the 32-bit reverse keys
+//    (p << 26 | x) per target in arbitrary slot order (the next pass sorts,
 //    so the output does not depend on it).
 //  * combine_kernel: one wave per row y: the R smallest reverse keys (wave
 //    bitonic sort, chunked for high in-degree), then the list
@@ -196,9 +196,19 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
     }
 }
 
+// Reverse-edge keys (p, x) ordered by p, then x, as 32-bit (p << 26 | x):
+// p < R <= 64 and x < MAX_ROWS < 2^26 - 1, so no key equals the all-ones
+// empty marker.  Half the bytes of a 64-bit (p << 32 | x) key for the
+// scatter, and half the sorting work for the combine pass.
+constexpr int REV_XBITS = 26;
+static_assert(MAX_ROWS < (int64_t(1) << REV_XBITS) - 1, "row ids must fit the reverse key");
+constexpr uint32_t REV_EMPTY = ~0u;
+__device__ inline uint32_t rev_key(int p, int64_t x) { return ((uint32_t)p << REV_XBITS) | (uint32_t)x; }
+__device__ inline int32_t rev_source(uint32_t k) { return (int32_t)(k & ((1u << REV_XBITS) - 1)); }
+
 __global__ void scatter_kernel(const int32_t* __restrict__ P, int64_t total, int R,
                                const int64_t* __restrict__ off, int64_t* __restrict__ fillc,
-                               uint64_t* __restrict__ rev) {
+                               uint32_t* __restrict__ rev) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         int32_t y = P[e];
@@ -206,7 +216,7 @@ __global__ void scatter_kernel(const int32_t* __restrict__ P, int64_t total, int
         int64_t x = e / R;
         int p = (int)(e - x * R);
         unsigned long long slot = atomicAdd(reinterpret_cast<unsigned long long*>(&fillc[y]), 1ull);
-        rev[off[y] + (int64_t)slot] = ((uint64_t)p << 32) | (uint32_t)x;
+        rev[off[y] + (int64_t)slot] = rev_key(p, x);
     }
 }
 
@@ -231,7 +241,7 @@ __device__ inline int span_of(int32_t v) {
 
 __global__ __launch_bounds__(256) void combine_kernel(const int32_t* __restrict__ P, int64_t n, int R,
                                                       const int64_t* __restrict__ off,
-                                                      const uint64_t* __restrict__ rev,
+                                                      const uint32_t* __restrict__ rev,
                                                       const int32_t* __restrict__ order,
                                                       int32_t* __restrict__ F) {
     const int l = threadIdx.x & 63;
@@ -242,21 +252,21 @@ __global__ __launch_bounds__(256) void combine_kernel(const int32_t* __restrict_
     if (y < 0 || y >= n) return;
     const int h = (R + 1) / 2;
     const int64_t b = off[y], cnt = off[y + 1] - off[y];
-    // the R smallest reverse keys, ascending, one per lane
-    uint64_t best = l < cnt ? rev[b + l] : EMPTY_KEY;
-    best = wave_sort_u64(best);
+    // the 64 smallest reverse keys, ascending, one per lane
+    uint32_t best = l < cnt ? rev[b + l] : REV_EMPTY;
+    best = wave_sort_u32(best);
     for (int64_t c0 = 64; c0 < cnt; c0 += 64) {
-        uint64_t v = c0 + l < cnt ? rev[b + c0 + l] : EMPTY_KEY;
-        v = wave_sort_u64(v);
+        uint32_t v = c0 + l < cnt ? rev[b + c0 + l] : REV_EMPTY;
+        v = wave_sort_u32(v);
         // bitonic merge of two ascending runs: reverse one, take elementwise min, sort
-        uint64_t vr = shfl_u64(v, 63 - l);
-        best = wave_sort_u64(best < vr ? best : vr);
+        const uint32_t vr = (uint32_t)__shfl((int)v, 63 - l, 64);
+        best = wave_sort_u32(best < vr ? best : vr);
     }
     // the sequence P(y)[0:h] ++ Rev(y) ++ P(y)[h:R], deduplicated in order
     // and cut at R: segment A in lanes 0..h-1, B (the 64 smallest reverse
     // keys' sources, by (p, x)) in lanes 0..63, C in lanes 0..R-h-1
     const int32_t va = l < h ? P[y * R + l] : SG_NONE;
-    const int32_t vb = best != EMPTY_KEY ? (int32_t)(uint32_t)best : SG_NONE;
+    const int32_t vb = best != REV_EMPTY ? rev_source(best) : SG_NONE;
     const int32_t vc = l < R - h ? P[y * R + h + l] : SG_NONE;
     const int na = span_of(va), nb = span_of(vb), nc = span_of(vc);
     const bool ka = first_occurrence(va, na, SG_NONE, 0, SG_NONE, 0);
@@ -290,7 +300,7 @@ inline Layout layout(int64_t n, int R) {
     L.cnt = align_up((size_t)(n + 1) * 8, 256);
     L.off = align_up((size_t)(n + 1) * 8, 256);
     L.fillc = align_up((size_t)(n + 1) * 8, 256);
-    L.rev = align_up((size_t)n * R * 8, 256);
+    L.rev = align_up((size_t)n * R * 4, 256);
     L.scan = align_up(exclusive_scan_tmp_bytes(n), 256);
     L.total = L.P + L.cnt + L.off + L.fillc + L.rev + L.scan + 1024;
     return L;
@@ -312,7 +322,7 @@ extern "C" sg_status sg_prune_workspace_size(int64_t n, int32_t K, int32_t R, si
 extern "C" sg_status sg_prune(const int32_t* knn, int64_t n, int32_t K, int32_t R, const int32_t* order,
                               int32_t* out, void* ws, size_t ws_bytes, void* stream) {
     return guarded([&] {
-        SG_REQUIRE(n >= 0 && n < (1ll << 31), "n out of range");
+        SG_REQUIRE(n >= 0 && n <= MAX_ROWS, "n out of range (at most 2^26 - 1024 rows)");
         SG_REQUIRE(K >= 1 && K <= 256, "K must be in 1..256");
         SG_REQUIRE(R >= 1 && R <= K && R <= 64, "R must be in 1..min(K, 64)");
         if (n == 0) return;
@@ -328,7 +338,7 @@ extern "C" sg_status sg_prune(const int32_t* knn, int64_t n, int32_t K, int32_t 
         int64_t* cnt = cv.take<int64_t>(n + 1);
         int64_t* off = cv.take<int64_t>(n + 1);
         int64_t* fillc = cv.take<int64_t>(n + 1);
-        uint64_t* rev = cv.take<uint64_t>((size_t)n * R);
+        uint32_t* rev = cv.take<uint32_t>((size_t)n * R);
         void* scan_tmp = cv.take<char>(exclusive_scan_tmp_bytes(n));
 
         unsigned grid = (unsigned)cdiv(n, prune::WAVES);

@@ -229,7 +229,7 @@ extern "C" sg_status sg_search(const void* X, sg_dtype dtype, int64_t n, int32_t
                                int32_t* out_ids, float* out_dist, void* ws, size_t ws_bytes,
                                void* stream) {
     return guarded([&] {
-        SG_REQUIRE(n >= 1 && n < (1ll << 31), "n out of range");
+        SG_REQUIRE(n >= 1 && n <= MAX_ROWS, "n out of range (at most 2^26 - 1024 rows)");
         SG_REQUIRE(d >= 1 && d <= search::MAX_D, "d must be in 1..1024");
         SG_REQUIRE(ld >= d && ldq >= d, "ld and ldq must be >= d");
         SG_REQUIRE(metric == SG_L2 || metric == SG_IP, "unknown metric");
@@ -237,7 +237,7 @@ extern "C" sg_status sg_search(const void* X, sg_dtype dtype, int64_t n, int32_t
         SG_REQUIRE(max_degree >= 1 && max_degree <= search::MAX_DEG, "max_degree must be in 1..256");
         SG_REQUIRE(topk >= 1 && topk <= L && L <= search::MAX_L, "need 1 <= topk <= L <= 512");
         SG_REQUIRE(entry < n, "entry out of range");
-        SG_REQUIRE(nq >= 0, "nq must be >= 0");
+        SG_REQUIRE(nq >= 0 && nq <= MAX_ROWS, "nq out of range (at most 2^26 - 1024 queries)");
         if (nq == 0) return;
         SG_REQUIRE(X && graph && Q && out_ids, "NULL pointer");
         search::Layout Ly = search::layout(n, d, nq);

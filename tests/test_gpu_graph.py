@@ -105,6 +105,16 @@ def test_prune_rows_whose_table_cannot_settle():
     np.testing.assert_array_equal(_prune_gpu(knn, R), oracle.prune(knn, R))
 
 
+def test_prune_rejects_more_rows_than_one_call_takes():
+    # wavefront-per-row launches hold 64 work-items per row and a dispatch
+    # fewer than 2^32: the entry point refuses 2^26 rows before any launch
+    knn = torch.full((1 << 26, 1), -1, dtype=torch.int32, device=DEV)
+    with pytest.raises(sg.SgError, match="n out of range"):
+        sg.sg_prune(knn, 1)
+    del knn
+    torch.cuda.empty_cache()
+
+
 def _merge_gpu(off, mem, graphs, R, n_global, cap):
     out, deg = sg.sg_merge(off, torch.from_numpy(np.asarray(mem, np.int32)).to(DEV),
                            torch.from_numpy(np.asarray(graphs, np.int32)).to(DEV), R, n_global, cap)
