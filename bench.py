@@ -381,6 +381,18 @@ def run_precision(args):
             return sg.sg_merge(soffs, mem_share, graphs, R, N, omega * R)
         return step
 
+    # launch-shape autotuning per form (outside the timed region), on the largest
+    # shard of each power-of-two size bucket present
+    buckets = {}
+    for i_, n_ in enumerate(sizes):
+        b_ = int(n_).bit_length() - 1
+        if b_ not in buckets or n_ > sizes[buckets[b_]]:
+            buckets[b_] = i_
+    tuned = {f: {"2^%d" % b_: sg.sg_knn_autotune(shards[i_], K, "ip", prec_, rerank=rr_)
+                 for b_, i_ in sorted(buckets.items())}
+             for f, prec_, rr_ in (("bf16", "bf16", C), ("fp8", "fp8", C))}
+    log("autotune %s" % tuned)
+
     res, lists = {}, {}
     for form, prec, rr in (("bf16", "bf16", C), ("fp8", "fp8", C), ("fp32", "fp32", 0)):
         steps = args.steps if form != "fp32" else max(1, min(args.steps, 2))
@@ -423,6 +435,7 @@ def run_precision(args):
                      "kernel_ms_avg": ch["kernel_ms_avg"]},
         "cpu_baseline": None,
         "forms": res, "recall_at_64_vs_plain": recall, "vs_fp64_oracle_100_rows": err,
+        "autotune": tuned,
         "chosen_vs_plain": ch["vps"] / res["fp32"]["vps"],
     }
     print(json.dumps(line), flush=True)
