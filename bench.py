@@ -346,7 +346,9 @@ def run_precision(args):
     """Precision form: N = 4M unit-norm rows, d = 96, 2000-component mixture (std 0.15), IP;
     k-means into 13 shards with omega = 2; one GPU's share = shards 0..7 (~600k rows each);
     BF16 / FP8 distance keys with an FP32 re-rank of the top 128 (FP8 also of the top 256) to
-    K = 64, prune to R = 32, merge; against the plain FP32 build of the same share."""
+    K = 64, prune to R = 32, merge; against the plain FP32 build of the same share.  The share's
+    shards are built in one batched pass (re-rank included); the 256-wide re-rank, wider than the
+    batched pass takes, runs shard by shard."""
     import torch
 
     import oracle
@@ -373,7 +375,18 @@ def run_precision(args):
     mem_share = mem[:offs[share]]
     flops = float(sum(2.0 * d * float(n) * float(n) for n in sizes))
 
+    Xshare = torch.cat(shards)               # the share's shard rows back to back (offsets soffs)
+    knn_share = torch.empty((total, K), dtype=torch.int32, device=dev)
+
     def make_step(prec, rerank):
+        if rerank <= 128:
+            # all shards of the share in one batched pass (re-rank included)
+            def step():
+                sg.sg_knn_graph_batched(Xshare, soffs, K, R, "ip", prec, out=(graphs, knn_share), rerank=rerank)
+                return sg.sg_merge(soffs, mem_share, graphs, R, N, omega * R)
+            return step
+
+        # a re-rank wider than the batched pass takes: one launch per shard
         def step():
             for s_, Xs in enumerate(shards):
                 sg.sg_knn_graph(Xs, K, "ip", prec, rerank=rerank, out=(nbrs[s_], None))
@@ -403,7 +416,8 @@ def run_precision(args):
         ach = flops * steps / (kms / 1e3) / 1e12
         res[form] = dict(sec=sec, vps=N * (share / S) / sec, shard_rows_ps=total / sec, tflops=ach,
                          frac=ach / PEAK[prec], kernel_ms_avg=kms / max(launches, 1), prec=prec, rerank=rr)
-        lists[form] = [nb[:2000].clone() for nb in nbrs[:2]]
+        lists[form] = ([knn_share[soffs[i]:soffs[i] + 2000].clone() for i in range(2)] if rr <= 128
+                       else [nb[:2000].clone() for nb in nbrs[:2]])
         log("%s: %.3f s/step, %.1f TFLOP/s" % (form, sec, ach))
 
     # recall@64 of the reduced forms against the plain FP32 build (same shards, sampled rows)

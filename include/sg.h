@@ -171,7 +171,9 @@ sg_status sg_knn_rows(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64
  *    graphs[offsets_h[s] + i][0..R)  pruned list of local row i of shard s,
  *    knn   [offsets_h[s] + i][0..k)  its kNN list (knn may be NULL).
  * k in 1..128, R in 1..min(k, 64); rows need a register-resident distance
- * kernel (FP32 d <= 128, 16-bit d <= 768, FP8 d <= 1024).  The distance work
+ * kernel (FP32 d <= 128, 16-bit d <= 768, FP8 d <= 1024).  rerank: 0, or a
+ * candidate width c in k..128 as in sg_knn_graph (the c best by the prec
+ * key, re-ranked by exact FP32 distance to the k lists).  The distance work
  * of all shards is one persistent launch (largest shards first); the launch
  * shape is the one sg_knn_autotune recorded for the largest shard, else the
  * default.
@@ -186,11 +188,11 @@ sg_status sg_knn_rows(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64
  * ---------------------------------------------------------------------- */
 typedef struct sg_batch_plan sg_batch_plan;
 sg_status sg_knn_graph_batched_workspace_size(const int64_t* offsets_h, int32_t S, int32_t d, int32_t k,
-                                              int32_t R, sg_prec prec, size_t* bytes);
+                                              int32_t R, sg_prec prec, int32_t rerank, size_t* bytes);
 sg_status sg_knn_graph_batched(const void* X, sg_dtype dtype, int32_t d, int64_t ld,
                                const int64_t* offsets_h, int32_t S, sg_metric metric, int32_t k,
-                               int32_t R, sg_prec prec, int32_t* graphs, int32_t* knn, void* ws,
-                               size_t ws_bytes, void* stream, sg_batch_plan** plan);
+                               int32_t R, sg_prec prec, int32_t rerank, int32_t* graphs, int32_t* knn,
+                               void* ws, size_t ws_bytes, void* stream, sg_batch_plan** plan);
 void sg_batch_plan_destroy(sg_batch_plan* plan);
 
 /* ------------------------------------------------------------------------

@@ -71,8 +71,8 @@ _SIGS = {
     "sg_knn_variant_count": (i32, [i32, i32, i32, C.POINTER(C.c_int32)]),
     "sg_knn_autotune": (i32, [vp, i32, i64, i32, i64, i32, i32, i32, i32, vp, sz, vp, vp, vp, i32]),
     "sg_knn_force_variant": (i32, [i32]),
-    "sg_knn_graph_batched_workspace_size": (i32, [vp, i32, i32, i32, i32, i32, psz]),
-    "sg_knn_graph_batched": (i32, [vp, i32, i32, i64, vp, i32, i32, i32, i32, i32, vp, vp, vp, sz, vp,
+    "sg_knn_graph_batched_workspace_size": (i32, [vp, i32, i32, i32, i32, i32, i32, psz]),
+    "sg_knn_graph_batched": (i32, [vp, i32, i32, i64, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, sz, vp,
                                    C.POINTER(C.c_void_p)]),
     "sg_batch_plan_destroy": (None, [vp]),
     "sg_knn_graph_learned_workspace_size": (i32, [i64, i32, i32, psz]),
@@ -232,7 +232,7 @@ class BatchPlan:
 
 
 def sg_knn_graph_batched(X, offsets, k, R, metric="l2", prec="fp32", knn=True, out=None, stream=None,
-                         plan=None):
+                         plan=None, rerank=0):
     """Pruned graphs (and kNN lists) of the shards X[offsets[s]:offsets[s+1]]:
     (graphs int32 [n, R], knn int32 [n, k] or None), ids local to each shard."""
     L = lib()
@@ -241,7 +241,7 @@ def sg_knn_graph_batched(X, offsets, k, R, metric="l2", prec="fp32", knn=True, o
     S = off.size - 1
     offp = off.ctypes.data_as(C.c_void_p)
     m, p = METRICS[metric], PRECS[prec]
-    nbytes = _size(L.sg_knn_graph_batched_workspace_size, offp, S, d, k, R, p)
+    nbytes = _size(L.sg_knn_graph_batched_workspace_size, offp, S, d, k, R, p, rerank)
     ws = _ws.get(nbytes, X.device, "batched")
     if out is not None:
         graphs, kn = out
@@ -249,7 +249,8 @@ def sg_knn_graph_batched(X, offsets, k, R, metric="l2", prec="fp32", knn=True, o
         graphs = torch.empty((int(off[-1]), R), dtype=torch.int32, device=X.device)
         kn = torch.empty((int(off[-1]), k), dtype=torch.int32, device=X.device) if knn else None
     pp = C.byref(plan.ptr) if plan is not None else None
-    _check("sg_knn_graph_batched", L.sg_knn_graph_batched(_ptr(X), dt, d, ld, offp, S, m, k, R, p, _ptr(graphs),
+    _check("sg_knn_graph_batched", L.sg_knn_graph_batched(_ptr(X), dt, d, ld, offp, S, m, k, R, p, rerank,
+                                                          _ptr(graphs),
                                                           _ptr(kn), _ptr(ws), ws.numel(), _stream(stream), pp))
     return graphs, kn
 

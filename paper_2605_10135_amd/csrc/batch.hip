@@ -203,23 +203,26 @@ struct BatchedMaker {
 struct Plan {
     Shards sh{};
     int S = 0, ksel = 0, DP = 0, eb = 0, nitems = 0;
+    int rerank = 0;   // FP32 re-rank width (0: none)
     int64_t n_all = 0, n_max = 0;
     BKern kern;
     size_t prune_bytes = 0, scan_bytes = 0, total = 0;
 };
 
-Plan make_plan(const int64_t* off, int S, int d, int k, int R, int prec) {
+Plan make_plan(const int64_t* off, int S, int d, int k, int R, int prec, int rerank) {
     SG_REQUIRE(S >= 1 && S <= MAXS, "S must be in 1..64");
     SG_REQUIRE(off != nullptr, "offsets_h is NULL");
     SG_REQUIRE(off[0] == 0, "offsets_h[0] must be 0");
     SG_REQUIRE(d >= 1 && d <= 1024, "d out of range");
     SG_REQUIRE(k >= 1 && k <= 128, "k must be in 1..128 for the batched build");
+    SG_REQUIRE(rerank == 0 || (rerank >= k && rerank <= 128), "rerank must be 0 or in k..128 for the batched build");
     SG_REQUIRE(R >= 1 && R <= k && R <= 64, "R must be in 1..min(k, 64)");
     SG_REQUIRE(prec >= SG_PREC_FP32 && prec <= SG_PREC_FP8, "unknown precision");
     Plan p;
     p.S = S;
     p.sh.S = S;
-    p.ksel = ksel_for(k) < 64 ? 64 : ksel_for(k);
+    p.rerank = rerank == k ? 0 : rerank;
+    p.ksel = std::max(64, ksel_for(p.rerank > 0 ? p.rerank : k));
     for (int s = 0; s < S; ++s) {
         SG_REQUIRE(off[s + 1] >= off[s], "offsets_h must be non-decreasing");
         SG_REQUIRE(off[s + 1] - off[s] < (int64_t(1) << 31), "shard too large");
@@ -351,7 +354,7 @@ void enqueue(const Plan& p, const void* X, int dtype, int d, int64_t ld, int met
     A.qmul = qmul;
     A.osc = osc;
     A.state = state;
-    A.nbr = knn;
+    A.nbr = p.rerank > 0 ? nullptr : knn;   // with a re-rank the lists come from the FP32 pass
     A.dist = nullptr;
     A.k_out = k;
     int dev = 0, cus = 0, per_cu = 0;
@@ -364,6 +367,9 @@ void enqueue(const Plan& p, const void* X, int dtype, int d, int64_t ld, int met
     p.kern.fn<<<grid, p.kern.threads, 0, s>>>(A, p.sh, counter, p.nitems);
     SG_LAUNCH_CHECK();
     if (eager) profile_record(s, false);
+    if (p.rerank > 0)   // exact FP32 distances of every row's rerank candidates; padding slots are skipped
+        launch_rerank<uint64_t>(X, dtype, pad, d, ld, metric, perm, p.n_all, state, p.ksel, p.rerank, k, knn, nullptr,
+                                perm, s);
 
     const sg_status pr = sg_prune(knn, p.n_all, k, R, order, graphs, prune_ws, p.prune_bytes, s);
     if (pr != SG_OK) throw Fail{pr};
@@ -400,6 +406,7 @@ std::vector<uint8_t> signature(const void* X, int dtype, int d, int64_t ld, cons
     put(&ws_bytes, sizeof ws_bytes);
     put(&s, sizeof s);
     put(&p.kern.fn, sizeof p.kern.fn);
+    put(&p.rerank, sizeof p.rerank);
     return v;
 }
 
@@ -409,20 +416,20 @@ std::vector<uint8_t> signature(const void* X, int dtype, int d, int64_t ld, cons
 using namespace sg;
 
 extern "C" sg_status sg_knn_graph_batched_workspace_size(const int64_t* offsets_h, int32_t S, int32_t d, int32_t k,
-                                                         int32_t R, sg_prec prec, size_t* bytes) {
+                                                         int32_t R, sg_prec prec, int32_t rerank, size_t* bytes) {
     return guarded([&] {
         SG_REQUIRE(bytes != nullptr, "bytes is NULL");
-        *bytes = batch::make_plan(offsets_h, S, d, k, R, prec).total;
+        *bytes = batch::make_plan(offsets_h, S, d, k, R, prec, rerank).total;
     });
 }
 
 extern "C" sg_status sg_knn_graph_batched(const void* X, sg_dtype dtype, int32_t d, int64_t ld,
                                           const int64_t* offsets_h, int32_t S, sg_metric metric, int32_t k,
-                                          int32_t R, sg_prec prec, int32_t* graphs, int32_t* knn, void* ws,
-                                          size_t ws_bytes, void* stream, sg_batch_plan** plan) {
+                                          int32_t R, sg_prec prec, int32_t rerank, int32_t* graphs, int32_t* knn,
+                                          void* ws, size_t ws_bytes, void* stream, sg_batch_plan** plan) {
     return guarded([&] {
-        const batch::Plan p = batch::make_plan(offsets_h, S, d, k, R, prec);
-        knn::check_args(X, dtype, p.n_all, d, ld, metric, k, prec, 0);
+        const batch::Plan p = batch::make_plan(offsets_h, S, d, k, R, prec, rerank);
+        knn::check_args(X, dtype, p.n_all, d, ld, metric, k, prec, p.rerank);
         SG_REQUIRE(graphs != nullptr, "graphs is NULL");
         if (ws == nullptr || ws_bytes < p.total) {
             set_error("sg_knn_graph_batched: workspace too small (need " + std::to_string(p.total) + " bytes)");

@@ -1086,10 +1086,12 @@ __device__ inline int32_t cand_id(uint64_t key) { return key_id(key); }
 __device__ inline int32_t cand_id(int32_t id) { return id; }
 
 // Sort the candidate keys of row i (element p*64 + l in lane l of v[p]),
-// drop repeated ids, write the best k to output row o (SG_NONE / +inf pad).
+// drop repeated ids, write the best k to output row o (SG_NONE / +inf pad;
+// nothing for o < 0).
 template <int PER>
 __device__ void rerank_finish(uint64_t (&v)[PER], int64_t o, int k, int32_t* __restrict__ nbr,
                               float* __restrict__ dist) {
+    if (o < 0) return;   // a padding slot of a batched layout (wave-uniform)
     const int l = lane_id();
     wave_sort_multi<PER>(v);
     // a repeated candidate id gives equal adjacent keys: keep the first copy

@@ -50,6 +50,29 @@ def test_batched_equals_per_shard_and_oracle_u8(prec):
         np.testing.assert_array_equal(knn_h[a:b], onbr, err_msg="shard %d" % s)
 
 
+@pytest.mark.parametrize("prec,rerank", [("bf16", 64), ("fp8", 128)])
+def test_batched_rerank_equals_per_shard(prec, rerank):
+    # reduced-precision keys, the best `rerank` re-ranked in FP32: the same
+    # candidate sets and the same exact re-rank as the single-shard path
+    sizes = [2500, 5200, 0, 900]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    X = synthdata.deep_like_unit(n=int(offs[-1]), d=96, seed=23)
+    Xg = torch.from_numpy(X).to(DEV)
+    k, R = 32, 16
+    graphs, knn = sg.sg_knn_graph_batched(Xg, offs, k, R, "ip", prec, rerank=rerank)
+    torch.cuda.synchronize()
+    g, kn = [], []
+    for s in range(len(sizes)):
+        a, b = offs[s], offs[s + 1]
+        if b == a:
+            continue
+        nb, _ = sg.sg_knn_graph(Xg[a:b], k, "ip", prec, rerank=rerank, dist=False)
+        kn.append(nb)
+        g.append(sg.sg_prune(nb, R))
+    assert torch.equal(knn, torch.cat(kn))
+    assert torch.equal(graphs, torch.cat(g))
+
+
 def test_batched_f16_ip_d768_equals_per_shard():
     sizes = [1500, 3200, 800, 4300]
     offs = np.concatenate([[0], np.cumsum(sizes)])
@@ -106,5 +129,7 @@ def test_batched_argument_errors():
         sg.sg_knn_graph_batched(Xg, [5, 50, 100], 8, 4)           # offsets[0] != 0
     with pytest.raises(sg.SgError):
         sg.sg_knn_graph_batched(Xg, [0, 50, 100], 200, 4)         # k > 128
+    with pytest.raises(sg.SgError):
+        sg.sg_knn_graph_batched(Xg, [0, 50, 100], 32, 4, rerank=256)   # re-rank wider than 128
     with pytest.raises(sg.SgError):
         sg.sg_knn_graph_batched(Xg, list(range(0, 66)), 8, 4)     # S > 64
