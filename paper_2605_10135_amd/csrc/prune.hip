@@ -220,16 +220,15 @@ __global__ void scatter_kernel(const int32_t* __restrict__ P, int64_t total, int
     }
 }
 
-// Keeps, of one value per lane (SG_NONE = absent), those that neither an
-// earlier lane of the same segment nor any lane of the earlier segments
-// e0[0..n0) / e1[0..n1) holds: the in-order deduplication of a segment, by
-// broadcasting each compared value from its lane (no LDS round trips).
-__device__ inline bool first_occurrence(int32_t v, int nv, int32_t e0, int n0, int32_t e1, int n1) {
-    const int l = lane_id();
+// Keeps, of one value per lane (SG_NONE = absent), those that no lane of the
+// earlier segment e[0..ne) holds, by broadcasting each compared value from its
+// lane (no LDS round trips).  This is all the in-order deduplication needs:
+// P(y) lists distinct ids (its kNN row does), so its head and tail share no
+// id and neither repeats one, and each row x adds y to its own list at most
+// once, so Rev(y) repeats no source either.
+__device__ inline bool first_occurrence(int32_t v, int32_t e, int ne) {
     bool keep = v != SG_NONE;
-    for (int t = 0; t < n0; ++t) keep &= v != __builtin_amdgcn_readlane(e0, t);
-    for (int t = 0; t < n1; ++t) keep &= v != __builtin_amdgcn_readlane(e1, t);
-    for (int t = 0; t < nv; ++t) keep &= !(t < l && v == __builtin_amdgcn_readlane(v, t));
+    for (int t = 0; t < ne; ++t) keep &= v != __builtin_amdgcn_readlane(e, t);
     return keep;
 }
 
@@ -268,10 +267,9 @@ __global__ __launch_bounds__(256) void combine_kernel(const int32_t* __restrict_
     const int32_t va = l < h ? P[y * R + l] : SG_NONE;
     const int32_t vb = best != REV_EMPTY ? rev_source(best) : SG_NONE;
     const int32_t vc = l < R - h ? P[y * R + h + l] : SG_NONE;
-    const int na = span_of(va), nb = span_of(vb), nc = span_of(vc);
-    const bool ka = first_occurrence(va, na, SG_NONE, 0, SG_NONE, 0);
-    const bool kb = first_occurrence(vb, nb, va, na, SG_NONE, 0);
-    const bool kc = first_occurrence(vc, nc, va, na, vb, nb);
+    const bool ka = va != SG_NONE;
+    const bool kb = first_occurrence(vb, va, span_of(va));
+    const bool kc = first_occurrence(vc, vb, span_of(vb));
     const uint64_t below = (1ull << l) - 1;
     const uint64_t ma = __builtin_amdgcn_ballot_w64(ka), mb = __builtin_amdgcn_ballot_w64(kb),
                    mc = __builtin_amdgcn_ballot_w64(kc);
