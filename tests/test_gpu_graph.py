@@ -74,6 +74,15 @@ def test_prune_hub_in_degree():
     np.testing.assert_array_equal(_prune_gpu(knn, 8), oracle.prune(knn, 8))
 
 
+@pytest.mark.parametrize("n,half,R", [(500, 8, 8), (500, 8, 16), (130, 32, 21), (70, 32, 64)])
+def test_prune_symmetric_graph(n, half, R):
+    # circulant graph, offsets +-1..+-half by |offset|: every edge is mutual, so
+    # Rev(y) repeats most of P(y) and the in-order deduplication decides F(y)
+    offs = [s * o for o in range(1, half + 1) for s in (1, -1)]
+    knn = (np.arange(n)[:, None] + np.array(offs)[None, :]) % n
+    np.testing.assert_array_equal(_prune_gpu(knn.astype(np.int32), R), oracle.prune(knn.astype(np.int32), R))
+
+
 def _cuckoo_slots(z, ct=256):
     """The two table slots the detour kernel's row hash gives id z (K <= 64)."""
     z = np.asarray(z, np.uint64)
