@@ -14,10 +14,11 @@
 //    and counts, for every position j, the i < j whose list holds y_j before
 //    position j.  Positions are ranked by (detour, j) (a wave sort of the
 //    keys) and the first R written: P(x); the in-degree histogram of P is
-//    counted as they are written.
+//    counted as they are written, and the count an edge x -> y reads is kept
+//    as its slot in y's reverse list.
 //  * exclusive scan of the in-degrees, scatter of the 32-bit reverse keys
-//    (p << 26 | x) per target in arbitrary slot order (the next pass sorts,
-//    so the output does not depend on it).
+//    (p << 26 | x) to those slots (no atomics; the slot order depends on
+//    timing, but the next pass sorts, so the output does not).
 //  * combine_kernel: one wave per row y: the R smallest reverse keys (wave
 //    bitonic sort, chunked for high in-degree), then the list
 //    P(y)[0:h] ++ Rev(y) ++ P(y)[h:R] is deduplicated in order (values
@@ -53,7 +54,8 @@ __device__ inline uint32_t cuckoo_h1(uint32_t m) { return ((m * 0x85EBCBu) >> 16
 template <int KP, int CT>
 __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__ knn, int64_t n,
                                                      int K, int R, const int32_t* __restrict__ order,
-                                                     int32_t* __restrict__ P, int64_t* __restrict__ cnt) {
+                                                     int32_t* __restrict__ P, int32_t* __restrict__ rslot,
+                                                     int64_t* __restrict__ cnt) {
     __shared__ uint64_t s_t[WAVES][2 * CT];
     __shared__ int32_t s_det[WAVES][64 * KP + 64];   // + one discard slot per lane
     __shared__ int32_t s_nx[WAVES][64 * KP];
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
         if (l < R) {
             const int32_t v = key == EMPTY_KEY ? SG_NONE : nx[key & 1023];
             P[x * R + l] = v;
-            if (v != SG_NONE) atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[v]), 1ull);
+            if (v != SG_NONE) rslot[x * R + l] = (int32_t)atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[v]), 1ull);
         }
     } else {
         int nvalid = 0;
@@ -189,7 +191,7 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
             }
             if (rank < R) {
                 P[x * R + rank] = y[t];
-                atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[y[t]]), 1ull);
+                rslot[x * R + rank] = (int32_t)atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[y[t]]), 1ull);
             }
         }
         for (int r = nvalid + l; r < R; r += 64) P[x * R + r] = SG_NONE;
@@ -206,8 +208,11 @@ constexpr uint32_t REV_EMPTY = ~0u;
 __device__ inline uint32_t rev_key(int p, int64_t x) { return ((uint32_t)p << REV_XBITS) | (uint32_t)x; }
 __device__ inline int32_t rev_source(uint32_t k) { return (int32_t)(k & ((1u << REV_XBITS) - 1)); }
 
-__global__ void scatter_kernel(const int32_t* __restrict__ P, int64_t total, int R,
-                               const int64_t* __restrict__ off, int64_t* __restrict__ fillc,
+// Edge e = x * R + p (P[e] = y) goes to rev[off[y] + rslot[e]]: rslot[e] is the
+// in-degree count of y that the edge read when the detour pass counted it, so
+// the slots of y's edges are 0 .. in-degree(y) - 1, each taken once.
+__global__ void scatter_kernel(const int32_t* __restrict__ P, const int32_t* __restrict__ rslot,
+                               int64_t total, int R, const int64_t* __restrict__ off,
                                uint32_t* __restrict__ rev) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -215,8 +220,7 @@ __global__ void scatter_kernel(const int32_t* __restrict__ P, int64_t total, int
         if (y == SG_NONE) continue;
         int64_t x = e / R;
         int p = (int)(e - x * R);
-        unsigned long long slot = atomicAdd(reinterpret_cast<unsigned long long*>(&fillc[y]), 1ull);
-        rev[off[y] + (int64_t)slot] = rev_key(p, x);
+        rev[off[y] + rslot[e]] = rev_key(p, x);
     }
 }
 
@@ -289,18 +293,18 @@ __global__ __launch_bounds__(256) void combine_kernel(const int32_t* __restrict_
 }
 
 struct Layout {
-    size_t P, cnt, off, fillc, rev, scan, total;
+    size_t P, rslot, cnt, off, rev, scan, total;
 };
 
 inline Layout layout(int64_t n, int R) {
     Layout L;
     L.P = align_up((size_t)n * R * 4, 256);
+    L.rslot = align_up((size_t)n * R * 4, 256);
     L.cnt = align_up((size_t)(n + 1) * 8, 256);
     L.off = align_up((size_t)(n + 1) * 8, 256);
-    L.fillc = align_up((size_t)(n + 1) * 8, 256);
     L.rev = align_up((size_t)n * R * 4, 256);
     L.scan = align_up(exclusive_scan_tmp_bytes(n), 256);
-    L.total = L.P + L.cnt + L.off + L.fillc + L.rev + L.scan + 1024;
+    L.total = L.P + L.rslot + L.cnt + L.off + L.rev + L.scan + 1024;
     return L;
 }
 
@@ -333,26 +337,25 @@ extern "C" sg_status sg_prune(const int32_t* knn, int64_t n, int32_t K, int32_t 
         hipStream_t s = as_stream(stream);
         Carver cv(ws);
         int32_t* P = cv.take<int32_t>((size_t)n * R);
+        int32_t* rslot = cv.take<int32_t>((size_t)n * R);
         int64_t* cnt = cv.take<int64_t>(n + 1);
         int64_t* off = cv.take<int64_t>(n + 1);
-        int64_t* fillc = cv.take<int64_t>(n + 1);
         uint32_t* rev = cv.take<uint32_t>((size_t)n * R);
         void* scan_tmp = cv.take<char>(exclusive_scan_tmp_bytes(n));
 
         unsigned grid = (unsigned)cdiv(n, prune::WAVES);
         fill<int64_t>(cnt, 0, n + 1, s);
-        fill<int64_t>(fillc, 0, n + 1, s);
         if (K <= 64)
-            prune::detour_kernel<1, 256><<<grid, 256, 0, s>>>(knn, n, K, R, order, P, cnt);
+            prune::detour_kernel<1, 256><<<grid, 256, 0, s>>>(knn, n, K, R, order, P, rslot, cnt);
         else if (K <= 128)
-            prune::detour_kernel<2, 512><<<grid, 256, 0, s>>>(knn, n, K, R, order, P, cnt);
+            prune::detour_kernel<2, 512><<<grid, 256, 0, s>>>(knn, n, K, R, order, P, rslot, cnt);
         else
-            prune::detour_kernel<4, 1024><<<grid, 256, 0, s>>>(knn, n, K, R, order, P, cnt);
+            prune::detour_kernel<4, 1024><<<grid, 256, 0, s>>>(knn, n, K, R, order, P, rslot, cnt);
         SG_LAUNCH_CHECK();
         int64_t total = n * (int64_t)R;
         unsigned eg = (unsigned)std::min<int64_t>(cdiv(total, 256), 8192);
         exclusive_scan_i64(cnt, off, n, scan_tmp, s);
-        prune::scatter_kernel<<<eg, 256, 0, s>>>(P, total, R, off, fillc, rev);
+        prune::scatter_kernel<<<eg, 256, 0, s>>>(P, rslot, total, R, off, rev);
         SG_LAUNCH_CHECK();
         prune::combine_kernel<<<grid, 256, 0, s>>>(P, n, R, off, rev, order, out);
         SG_LAUNCH_CHECK();
