@@ -79,11 +79,17 @@ def calib_copy(torch, dev):
     del src, dst
 
 
-def traffic_of(name):
+def traffic_of(name, variant):
     """HBM bytes per distance-kernel launch from the committed counter record of
-    this workload, or None when there is none for the current kernel sources."""
+    this workload taken with the launch shape `variant` pinned, or None when
+    there is none for that shape and the current kernel sources."""
+    import glob
     from paper_2605_10135_amd import profiling
-    return profiling.read_traffic(os.path.join(ROOT, "profiles", "dist_topk_%s_traffic.txt" % name))
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "dist_topk_%s*_traffic.txt" % name))):
+        rec = profiling.read_traffic(path)
+        if rec is not None and rec["variant"] == variant:
+            return rec
+    return None
 
 
 def main():
@@ -98,6 +104,9 @@ def main():
     ap.add_argument("--no-per-shard", action="store_true",
                     help="skip the comparison with one distance launch and one prune per shard")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--force-variant", type=int, default=None,
+                    help="after tuning, pin every distance launch to this launch-shape index "
+                         "(counter runs use it to measure the shape a timed run chose)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--queries", type=int, default=10_000)
     ap.add_argument("--workload", default="sift1m", choices=["sift1m", "precision", "batched", "learned"])
@@ -162,6 +171,11 @@ def main():
     tuned = {f: {b_: sg.sg_knn_autotune(shards[i_], K, "l2", f) for b_, i_ in sorted(buckets.items())}
              for f in forms}
     log("autotune %s" % tuned)
+    # the batched pass launches the shape chosen for its largest shard
+    variant = tuned[args.chosen][int(max(sizes)).bit_length() - 1][0]
+    if args.force_variant is not None:
+        sg.sg_knn_force_variant(args.force_variant)
+        variant = args.force_variant
     res = {}
     graph_of = {}
     for form in forms:
@@ -290,7 +304,7 @@ def main():
 
     ch = res[args.chosen]
     prec = args.chosen
-    traf = traffic_of("sift1m_u8") if prec == "f16" else None
+    traf = traffic_of("sift1m_u8", variant) if prec == "f16" else None
     # algorithmic bytes: each shard's rows read once as 16-bit operands, the
     # K-list of ids written once
     alg_bytes = float(sum(float(n) * (2 * d + 4 * K) for n in sizes))
@@ -317,6 +331,8 @@ def main():
                      "traffic": traf["bytes"] if traf else None,
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "dist_topk_batched_kernel (all 16 shards in one launch)",
+                     "variant": variant,
+                     "traffic_kernel": traf["kernels"] if traf else None,
                      "kernel_ms_avg": ch["kernel_ms_avg"],
                      "flops_per_launch_avg": flops * args.steps / max(ch["launches"], 1),
                      "algorithmic_bytes_per_launch_avg": alg_bytes * args.steps / max(ch["launches"], 1)},

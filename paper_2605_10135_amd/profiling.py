@@ -78,7 +78,10 @@ def _calib(vals: dict):
 
 
 def traffic(fetch_csv: str, write_csv: str, out: str, fetch_cmd: str, write_cmd: str,
-            kernel: str = DIST_KERNEL) -> None:
+            kernel: str = DIST_KERNEL, variant: str = "") -> None:
+    """Writes the traffic record; `variant` is the launch-shape index the
+    counter runs pinned (bench.py --force-variant), matched against the index a
+    timed run chose before its record is used."""
     f, w = counter_values(fetch_csv, "FETCH_SIZE"), counter_values(write_csv, "WRITE_SIZE")
     (ck, cf), (_, cw) = _calib(f), _calib(w)
     ffac = CALIB_BYTES / (cf * 1024.0)
@@ -91,6 +94,7 @@ def traffic(fetch_csv: str, write_csv: str, out: str, fetch_cmd: str, write_cmd:
         "# HBM traffic of the distance kernel (rocprofv3 --pmc, mean per dispatch of the kernels named below)",
         "kernel_filter: %s" % kernel,
         "kernels: %s" % "; ".join(names),
+    ] + (["variant: %d" % int(variant)] if variant != "" else []) + [
         "dispatches: %d" % dn,
         "calibration_kernel: %s (largest dispatch; %d bytes read, %d written)" % (ck, CALIB_BYTES, CALIB_BYTES),
         "fetch_kib_raw: %.1f" % dfetch,
@@ -166,7 +170,9 @@ def read_traffic(path: str):
         return {"bytes": float(rec["traffic_bytes_per_launch"]),
                 "fetch_bytes": float(rec["fetch_bytes_per_launch"]),
                 "write_bytes": float(rec["write_bytes_per_launch"]),
-                "fetch_factor": float(rec["fetch_factor"]), "write_factor": float(rec["write_factor"])}
+                "fetch_factor": float(rec["fetch_factor"]), "write_factor": float(rec["write_factor"]),
+                "variant": int(rec["variant"]) if "variant" in rec else None,
+                "kernels": rec.get("kernels", "")}
     except (KeyError, ValueError):
         return None
 
@@ -193,7 +199,7 @@ if __name__ == "__main__":
     if len(sys.argv) >= 5 and sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif len(sys.argv) >= 7 and sys.argv[1] == "traffic":
-        traffic(*sys.argv[2:8])
+        traffic(*sys.argv[2:9])
     elif len(sys.argv) >= 8 and sys.argv[1] == "integer":
         integer_table(*sys.argv[2:8])
     else:
