@@ -64,3 +64,26 @@ def test_integer_table_lists_each_filtered_kernel(tmp_path):
     assert det[1] == "2" and det[2] == "%.1f" % (3072 * 1024 / 1e6) and det[3] == "%.1f" % (1024 * 1024 / 1e6)
     assert det[4] == "2.000"
     assert os.path.exists(out)
+
+
+def test_bench_takes_the_record_of_the_shape_it_chose(tmp_path, monkeypatch):
+    # one record per pinned launch shape; the bench line takes the one whose
+    # variant is the shape its autotuner chose, and none for an unrecorded shape
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    calib_kib = profiling.CALIB_BYTES / 1024.0
+    (tmp_path / "profiles").mkdir()
+    for v, kib in ((2, 1000.0), (3, 3000.0)):
+        _write(tmp_path / "f.csv", "FETCH_SIZE", [("__amd_rocclr_copyBuffer", calib_kib, 10),
+                                                 ("void sg::batch::dist_topk_batched_kernel<%d>(x)" % v, kib, 10)])
+        _write(tmp_path / "w.csv", "WRITE_SIZE", [("__amd_rocclr_copyBuffer", calib_kib, 10),
+                                                  ("void sg::batch::dist_topk_batched_kernel<%d>(x)" % v, 0.0, 10)])
+        profiling.traffic(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"),
+                          str(tmp_path / "profiles" / ("dist_topk_wl_v%d_traffic.txt" % v)), "f", "w",
+                          "dist_topk_batched", str(v))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    r2, r3 = bench.traffic_of("wl", 2), bench.traffic_of("wl", 3)
+    assert r2["variant"] == 2 and r2["fetch_bytes"] == 1000.0 * 1024 and "<2>" in r2["kernels"]
+    assert r3["variant"] == 3 and r3["fetch_bytes"] == 3000.0 * 1024 and "<3>" in r3["kernels"]
+    assert bench.traffic_of("wl", 0) is None
