@@ -1,73 +1,107 @@
 """Parity helpers shared by the GPU tests (comparison logic only).
 
-kNN rows from the GPU are compared with the oracle's exact lists under the
-tie rule for floating-point data: with tau = 1e-5, a GPU row passes when
-  1. its ids are distinct and exclude the row itself,
-  2. its distances are sorted,
-  3. every GPU id outside the oracle's set has delta <= delta_K (1 + tau),
-  4. every oracle id missing from the GPU set has delta >= delta_K (1 - tau),
-  5. at every position j, |delta(gpu_j) - delta_oracle(j)| <= tau max(delta_oracle(j), floor),
-where delta is the FP64 oracle distance, delta_K the oracle's K-th distance and
-floor = 1e-6 x the median |delta_K|.  For IP the tolerance is relative to the IP
-distance -x.y itself (an FP32 dot product resolves it to ~1e-7 relative; its
-L2 form 2 + 2 delta is reported separately by l2_form_violations because an
-FP32 dot product cannot resolve that form to 1e-5 for near-duplicate rows).
-For integer-valued data the comparison is exact.
+Integer-valued rows are compared bit for bit elsewhere.  For floating-point
+rows the GPU ranks candidates by an FP32 key, so where two candidates of a row
+lie closer together than FP32 can resolve, either order is correct.  The rule
+below allows exactly that much and nothing more, with no row allowance: every
+row must pass.
+
+Error bound of one GPU distance (standard forward error analysis of a sum of
+products, u = 2^-24, gamma_n = n u / (1 - n u)).  For row i and candidate j
+with stored rows x, y (widened exactly):
+  L2 : the prep pass forms ||y||^2 and ||x||^2 (d rounded FMAs each), the
+       contraction adds the products -2 x_t y_t to the accumulator ||y||^2
+       (d more roundings), the output adds ||x||^2 (one more):
+         E(i,j) = gamma_{d+3} (2||x||^2 + 2||y||^2 + 2 sum_t |x_t y_t|)
+  IP : the contraction sums -x_t y_t from zero:
+         E(i,j) = gamma_{d+1} sum_t |x_t y_t|
+E bounds both |key(i,j) - (delta(i,j) - row constant)| and |dist_gpu - delta|;
+the FP64 oracle's own error (u = 2^-53) is added on top.
+
+A GPU row passes when
+  1. its valid ids are distinct, exclude the row, and are as many as the oracle's;
+  2. its returned distances are non-decreasing;
+  3. for every GPU id g outside the oracle's set and every oracle id m missing
+     from the GPU's set: delta(g) - delta(m) <= E(g) + E(m)  (the GPU preferred g
+     to m, so key(g) <= key(m));
+  4. at every position j: |delta(gpu_j) - delta_oracle(j)| <= 2 max E over the
+     union of both lists (order statistics of values perturbed by at most E
+     move by at most E);
+  5. every returned distance is within E of the FP64 distance of its pair.
+For integer-valued data E is far below the distance spacing, so the rule
+reduces to equality; those cases are also compared bit for bit.
 """
 import numpy as np
 
 import oracle
 
-TAU = 1e-5
+U32 = 2.0 ** -24
+U64 = 2.0 ** -53
 
 
-def l2_form(d, metric):
-    return d if metric == oracle.L2 else 2.0 + 2.0 * d
+def gamma(n, u=U32):
+    return n * u / (1.0 - n * u)
 
 
-def _mag(d):
-    return np.abs(d)
+def fp32_bound(X64, rows, cols, metric=oracle.L2):
+    """E(i, j) for rows[r] against every id cols[r, c] (SG_NONE gives +inf)."""
+    rows = np.asarray(rows, np.int64)
+    cols = np.asarray(cols, np.int64)
+    d = X64.shape[1]
+    ok = cols >= 0
+    c = np.where(ok, cols, 0)
+    xi = X64[rows]                                   # nr x d
+    absdot = np.einsum("rd,rkd->rk", np.abs(xi), np.abs(X64[c]))
+    if metric == oracle.L2:
+        n2 = (X64 * X64).sum(1)
+        mag = 2.0 * n2[rows][:, None] + 2.0 * n2[c] + 2.0 * absdot
+        e = gamma(d + 3) * mag + gamma(d + 3, U64) * mag
+    else:
+        e = gamma(d + 1) * absdot + gamma(d + 1, U64) * absdot
+    return np.where(ok, e, np.inf)
 
 
-def check_rows(X64, rows, gpu_nbr, gpu_dist, ora_nbr, ora_dist, metric=oracle.L2, tau=TAU):
+def check_rows(X64, rows, gpu_nbr, gpu_dist, ora_nbr, ora_dist, metric=oracle.L2):
+    """Rows violating the rule, as (row, reason) pairs (empty: all pass)."""
     rows = np.asarray(rows)
+    gpu_nbr = np.asarray(gpu_nbr)
+    ora_nbr = np.asarray(ora_nbr)
     K = ora_nbr.shape[1]
-    od = ora_dist
-    valid_k = np.isfinite(od[:, -1])
-    floor = 1e-6 * (np.median(np.abs(od[valid_k, -1])) if valid_k.any() else 1.0)
-    gd64 = oracle.pair_dist(X64, np.repeat(rows[:, None], K, 1), gpu_nbr, metric)
+    R2 = np.repeat(rows[:, None], K, 1)
+    gd64 = oracle.pair_dist(X64, R2, gpu_nbr, metric)
+    eg = fp32_bound(X64, rows, gpu_nbr, metric)
+    eo = fp32_bound(X64, rows, ora_nbr, metric)
     bad = []
     for r, i in enumerate(rows):
-        g = gpu_nbr[r]
-        o = ora_nbr[r]
-        gv = g[g >= 0]
-        ov = o[o >= 0]
+        g, o = gpu_nbr[r], ora_nbr[r]
+        gv, ov = g[g >= 0], o[o >= 0]
         if len(gv) != len(ov) or len(set(gv.tolist())) != len(gv) or i in gv:
             bad.append((int(i), "ids: count/distinct/self"))
             continue
+        nv = len(ov)
         if gpu_dist is not None:
-            gdist = gpu_dist[r][: len(gv)]
+            gdist = np.asarray(gpu_dist[r][:nv], np.float64)
             if np.any(np.diff(gdist) < 0):
                 bad.append((int(i), "gpu distances not sorted"))
                 continue
-        if len(ov) == 0:
+            if np.any(np.abs(gdist - gd64[r][:nv]) > eg[r][:nv]):
+                bad.append((int(i), "returned distance outside the FP32 bound"))
+                continue
+        if nv == 0:
             continue
-        dK = od[r, len(ov) - 1]
-        extra = set(gv.tolist()) - set(ov.tolist())
-        missing = set(ov.tolist()) - set(gv.tolist())
+        gpos = {v: k for k, v in enumerate(g[:nv].tolist())}
+        opos = {v: k for k, v in enumerate(o[:nv].tolist())}
+        extra = [gpos[v] for v in gpos if v not in opos]
+        missing = [opos[v] for v in opos if v not in gpos]
         if extra:
-            dx = gd64[r][[k for k, v in enumerate(g) if v in extra]]
-            if np.any(dx > dK + tau * abs(dK) + floor):
-                bad.append((int(i), "extra id beyond K-th"))
+            dx, ex = gd64[r][extra], eg[r][extra]
+            dm, em = ora_dist[r][missing], eo[r][missing]
+            if np.any(dx[:, None] - dm[None, :] > ex[:, None] + em[None, :]):
+                bad.append((int(i), "GPU preferred an id by more than the FP32 bound"))
                 continue
-        if missing:
-            dm = od[r][[k for k, v in enumerate(o) if v in missing]]
-            if np.any(dm < dK - tau * abs(dK) - floor):
-                bad.append((int(i), "missing id well inside K-th"))
-                continue
-        diff = np.abs(gd64[r][: len(ov)] - od[r][: len(ov)])
-        if np.any(diff > tau * np.maximum(np.abs(od[r][: len(ov)]), floor)):
-            bad.append((int(i), "position distance mismatch"))
+        emax = max(np.max(eg[r][:nv]), np.max(eo[r][:nv]))
+        if np.any(np.abs(gd64[r][:nv] - ora_dist[r][:nv]) > 2.0 * emax):
+            bad.append((int(i), "position distance mismatch beyond the FP32 bound"))
     return bad
 
 
@@ -79,16 +113,3 @@ def recall(gpu_nbr, ora_nbr):
         hit += len(ov & set(g[g >= 0].tolist()))
         tot += len(ov)
     return hit / max(tot, 1)
-
-
-def l2_form_violations(X64, rows, gpu_nbr, ora_dist, tau=TAU):
-    """Rows of an IP result whose per-position distances differ from the
-    oracle's by more than tau relative in the L2 form 2 + 2 delta."""
-    rows = np.asarray(rows)
-    K = ora_dist.shape[1]
-    gd = oracle.pair_dist(X64, np.repeat(rows[:, None], K, 1), gpu_nbr, oracle.IP)
-    a, b = 2 + 2 * gd, 2 + 2 * ora_dist
-    ok = np.isfinite(b)
-    floor = 1e-6 * np.median(b[ok])
-    viol = (np.abs(a - b) > tau * np.maximum(b, floor)) & ok
-    return np.nonzero(viol.any(1))[0]

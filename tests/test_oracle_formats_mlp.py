@@ -144,3 +144,32 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(w1, w - 0.1 * g / (np.abs(g) + 1e-8), rtol=1e-12)
     np.testing.assert_allclose(m1, 0.1 * g)
     np.testing.assert_allclose(v1, 0.001 * g * g)
+
+
+def test_adam_moment_recursion_against_torch():
+    """Several Adam steps starting from non-zero moments at a late step count,
+    against torch.optim.Adam in FP64 on the CPU: a dropped beta1*m or beta2*v
+    term, or a wrong bias correction, changes every step after the first."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(17)
+    n = 257
+    w = rng.standard_normal(n)
+    m = 0.05 * rng.standard_normal(n)
+    v = 0.01 * rng.random(n) + 1e-6
+    step0 = 40
+    lr, b1, b2, eps = 3e-3, 0.8, 0.95, 1e-6
+    p = torch.nn.Parameter(torch.tensor(w, dtype=torch.float64))
+    opt = torch.optim.Adam([p], lr=lr, betas=(b1, b2), eps=eps)
+    opt.state[p] = {"step": torch.tensor(float(step0), dtype=torch.float64),
+                    "exp_avg": torch.tensor(m, dtype=torch.float64),
+                    "exp_avg_sq": torch.tensor(v, dtype=torch.float64)}
+    ow, om, ov = w.copy(), m.copy(), v.copy()
+    for t in range(1, 6):
+        g = rng.standard_normal(n) * (0.1 + t)
+        p.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        ow, om, ov = oracle.adam(ow, g, om, ov, lr, b1, b2, eps, step0 + t)
+        st = opt.state[p]
+        np.testing.assert_allclose(om, st["exp_avg"].numpy(), rtol=1e-13, atol=1e-16)
+        np.testing.assert_allclose(ov, st["exp_avg_sq"].numpy(), rtol=1e-13, atol=1e-16)
+        np.testing.assert_allclose(ow, p.detach().numpy(), rtol=1e-12, atol=1e-15)
