@@ -183,6 +183,37 @@ def assign_replicas(X64, centroids, primary, omega: int, eps: float, tau: float 
     return assign, counts
 
 
+def assign_blockwise(X64, centroids, omega: int, eps: float, tau0: float = 1.0, block_rows: int = 0,
+                     cap: int = 0, adaptive: bool = True):
+    """Blockwise-adaptive assignment (Sec. V-A/V-B, Algorithm 1): (assign n x
+    omega, counts S).  block_rows <= 0 means one block of all rows; cap = 0
+    means no size limit."""
+    X64 = np.ascontiguousarray(X64, np.float64)
+    Cc = np.ascontiguousarray(centroids, np.float64)
+    n, d = X64.shape
+    S = Cc.shape[0]
+    assign = np.empty((max(n, 1), omega), np.int32)
+    counts = np.empty((S,), np.int64)
+    lib = _load()
+    lib.orc_assign_blockwise.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_void_p, C.c_int, C.c_int,
+                                         C.c_double, C.c_double, C.c_int64, C.c_int64, C.c_int,
+                                         C.c_void_p, C.c_void_p]
+    b = int(block_rows) if block_rows > 0 else max(n, 1)
+    _check(lib.orc_assign_blockwise(_p(X64), n, d, _p(Cc), S, omega, float(eps), float(tau0), b, int(cap),
+                                    int(bool(adaptive)), _p(assign), _p(counts)), "assign_blockwise")
+    return assign[:n], counts
+
+
+def partition_blockwise(X64, S: int, omega: int, iters: int, init_idx, eps: float = float("inf"),
+                        tau0: float = 1.0, block_rows: int = 0, cap: int = 0, adaptive: bool = True):
+    """k-means, then the blockwise-adaptive assignment and CSR membership:
+    (centroids, primary, offsets, members)."""
+    Cc, _ = kmeans(X64, S, iters, init_idx)
+    assign, _ = assign_blockwise(X64, Cc, omega, eps, tau0, block_rows, cap, adaptive)
+    off, mem = membership(assign, S)
+    return Cc, assign[:, 0].copy(), off, mem
+
+
 def membership(assign, S: int):
     a = np.ascontiguousarray(assign, np.int32)
     n, omega = a.shape

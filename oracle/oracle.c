@@ -434,6 +434,142 @@ int orc_assign_replicas(const double* X, int64_t n, int d, const double* C, int 
     return 0;
 }
 
+/* Blockwise-adaptive assignment (Sec. V-A) with selective replication
+ * (Sec. V-B, Algorithm 1), rows streamed in blocks of `block_rows` in row
+ * order.  For block t = 1, 2, ...:
+ *   1. each row in order joins its nearest AVAILABLE cluster (size < cap;
+ *      with every cluster full, its nearest) as its primary ("original
+ *      vectors first");
+ *   2. statistics: R2[c] = largest squared distance of c's primaries so far;
+ *      the replica threshold theta[c] = cap - ceil(prim[c] * n / seen), at
+ *      least 0 (space kept for the primaries still expected; dense clusters
+ *      get small thresholds), unlimited when cap = 0 or adaptive = 0;
+ *      tau_t = 1 + (tau0 - 1) / t (large early, tending to 1);
+ *   3. each row in order visits the other clusters by ascending distance and
+ *      joins c' when size[c'] < cap and rep[c'] < theta[c'] (checkSizeLimit)
+ *      and d'^2 < eps^2 d^2 and d'^2 < eps^2 tau_t^2 R2[c'] (both constraints,
+ *      squared), until it is in omega clusters (eps = +inf: every available
+ *      cluster).
+ * The decisions are integer outcomes of floating-point comparisons, taken
+ * here in the FP32 arithmetic the GPU kernel uses: centroids rounded to FP32,
+ * squared distances summed as s = fma(u, u, s) over ascending t with
+ * u = x_t - c_t, visiting order by (squared distance, index), and the
+ * products eps^2 * d^2 and (eps^2 * tau_t^2) * R2 rounded to FP32.
+ * assign: n x omega (primary first, then replicas in the order taken,
+ * ORC_NONE padded); counts: S cluster sizes. */
+typedef struct {
+    float d2;
+    int id;
+} fcand_t;
+
+static int fcand_cmp(const void* pa, const void* pb) {
+    const fcand_t* a = (const fcand_t*)pa;
+    const fcand_t* b = (const fcand_t*)pb;
+    if (a->d2 < b->d2) return -1;
+    if (a->d2 > b->d2) return 1;
+    return a->id < b->id ? -1 : (a->id > b->id ? 1 : 0);
+}
+
+static float sqdist_f32(const double* x, const float* c, int d) {
+    float s = 0.0f;
+    for (int t = 0; t < d; ++t) {
+        float u = (float)x[t] - c[t];
+        s = fmaf(u, u, s);
+    }
+    return s;
+}
+
+int orc_assign_blockwise(const double* X, int64_t n, int d, const double* C, int S, int omega,
+                         double eps, double tau0, int64_t block_rows, int64_t cap, int adaptive,
+                         int32_t* assign, int64_t* counts) {
+    if (n < 0 || d <= 0 || S <= 0 || omega <= 0 || block_rows <= 0 || cap < 0 || tau0 < 1.0)
+        return -1;
+    float* Cf = (float*)malloc(sizeof(float) * (size_t)S * d);
+    for (int64_t e = 0; e < (int64_t)S * d; ++e) Cf[e] = (float)C[e];
+    int64_t* size = (int64_t*)calloc((size_t)S, sizeof(int64_t));
+    int64_t* prim = (int64_t*)calloc((size_t)S, sizeof(int64_t));
+    int64_t* rep = (int64_t*)calloc((size_t)S, sizeof(int64_t));
+    int64_t* theta = (int64_t*)malloc(sizeof(int64_t) * S);
+    float* R2 = (float*)calloc((size_t)S, sizeof(float));
+    fcand_t* cs = (fcand_t*)malloc(sizeof(fcand_t) * (size_t)S * (size_t)(block_rows < n ? block_rows : (n > 0 ? n : 1)));
+    int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * (size_t)(block_rows < n ? block_rows : (n > 0 ? n : 1)));
+    const int accept_all = isinf(eps) && eps > 0;
+    const float eps_f = (float)eps;
+    const float eps2 = eps_f * eps_f;
+    const float tau0_f = (float)tau0;
+    for (int64_t b0 = 0, t = 1; b0 < n; b0 += block_rows, ++t) {
+        const int64_t b1 = b0 + block_rows < n ? b0 + block_rows : n;
+        /* visiting order of every row of the block */
+        for (int64_t i = b0; i < b1; ++i) {
+            fcand_t* ci = cs + (i - b0) * S;
+            for (int c = 0; c < S; ++c) {
+                ci[c].d2 = sqdist_f32(X + i * d, Cf + (int64_t)c * d, d);
+                ci[c].id = c;
+            }
+            qsort(ci, (size_t)S, sizeof(fcand_t), fcand_cmp);
+        }
+        /* 1. primaries: nearest available cluster, in row order */
+        for (int64_t i = b0; i < b1; ++i) {
+            const fcand_t* ci = cs + (i - b0) * S;
+            int k = 0;
+            if (cap > 0) {
+                while (k < S && size[ci[k].id] >= cap) ++k;
+                if (k == S) k = 0;            /* every cluster full: the nearest */
+            }
+            const int c = ci[k].id;
+            pos[i - b0] = k;
+            size[c] += 1;
+            prim[c] += 1;
+            if (ci[k].d2 > R2[c]) R2[c] = ci[k].d2;
+            int32_t* a = assign + i * omega;
+            a[0] = c;
+            for (int j = 1; j < omega; ++j) a[j] = ORC_NONE;
+        }
+        /* 2. thresholds and radius factor after the block's primaries */
+        const int64_t seen = b1;
+        for (int c = 0; c < S; ++c) {
+            if (cap == 0 || !adaptive) {
+                theta[c] = INT64_MAX;
+            } else {
+                const int64_t expect = (prim[c] * n + seen - 1) / seen;   /* ceil(prim * n / seen) */
+                theta[c] = cap - expect > 0 ? cap - expect : 0;
+            }
+        }
+        const float tau_t = 1.0f + (tau0_f - 1.0f) / (float)t;
+        const float et2 = eps2 * (tau_t * tau_t);
+        /* 3. replicas (Algorithm 1), in row order */
+        for (int64_t i = b0; i < b1; ++i) {
+            const fcand_t* ci = cs + (i - b0) * S;
+            int32_t* a = assign + i * omega;
+            const int c = a[0];
+            const float dc2 = ci[pos[i - b0]].d2;
+            int assigned = 1;
+            for (int k = 0; k < S && assigned < omega; ++k) {
+                const int cc = ci[k].id;
+                if (cc == c) continue;
+                if (cap > 0 && size[cc] >= cap) continue;          /* checkSizeLimit */
+                if (rep[cc] >= theta[cc]) continue;
+                const float dp2 = ci[k].d2;
+                if (accept_all || (dp2 < eps2 * dc2 && dp2 < et2 * R2[cc])) {
+                    a[assigned++] = cc;
+                    size[cc] += 1;
+                    rep[cc] += 1;
+                }
+            }
+        }
+    }
+    for (int c = 0; c < S; ++c) counts[c] = size[c];
+    free(Cf);
+    free(size);
+    free(prim);
+    free(rep);
+    free(theta);
+    free(R2);
+    free(cs);
+    free(pos);
+    return 0;
+}
+
 int orc_membership(const int32_t* assign, int64_t n, int omega, int S, int64_t* off,
                    int32_t* member_ids) {
     if (n < 0 || omega <= 0 || S <= 0) return -1;

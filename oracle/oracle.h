@@ -8,8 +8,11 @@
  * GPU library.
  *
  * Every function states the passage of the paper (or the documented reading of
- * it) that it follows.  Floating point is FP64 throughout; inputs are the same
- * stored arrays (FP32 / FP16 / BF16 / U8) the GPU consumes, widened to FP64.
+ * it) that it follows.  Floating point is FP64, except where a floating-point
+ * comparison decides an integer outcome that the kernel decides too (the
+ * blockwise assignment): that decision is taken in the kernel's FP32
+ * arithmetic, written out step by step.  Inputs are the same stored arrays
+ * (FP32 / FP16 / BF16 / U8) the GPU consumes, widened to FP64.
  *
  * Return value convention: 0 on success, negative on a bad argument.
  */
@@ -91,6 +94,20 @@ int orc_kmeans(const double* X, int64_t n, int d, int S, int iters,
 int orc_assign_replicas(const double* X, int64_t n, int d, const double* centroids,
                         int S, const int32_t* primary, int omega, double eps, double tau,
                         int32_t* assign, int64_t* counts);
+
+/* Blockwise-adaptive assignment with selective replication (Sec. V-A, V-B,
+ * Algorithm 1) over rows streamed in blocks of block_rows (row order):
+ * per block, primaries to the nearest available cluster (size < cap), then
+ * radius, replica thresholds theta[c] = max(0, cap - ceil(prim[c] n / seen))
+ * (unlimited when cap = 0 or adaptive = 0) and tau_t = 1 + (tau0 - 1)/t, then
+ * replicas by Algorithm 1 with the size check size < cap and rep < theta and
+ * the constraints in squared form, d'^2 < eps^2 d^2, d'^2 < eps^2 tau_t^2 R2.
+ * Decisions are taken in FP32 (the kernel's precision): FP32 centroids,
+ * fma-summed squared distances over ascending t, FP32 products.
+ * assign: n x omega (primary first, ORC_NONE padded); counts: S sizes. */
+int orc_assign_blockwise(const double* X, int64_t n, int d, const double* C, int S, int omega,
+                         double eps, double tau0, int64_t block_rows, int64_t cap, int adaptive,
+                         int32_t* assign, int64_t* counts);
 
 /* Shard membership in CSR form, each shard's member list ascending by global
  * id (so the order of vectors inside a shard is deterministic). */
