@@ -113,6 +113,47 @@ sg_status sg_partition(const void* X, sg_dtype dtype, int64_t n, int32_t d, int6
                        void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * sg_partition_blockwise -- k-means partition with blockwise-adaptive
+ * assignment and selective replication
+ *
+ * Follows Sec. V-A (blockwise-adaptive assignment) and Sec. V-B with
+ * Algorithm 1, for rows streamed in blocks of block_rows in row order (the
+ * order a disk-resident dataset is read in).  k-means as in sg_partition;
+ * then, with the final centroids, for block t = 1, 2, ...:
+ *  1. Original vectors first: each row of the block, in row order, joins its
+ *     nearest AVAILABLE cluster (size < shard_cap; if every cluster is full,
+ *     its nearest) as its primary.
+ *  2. Statistics: R2[c] = largest squared distance of c's primaries so far;
+ *     replica threshold theta[c] = max(0, shard_cap - ceil(prim[c] * n /
+ *     seen)), the room left once the primaries expected from c's share so far
+ *     are reserved (dense clusters get small thresholds; unlimited when
+ *     shard_cap = 0 or adaptive = 0); tau_t = 1 + (tau0 - 1) / t, a radius
+ *     factor that starts at tau0 and falls towards 1.
+ *  3. Algorithm 1: each row, in row order, visits the other clusters by
+ *     ascending distance and joins c' when size[c'] < shard_cap and
+ *     rep[c'] < theta[c'] (checkSizeLimit) and d'^2 < eps^2 d^2 and
+ *     d'^2 < eps^2 tau_t^2 R2[c'] (the distance and radius constraints,
+ *     squared), until it is in omega clusters; epsilon = +inf skips the
+ *     constraints.
+ * Decisions use FP32 squared distances (FP32 centroids, fma sums over
+ * ascending dimensions), visiting order by (squared distance, index) and
+ * FP32 products.  One block of all rows with shard_cap = 0 and tau0 = 1 is the
+ * single-block rule of sg_partition (in squared form).
+ *  block_rows: >= 1;  shard_cap: >= 0 (0 = no limit);  tau0 >= 1;
+ *  adaptive: 0 or 1.  primary: out, n int32, each row's primary cluster (its
+ *  nearest available one).  Other arguments and outputs as sg_partition;
+ *  the workspace size depends on block_rows.  Synchronises `stream`.
+ * ---------------------------------------------------------------------- */
+sg_status sg_partition_blockwise_workspace_size(int64_t n, int32_t d, int32_t S, int32_t omega,
+                                                int64_t block_rows, size_t* bytes);
+sg_status sg_partition_blockwise(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t ld,
+                                 int32_t S, int32_t omega, int32_t iters, float epsilon, float tau0,
+                                 int64_t block_rows, int64_t shard_cap, int32_t adaptive,
+                                 const int64_t* init_idx_h, double* centroids, int32_t* primary,
+                                 int64_t* shard_offsets_h, int32_t* member_ids, int64_t capacity,
+                                 void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * sg_knn_graph -- exact (or reduced-precision + re-ranked) kNN graph of one shard
  *
  * The per-shard index build of Sec. IV step 2, done as a tiled all-pairs
@@ -131,8 +172,9 @@ sg_status sg_partition(const void* X, sg_dtype dtype, int64_t n, int32_t d, int6
  *  nbr    : out, n x k int32.   dist: out, n x k FP32, may be NULL.
  *  order  : out, n int32, may be NULL: the rows in the order the build
  *           visited them (its locality order: rows grouped by nearest of
- *           about n/256 pivot rows; the identity for small n), a permutation
- *           of 0..n-1 to pass to sg_prune.
+ *           about n/256 pivot rows, ascending row order within a pivot; the
+ *           identity for small n), a permutation of 0..n-1 to pass to
+ *           sg_prune.  The same call writes the same order.
  *  d      : 1..1024 for FP32 and FP8, 1..768 for FP16 / BF16 (larger d returns
  *           SG_ERR_UNSUPPORTED).  Queries are register resident up to FP32
  *           d <= 128 and 16-bit / FP8 d <= 768 / 1024; wider FP32 rows use a
@@ -143,6 +185,31 @@ sg_status sg_knn_graph_workspace_size(int64_t n, int32_t d, int32_t k, sg_prec p
 sg_status sg_knn_graph(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t ld,
                        sg_metric metric, int32_t k, sg_prec prec, int32_t rerank, int32_t* nbr,
                        float* dist, int32_t* order, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * sg_quantize_rows -- the operand rows the distance contraction consumes
+ *
+ * The preparation step of the shard build: each row converted to the
+ * arithmetic type of `prec`, exactly as sg_knn_graph prepares it (the
+ * reduced-precision form of the precision study; the rounding and the
+ * per-row scale are a reading -- the paper fixes no compute precision):
+ *   SG_PREC_FP32 : FP32 values (exact for every input type);
+ *   SG_PREC_F16  : FP16 (F16 or U8 input: exact);
+ *   SG_PREC_BF16 : BF16 bits, round to nearest even (a NaN stays a quiet NaN);
+ *   SG_PREC_FP8  : OCP FP8 E4M3 codes of x / 2^e (round to nearest even,
+ *                  saturating at +-448, NaN -> 0x7f), with the per-row scale
+ *                  exponent e = the smallest integer such that max|x| / 2^e
+ *                  <= 448 (0 for an all-zero row), written to scale_exp.
+ *  out      : n x ldo elements of the operand type (4, 2, 2 or 1 bytes),
+ *             columns d..ldo-1 set to zero.  ldo: d..2^20.
+ *  scale_exp: n int32 (FP8 only; NULL otherwise allowed).
+ *  sqnorm   : n FP32, may be NULL: the squared L2 norm of the rounded row,
+ *             the norm term the distance kernel adds (FP32 sum, each lane
+ *             summing every 64th element, then a fixed butterfly).
+ * Same input rules as sg_knn_graph (k and rerank aside).  No workspace.
+ * ---------------------------------------------------------------------- */
+sg_status sg_quantize_rows(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t ld, sg_prec prec,
+                           void* out, int64_t ldo, int32_t* scale_exp, float* sqnorm, void* stream);
 
 /* ------------------------------------------------------------------------
  * sg_knn_rows -- exact (or re-ranked) kNN of listed rows against all rows
@@ -273,11 +340,12 @@ sg_status sg_knn_graph_learned(const void* X, sg_dtype dtype, int32_t d, int64_t
  *        followed by any SG_NONE padding (as sg_knn_graph writes it).
  *  K   : 1..256;  R: 1..min(K, 64).   out: n x R int32 (SG_NONE padded).
  *  Ids outside [0, n) in knn are treated as SG_NONE.
- *  order: NULL, or a permutation of 0..n-1 (device int32) giving the order in
- *        which rows are processed, e.g. the order sg_knn_graph returns, so
- *        that rows processed together share neighbour lists in cache.  The
- *        result does not depend on it; entries outside [0, n) are skipped
- *        and rows missing from a non-permutation are left unwritten.
+ *  order: NULL, or n device int32 giving the order in which rows are
+ *        processed, e.g. the order sg_knn_graph returns, so that rows
+ *        processed together share neighbour lists in cache.  The result never
+ *        depends on it: an array that is not a permutation of 0..n-1 (an
+ *        entry out of range or repeated) is detected on the device and the
+ *        rows are then processed in row order.
  * ---------------------------------------------------------------------- */
 sg_status sg_prune_workspace_size(int64_t n, int32_t K, int32_t R, size_t* bytes);
 sg_status sg_prune(const int32_t* knn, int64_t n, int32_t K, int32_t R, const int32_t* order,

@@ -58,6 +58,9 @@ _SIGS = {
     "sg_partition_workspace_size": (i32, [i64, i32, i32, i32, psz]),
     "sg_partition": (i32, [vp, i32, i64, i32, i64, i32, i32, i32, f32, f32, vp, vp, vp, vp, vp,
                            i64, vp, sz, vp]),
+    "sg_partition_blockwise_workspace_size": (i32, [i64, i32, i32, i32, i64, psz]),
+    "sg_partition_blockwise": (i32, [vp, i32, i64, i32, i64, i32, i32, i32, f32, f32, i64, i64, i32, vp, vp,
+                                     vp, vp, vp, i64, vp, sz, vp]),
     "sg_knn_graph_workspace_size": (i32, [i64, i32, i32, i32, i32, psz]),
     "sg_knn_graph": (i32, [vp, i32, i64, i32, i64, i32, i32, i32, i32, vp, vp, vp, vp, sz, vp]),
     "sg_knn_rows_workspace_size": (i32, [i64, i32, i64, i32, i32, i32, psz]),
@@ -68,6 +71,7 @@ _SIGS = {
     "sg_merge": (i32, [i32, vp, vp, vp, i32, i64, i32, vp, vp, vp, sz, vp]),
     "sg_search_workspace_size": (i32, [i64, i32, i64, psz]),
     "sg_rerank": (i32, [vp, i32, i64, i32, i64, i32, vp, i32, i32, vp, vp, vp]),
+    "sg_quantize_rows": (i32, [vp, i32, i64, i32, i64, i32, vp, i64, vp, vp, vp]),
     "sg_knn_variant_count": (i32, [i32, i32, i32, C.POINTER(C.c_int32)]),
     "sg_knn_autotune": (i32, [vp, i32, i64, i32, i64, i32, i32, i32, i32, vp, sz, vp, vp, vp, i32]),
     "sg_knn_force_variant": (i32, [i32]),
@@ -183,6 +187,26 @@ def sg_knn_graph(X, k, metric="l2", prec="fp32", rerank=0, dist=True, stream=Non
     _check("sg_knn_graph", L.sg_knn_graph(_ptr(X), dt, n, d, ld, m, k, p, rerank, _ptr(nbr), _ptr(dd),
                                           _ptr(order_out), _ptr(ws), ws.numel(), _stream(stream)))
     return nbr, dd
+
+
+_OPERAND_DTYPES = {0: torch.float32, 1: torch.float16, 2: torch.int16, 3: torch.uint8}
+
+
+def sg_quantize_rows(X, prec="fp32", ldo=None, stream=None):
+    """Operand rows of `prec` as the distance kernel prepares them:
+    (rows [n, ldo] -- float32, float16, BF16 bits as int16 or FP8 E4M3 codes as
+    uint8 --, scale exponents int32 [n] for FP8 else None, squared norms
+    float32 [n])."""
+    L = lib()
+    dt, n, d, ld = _rows(X)
+    p = PRECS[prec]
+    ldo = d if ldo is None else int(ldo)
+    out = torch.empty((n, ldo), dtype=_OPERAND_DTYPES[p], device=X.device)
+    sexp = torch.empty(n, dtype=torch.int32, device=X.device) if prec == "fp8" else None
+    sq = torch.empty(n, dtype=torch.float32, device=X.device)
+    _check("sg_quantize_rows", L.sg_quantize_rows(_ptr(X), dt, n, d, ld, p, _ptr(out), ldo, _ptr(sexp), _ptr(sq),
+                                                  _stream(stream)))
+    return out, sexp, sq
 
 
 def sg_knn_variant_count(d, k, prec="fp32"):
@@ -322,6 +346,29 @@ def sg_partition(X, S, omega, iters, init_idx, epsilon=float("inf"), tau=1.0, st
                                           float(tau), C.c_void_p(init.data_ptr()), _ptr(cent),
                                           _ptr(prim), C.c_void_p(off.data_ptr()), _ptr(mem), cap,
                                           _ptr(ws), ws.numel(), _stream(stream)))
+    return cent, prim, off, mem[: int(off[-1])]
+
+
+def sg_partition_blockwise(X, S, omega, iters, init_idx, epsilon=float("inf"), tau0=1.0, block_rows=None,
+                           shard_cap=0, adaptive=True, stream=None):
+    """k-means + blockwise-adaptive assignment with selective replication:
+    (centroids f64 [S,d], primary int32 [n], shard_offsets int64 [S+1] (host),
+    member_ids int32 [total]).  block_rows None: one block of all rows."""
+    L = lib()
+    dt, n, d, ld = _rows(X)
+    b = n if block_rows is None else int(block_rows)
+    init = torch.as_tensor(init_idx, dtype=torch.int64).cpu().contiguous()
+    ws = _ws.get(_size(L.sg_partition_blockwise_workspace_size, n, d, S, omega, b), X.device, "partition")
+    cent = torch.empty((S, d), dtype=torch.float64, device=X.device)
+    prim = torch.empty((n,), dtype=torch.int32, device=X.device)
+    off = torch.empty((S + 1,), dtype=torch.int64)
+    cap = n * omega
+    mem = torch.empty((cap,), dtype=torch.int32, device=X.device)
+    _check("sg_partition_blockwise",
+           L.sg_partition_blockwise(_ptr(X), dt, n, d, ld, S, omega, iters, float(epsilon), float(tau0), b,
+                                    int(shard_cap), int(bool(adaptive)), C.c_void_p(init.data_ptr()), _ptr(cent),
+                                    _ptr(prim), C.c_void_p(off.data_ptr()), _ptr(mem), cap, _ptr(ws), ws.numel(),
+                                    _stream(stream)))
     return cent, prim, off, mem[: int(off[-1])]
 
 

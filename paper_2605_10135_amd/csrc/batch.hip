@@ -92,37 +92,31 @@ __global__ __launch_bounds__(NEAR_WAVES * 64) void near_batched_kernel(Shards sh
                                         (int)(sh.row0[s + 1] - sh.row0[s]), qmul, lab + p0, (int32_t)sh.piv0[s]);
 }
 
-__global__ void count_batched_kernel(Shards sh, const int32_t* __restrict__ lab, int64_t* __restrict__ cnt) {
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < sh.pad0[sh.S];
-         j += (int64_t)gridDim.x * blockDim.x) {
-        const int s = shard_of(sh.pad0, sh.S, j);
-        if (j - sh.pad0[s] >= sh.row0[s + 1] - sh.row0[s]) continue;   // padding
-        int64_t c = lab[j];
+// Labels of the batch's rows in compact row order (row r of shard s is
+// operand row pad0[s] + r - row0[s]); a label outside the shard's range is
+// taken as the shard's first.
+__global__ void compact_labels_kernel(Shards sh, const int32_t* __restrict__ lab, int32_t* __restrict__ labc) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < sh.row0[sh.S];
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int s = shard_of(sh.row0, sh.S, r);
+        int64_t c = lab[sh.pad0[s] + r - sh.row0[s]];
         if (c < sh.piv0[s] || c >= sh.piv0[s + 1]) c = sh.piv0[s];
-        atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[c]), 1ull);
+        labc[r] = (int32_t)c;
     }
 }
 
-// Rows of each shard grouped by label (labels of shard s follow those of
-// shard s-1, so the scan of the counts starts shard s at row0[s]).  Any order
-// within a label gives the same lists: keys carry the row ids.
-// Also writes the locality order over all rows (position -> row, positions
-// of shard s from row0[s]), the order the prune visits the rows in.
-__global__ void scatter_batched_kernel(Shards sh, const int32_t* __restrict__ lab, const int64_t* __restrict__ off,
-                                       int64_t* __restrict__ cur, int64_t* __restrict__ perm,
-                                       int32_t* __restrict__ pid, int32_t* __restrict__ order) {
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < sh.pad0[sh.S];
-         j += (int64_t)gridDim.x * blockDim.x) {
-        const int s = shard_of(sh.pad0, sh.S, j);
-        const int64_t loc = j - sh.pad0[s];
-        if (loc >= sh.row0[s + 1] - sh.row0[s]) continue;
-        int64_t c = lab[j];
-        if (c < sh.piv0[s] || c >= sh.piv0[s + 1]) c = sh.piv0[s];
-        const int64_t pos = off[c] + (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&cur[c]), 1ull);
+// From the locality order over all rows (position -> row, sorted by global
+// label, so the positions of shard s are row0[s]..row0[s+1]-1 because shard
+// s's labels follow shard s-1's): the operand-layout maps of each shard.
+__global__ void place_batched_kernel(Shards sh, const int32_t* __restrict__ order, int64_t* __restrict__ perm,
+                                     int32_t* __restrict__ pid) {
+    for (int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pos < sh.row0[sh.S];
+         pos += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = order[pos];
+        const int s = shard_of(sh.row0, sh.S, pos);
         const int64_t o = pos - sh.row0[s] + sh.pad0[s];
-        perm[o] = sh.row0[s] + loc;
-        pid[o] = (int32_t)(sh.row0[s] + loc);
-        order[pos] = (int32_t)(sh.row0[s] + loc);
+        perm[o] = r;
+        pid[o] = r;
     }
 }
 
@@ -269,14 +263,13 @@ Plan make_plan(const int64_t* off, int S, int d, int k, int R, int prec, int rer
     size_t pb = 0;
     if (sg_prune_workspace_size(p.n_all, k, R, &pb) != SG_OK) throw Fail{SG_ERR_INTERNAL};
     p.prune_bytes = pb;
-    p.scan_bytes = exclusive_scan_tmp_bytes(std::max<int64_t>(piv, 1));
+    p.scan_bytes = label_sort_tmp_bytes(p.n_all, bits_for(std::max<int64_t>(piv, 1)));
     const size_t P8 = align_up((size_t)pad * 8, 256), P4 = align_up((size_t)pad * 4, 256);
     const size_t Q8 = align_up((size_t)ppad * 8, 256), Q4 = align_up((size_t)ppad * 4, 256);
-    const size_t L8 = align_up((size_t)(piv + 1) * 8, 256);
     p.total = align_up((size_t)pad * p.DP * p.eb, 256) + 3 * P4        // ops, ninit, nout, sexp
               + 2 * P8 + 2 * P4                                       // idmap, perm, pid, lab
               + Q8 + align_up((size_t)ppad * p.DP * p.eb, 256) + 3 * Q4   // pivots
-              + 3 * L8 + align_up(p.scan_bytes, 256)                  // label counts / offsets / cursors
+              + align_up((size_t)p.n_all * 4, 256) + align_up(p.scan_bytes, 256)   // compact labels, label sort
               + align_up((size_t)pad * p.ksel * 8, 256)               // state
               + 256                                                   // counter
               + align_up((size_t)p.n_all * k * 4, 256)                // kNN lists (when not returned)
@@ -304,10 +297,8 @@ void enqueue(const Plan& p, const void* X, int dtype, int d, int64_t ld, int met
     float* pinit = cv.take<float>(ppad);
     float* pnout = cv.take<float>(ppad);
     int32_t* psexp = cv.take<int32_t>(ppad);
-    int64_t* cnt = cv.take<int64_t>(piv + 1);
-    int64_t* loff = cv.take<int64_t>(piv + 1);
-    int64_t* cur = cv.take<int64_t>(piv + 1);
-    void* scan_tmp = cv.take<char>(p.scan_bytes);
+    int32_t* labc = cv.take<int32_t>(p.n_all);
+    void* sort_tmp = cv.take<char>(p.scan_bytes);
     uint64_t* state = cv.take<uint64_t>((size_t)pad * p.ksel);
     unsigned int* counter = cv.take<unsigned int>(64);
     int32_t* knn_ws = cv.take<int32_t>((size_t)p.n_all * k);
@@ -331,12 +322,11 @@ void enqueue(const Plan& p, const void* X, int dtype, int d, int64_t ld, int met
     p.kern.near<<<(unsigned)(pad / (NEAR_WAVES * 32)), NEAR_WAVES * 64, 0, s>>>(
         p.sh, pops, pinit, fp8 ? psexp : nullptr, ops, fp8 ? sexp : nullptr, qmul, lab);
     SG_LAUNCH_CHECK();
-    fill<int64_t>(cnt, 0, piv + 1, s);
-    fill<int64_t>(cur, 0, piv + 1, s);
-    count_batched_kernel<<<eg, 256, 0, s>>>(p.sh, lab, cnt);
+    // the locality order: rows sorted by (global label, row), stable
+    compact_labels_kernel<<<eg, 256, 0, s>>>(p.sh, lab, labc);
     SG_LAUNCH_CHECK();
-    exclusive_scan_i64(cnt, loff, piv, scan_tmp, s);
-    scatter_batched_kernel<<<eg, 256, 0, s>>>(p.sh, lab, loff, cur, perm, pid, order);
+    label_sort(labc, p.n_all, bits_for(std::max<int64_t>(piv, 1)), order, sort_tmp, s);
+    place_batched_kernel<<<eg, 256, 0, s>>>(p.sh, order, perm, pid);
     SG_LAUNCH_CHECK();
     prep_kernel<<<(unsigned)cdiv(pad, 4), 256, 0, s>>>(X, dtype, pad, d, ld, perm, p.n_all, pad, p.DP, prec, metric,
                                                       ops, ninit, nout, fp8 ? sexp : nullptr);

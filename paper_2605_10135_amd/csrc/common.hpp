@@ -274,4 +274,15 @@ inline void fill_iota(int64_t* p, int64_t start, int64_t n, hipStream_t s) {
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t s);
 size_t exclusive_scan_tmp_bytes(int64_t n);
 
+// Stable sort of rows 0..n-1 by label (labels in [0, 2^bits)): rows_out[p] is
+// the row at position p of the (label, row) order.  Deterministic, no atomics
+// in the placement, no memset (valid inside a captured graph).
+void label_sort(const int32_t* lab, int64_t n, int bits, int32_t* rows_out, void* tmp, hipStream_t s);
+size_t label_sort_tmp_bytes(int64_t n, int bits);
+inline int bits_for(int64_t count) {
+    int b = 0;
+    while ((int64_t(1) << b) < count) ++b;
+    return b;
+}
+
 }  // namespace sg

@@ -6,23 +6,30 @@
 //
 //  * prep: rows -> MFMA operand rows (FP32 / FP16 / BF16 / FP8 with a
 //    power-of-two per-row scale), zero-padded to the k granule, plus the
-//    squared norms of the operand rows (+inf for padding rows).
-//  * dist_topk: a 512-thread workgroup (8 waves, two per SIMD so that one
-//    wave's selection overlaps the other's MFMAs) owns 256 query rows, 32
-//    per wave, and streams every candidate row of the shard through LDS in
-//    double-buffered tiles (the next tile is already loading into registers
-//    while the current one is computed).  Each 32x32 MFMA output tile holds
-//    candidates on its rows and queries on its columns, so every lane sees
-//    16 candidates of ONE query and keeps that query's admission threshold in
-//    a register.  The accumulator starts at ||c||^2 and the query operand is
-//    pre-scaled by -2 (exact), so the MFMA result is already the ranking key
-//    ||c||^2 - 2 q.c (L2) or -q.c (IP).  Keys below the threshold go to a
-//    32-entry LDS buffer per query; a buffer that overflows is merged in
-//    registers (wave bitonic sort + bitonic merge) into the query's sorted
-//    top-K list kept in the workspace, which lowers the threshold, and the
-//    overflowing keys are re-admitted against it.  Candidates are visited in
-//    ascending id order, so a key equal to the threshold can never enter the
-//    list and the strict comparison is exact.
+//    squared norms of the operand rows (NaN for padding rows, never admitted).
+//  * locality order (shards of >= 4096 rows): rows grouped by their nearest of
+//    about n/256 evenly spaced pivot rows (a stable sort: ascending row order
+//    within a pivot, so the order returned is the same on every run).
+//  * dist_topk: a workgroup (a launch shape: 8 waves x 32 queries, or 4 waves
+//    with 64- or 32-row candidate tiles, chosen by the autotuner) owns a block
+//    of query rows, each wave 32 of them held in registers, and streams every
+//    candidate row of the shard through LDS in double-buffered tiles (the
+//    next tile already loading into registers while the current one is
+//    computed), first the tiles of its own pivot group, then all others in
+//    one shared order.  Each 32x32 MFMA output tile holds candidates on its
+//    rows and queries on its columns, so every lane sees 16 candidates of
+//    ONE query and keeps that query's admission threshold in a register.  The
+//    accumulator starts at ||c||^2 and the query operand is pre-scaled by -2
+//    (exact), so the MFMA result is already the ranking key ||c||^2 - 2 q.c
+//    (L2) or -q.c (IP).  Keys at or below the threshold go to a 16- or
+//    32-entry LDS buffer per query; a full buffer is merged in registers (wave
+//    bitonic sort + bitonic merge) into the query's sorted top-K list of
+//    (distance, id) keys in the workspace, which lowers the threshold.
+//    Admission is exact in any candidate order: a candidate farther than the
+//    K-th distance of a subset already seen cannot be in the top K, and one
+//    at exactly that distance is admitted (the comparison is <=) and ranked by
+//    (distance, id) in the merge.  The query itself (by index) and padding
+//    rows carry NaN keys, which no comparison admits.
 //  * rerank: the top-c candidates of a reduced-precision key re-scored with
 //    the exact FP32 difference-form distance, best k kept.
 #include "knn_impl.hpp"
@@ -123,10 +130,7 @@ void run(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int
         perm = cv.take<int64_t>(L.n_pad);
         pid = cv.take<int32_t>(L.n_pad);
         int32_t* lab = cv.take<int32_t>(L.n_pad);
-        int64_t* cnt = cv.take<int64_t>(P + 1);
-        int64_t* off = cv.take<int64_t>(P + 1);
-        int64_t* cur = cv.take<int64_t>(P + 1);
-        void* scan_tmp = cv.take<char>(exclusive_scan_tmp_bytes(P));
+        void* sort_tmp = cv.take<char>(label_sort_tmp_bytes(n, bits_for(P)));
         uint8_t* pops = cv.take<uint8_t>((size_t)Pp * L.DP * elem_bytes(prec));
         float* pinit = cv.take<float>(Pp);
         float* pnout = cv.take<float>(Pp);
@@ -144,14 +148,10 @@ void run(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int
         kern.near<<<(unsigned)(L.n_pad / (32 * NEAR_WAVES)), NEAR_WAVES * 64, 0, s>>>(
             pops, pinit, prec == SG_PREC_FP8 ? psexp : nullptr, (int)P, ops, sexp, (int)n, qmul, lab);
         SG_LAUNCH_CHECK();
-        // group the rows by pivot
-        fill<int64_t>(cnt, 0, P + 1, s);
-        fill<int64_t>(cur, 0, P + 1, s);
+        // group the rows by pivot, ascending row order within a pivot (stable)
+        label_sort(lab, n, bits_for(P), pid, sort_tmp, s);
         const unsigned eg = (unsigned)std::min<int64_t>(cdiv(L.n_pad, 256), 4096);
-        label_count_kernel<<<eg, 256, 0, s>>>(lab, n, P, cnt);
-        SG_LAUNCH_CHECK();
-        exclusive_scan_i64(cnt, off, P, scan_tmp, s);
-        label_scatter_kernel<<<eg, 256, 0, s>>>(lab, n, L.n_pad, P, off, cur, perm, pid);
+        rows_to_perm_kernel<<<eg, 256, 0, s>>>(pid, n, L.n_pad, perm, pid);
         SG_LAUNCH_CHECK();
     }
 
@@ -336,5 +336,22 @@ extern "C" sg_status sg_knn_graph_learned(const void* X, sg_dtype dtype, int32_t
         knn::run(P, SG_F32, n, e, ldp, SG_IP, c, SG_PREC_FP8, 0, nullptr, -1, cand, nullptr,
                  static_cast<char*>(ws) + cbytes, ws_bytes - cbytes, s);
         knn::launch_rerank<int32_t>(X, dtype, n, d, ld, metric, nullptr, n, cand, c, c, k, nbr, dist, nullptr, s);
+    });
+}
+
+extern "C" sg_status sg_quantize_rows(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t ld,
+                                      sg_prec prec, void* out, int64_t ldo, int32_t* scale_exp, float* sqnorm,
+                                      void* stream) {
+    return guarded([&] {
+        knn::check_args(X, dtype, n, d, ld, SG_L2, 1, prec, 0);
+        SG_REQUIRE(ldo >= d && ldo <= (int64_t(1) << 20), "ldo must be in d..2^20");
+        if (n == 0) return;
+        SG_REQUIRE(out != nullptr, "out is NULL");
+        SG_REQUIRE(prec != SG_PREC_FP8 || scale_exp != nullptr, "FP8 needs scale_exp");
+        hipStream_t s = as_stream(stream);
+        knn::prep_kernel<<<(unsigned)cdiv(n, 4), 256, 0, s>>>(X, dtype, n, d, ld, nullptr, n, n, (int)ldo, prec,
+                                                               SG_L2, static_cast<uint8_t*>(out), sqnorm, nullptr,
+                                                               prec == SG_PREC_FP8 ? scale_exp : nullptr);
+        SG_LAUNCH_CHECK();
     });
 }

@@ -120,9 +120,9 @@ __host__ __device__ inline bool norm_corrected_ip(int metric, int prec) {
 
 // One wave per operand row (source row rowmap[row], or row itself when
 // rowmap is NULL).  Writes the converted row (zero padded to DP),
-// the accumulator start of the row as a candidate (ninit, +inf for padding
+// the accumulator start of the row as a candidate (ninit, NaN for padding
 // rows), its output offset as a query (nout) and, for FP8, the row's scale
-// exponent.
+// exponent (ninit, nout and sexp may be NULL).
 static __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_t n, int d, int64_t ld,
                             const int64_t* __restrict__ rowmap, int64_t n_src, int64_t n_pad, int DP,
                             int prec, int metric, uint8_t* __restrict__ ops, float* __restrict__ ninit,
@@ -140,8 +140,8 @@ static __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_
             else out[t] = 0;
         }
         if (l == 0) {
-            ninit[row] = __builtin_nanf("");   // never admitted: NaN fails every comparison
-            nout[row] = 0.f;
+            if (ninit) ninit[row] = __builtin_nanf("");   // never admitted: NaN fails every comparison
+            if (nout) nout[row] = 0.f;
             if (sexp) sexp[row] = 0;
         }
         return;
@@ -197,16 +197,9 @@ static __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_
         ssx += __shfl_xor(ssx, o, 64);
     }
     if (l == 0) {
-        if (metric == SG_L2) {
-            ninit[row] = ssq;
-            nout[row] = ssq;
-        } else if (norm_corrected_ip(metric, prec)) {
-            ninit[row] = ssq - ssx;
-            nout[row] = ssq - ssx;
-        } else {
-            ninit[row] = 0.f;
-            nout[row] = 0.f;
-        }
+        const float term = metric == SG_L2 ? ssq : norm_corrected_ip(metric, prec) ? ssq - ssx : 0.f;
+        if (ninit) ninit[row] = term;
+        if (nout) nout[row] = term;
         if (sexp) sexp[row] = sx;
     }
 }
@@ -1533,7 +1526,7 @@ inline bool use_locality(int64_t n, bool subset) { return !subset && n >= LOCAL_
 inline size_t locality_bytes(const Layout& L, int64_t n, int prec) {
     const int64_t P = n_pivots(n), Pp = pad_rows(P);
     return align_up((size_t)L.n_pad * 8, 256) + 2 * align_up((size_t)L.n_pad * 4, 256) +
-           3 * align_up((size_t)(P + 1) * 8, 256) + align_up(exclusive_scan_tmp_bytes(P), 256) +
+           align_up(label_sort_tmp_bytes(n, bits_for(P)), 256) +
            align_up((size_t)Pp * L.DP * elem_bytes(prec), 256) + 3 * align_up((size_t)Pp * 4, 256) +
            align_up((size_t)P * 8, 256);
 }
@@ -1565,32 +1558,15 @@ static __global__ void pivot_rows_kernel(int64_t* __restrict__ piv, int64_t P, i
     if (p < P) piv[p] = p * n / P;
 }
 
-static __global__ void label_count_kernel(const int32_t* __restrict__ lab, int64_t n, int64_t P,
-                                   int64_t* __restrict__ cnt) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t c = lab[i];
-        atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[c >= 0 && c < P ? c : 0]), 1ull);
-    }
-}
-
-// Rows grouped by label; within a label the order follows the atomics (any
-// order gives the same lists: keys carry the original row ids).  Padding rows
-// n..n_pad get id -1.
-static __global__ void label_scatter_kernel(const int32_t* __restrict__ lab, int64_t n, int64_t n_pad, int64_t P,
-                                     const int64_t* __restrict__ off, int64_t* __restrict__ cur,
-                                     int64_t* __restrict__ perm, int32_t* __restrict__ pid) {
+// The locality order as operand-row maps: position p < n holds row rows[p]
+// (perm as int64, pid as int32 candidate id); padding positions get -1.
+static __global__ void rows_to_perm_kernel(const int32_t* __restrict__ rows, int64_t n, int64_t n_pad,
+                                           int64_t* __restrict__ perm, int32_t* __restrict__ pid) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad;
          i += (int64_t)gridDim.x * blockDim.x) {
-        if (i >= n) {
-            perm[i] = -1;
-            pid[i] = -1;
-            continue;
-        }
-        const int32_t c0 = lab[i];
-        const int32_t c = c0 >= 0 && c0 < P ? c0 : 0;
-        const int64_t pos = off[c] + (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(&cur[c]), 1ull);
-        perm[pos] = i;
-        pid[pos] = (int32_t)i;
+        const int32_t r = i < n ? rows[i] : -1;
+        perm[i] = r;
+        if (i >= n) pid[i] = -1;
     }
 }
 

@@ -236,6 +236,210 @@ __global__ __launch_bounds__(AR) void replica_kernel(const void* __restrict__ X,
     for (int k = assigned; k < omega; ++k) a[k] = SG_NONE;
 }
 
+// ---------------------------------------------------------------------------
+// blockwise-adaptive assignment (Sec. V-A, Sec. V-B, Algorithm 1)
+// ---------------------------------------------------------------------------
+
+// Squared FP32 distances of every row to every centroid (the sums of
+// row_dists), D2[i * S + c].
+template <int SMAX>
+__global__ __launch_bounds__(AR) void sqdist_kernel(const void* __restrict__ X, int dtype, int64_t n, int d,
+                                                    int64_t ld, const float* __restrict__ Cf, int S,
+                                                    float* __restrict__ D2) {
+    __shared__ DistSmem<SMAX> sm;
+    const int64_t row0 = (int64_t)blockIdx.x * AR;
+    float acc[SMAX];
+    row_dists<SMAX>(sm, X, dtype, n, d, ld, Cf, S, row0, acc);
+    const int64_t i = row0 + threadIdx.x;
+    if (i >= n) return;
+#pragma unroll
+    for (int c = 0; c < SMAX; ++c)
+        if (c < S) D2[i * S + c] = acc[c];
+}
+
+// d[c] for a run-time c without indexing the register array
+template <int SMAX>
+__device__ inline float pick(const float (&d)[SMAX], int c) {
+    float r = 0.f;
+#pragma unroll
+    for (int u = 0; u < SMAX; ++u)
+        if (u == c) r = d[u];
+    return r;
+}
+
+// The clusters of one row in visiting order (ascending squared distance,
+// ties to the lower index), one at a time: next() returns the next cluster
+// or -1 once all S are visited.
+template <int SMAX>
+struct Visit {
+    const float (&d)[SMAX];
+    int S;
+    uint64_t seen = 0;
+    __device__ Visit(const float (&dd)[SMAX], int s) : d(dd), S(s) {}
+    __device__ int next() {
+        int bi = -1;
+        float bd = 0.f;
+#pragma unroll
+        for (int c = 0; c < SMAX; ++c) {
+            if (c >= S || ((seen >> c) & 1ull)) continue;
+            if (bi < 0 || d[c] < bd) {
+                bi = c;
+                bd = d[c];
+            }
+        }
+        if (bi >= 0) seen |= 1ull << bi;
+        return bi;
+    }
+};
+
+// One wave walks the blocks of rows in order.  Cluster state lives in LDS:
+// size (members), prim (primaries), rep (replicas), theta (replica
+// threshold), R2 (largest squared primary distance, as float bits).  Each
+// block: (1) primaries to the nearest available cluster, (2) thresholds,
+// (3) replicas by Algorithm 1.  Rows go 64 at a time, one per lane; a chunk
+// takes its decisions from the state at its start when no cluster it touches
+// crosses a limit within the chunk -- then every lane decides exactly as it
+// would row by row -- and otherwise replays the chunk row by row.
+//   et2[t]: eps^2 * tau_t^2 of block t (FP32, from the host).
+template <int SMAX>
+__global__ __launch_bounds__(64) void blockwise_kernel(const float* __restrict__ D2, int64_t n, int S, int omega,
+                                                       float eps2, const float* __restrict__ et2,
+                                                       int64_t block_rows, int64_t cap, int adaptive,
+                                                       int accept_all, int32_t* __restrict__ assign,
+                                                       int32_t* __restrict__ primary) {
+    __shared__ int64_t size[SMAX], prim[SMAX], rep[SMAX], theta[SMAX];
+    __shared__ unsigned int R2[SMAX];
+    __shared__ int cnt[SMAX];
+    const int l = threadIdx.x;
+    const int64_t UNLIMITED = INT64_MAX;
+    if (l < SMAX) {
+        size[l] = prim[l] = rep[l] = 0;
+        theta[l] = UNLIMITED;
+        R2[l] = 0u;
+        cnt[l] = 0;
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    auto full = [&](int c) { return cap > 0 && size[c] >= cap; };
+    auto load_row = [&](int64_t i, float (&d)[SMAX]) {
+#pragma unroll
+        for (int c = 0; c < SMAX; ++c) d[c] = (i < n && c < S) ? D2[i * S + c] : 0.f;
+    };
+    // primary of one row under the current sizes (nearest available, else nearest)
+    auto choose_primary = [&](const float (&d)[SMAX]) {
+        Visit<SMAX> v(d, S);
+        int first = -1;
+        for (int k = 0; k < S; ++k) {
+            const int c = v.next();
+            if (first < 0) first = c;
+            if (!full(c)) return c;
+        }
+        return first;
+    };
+    // replicas of one row under the current state: up to omega - 1 proposals
+    auto propose = [&](const float (&d)[SMAX], int c0, float et, int (&out)[8]) {
+        const float dc2 = pick(d, c0);
+        Visit<SMAX> v(d, S);
+        int got = 1;
+        for (int k = 0; k < S && got < omega; ++k) {
+            const int c = v.next();
+            if (c == c0 || full(c) || rep[c] >= theta[c]) continue;
+            const float dp2 = pick(d, c);
+            if (accept_all || (dp2 < eps2 * dc2 && dp2 < et * __builtin_bit_cast(float, R2[c]))) out[got++] = c;
+        }
+        return got;
+    };
+
+    int64_t t = 0;
+    for (int64_t b0 = 0; b0 < n; b0 += block_rows, ++t) {
+        const int64_t b1 = b0 + block_rows < n ? b0 + block_rows : n;
+        // (1) primaries
+        for (int64_t c0 = b0; c0 < b1; c0 += 64) {
+            const int64_t i = c0 + l;
+            const bool valid = i < b1;
+            float d[SMAX];
+            load_row(i, d);
+            int ch = valid ? choose_primary(d) : 0;
+            if (valid) atomicAdd(&cnt[ch], 1);
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            const bool over = valid && cap > 0 && size[ch] + cnt[ch] > cap;
+            const bool serial = __builtin_amdgcn_ballot_w64(over) != 0;
+            if (!serial) {
+                if (l < S) {
+                    size[l] += cnt[l];
+                    prim[l] += cnt[l];
+                }
+            } else {
+                for (int j = 0; j < 64; ++j) {
+                    if (l == j && valid) {
+                        ch = choose_primary(d);
+                        size[ch] += 1;
+                        prim[ch] += 1;
+                    }
+                    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+                }
+            }
+            if (valid) {
+                atomicMax(&R2[ch], __builtin_bit_cast(unsigned int, pick(d, ch)));
+                assign[i * omega] = ch;
+                for (int k = 1; k < omega; ++k) assign[i * omega + k] = SG_NONE;
+                primary[i] = ch;
+            }
+            if (l < SMAX) cnt[l] = 0;
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        }
+        // (2) thresholds after the block's primaries
+        if (l < S) {
+            if (cap == 0 || !adaptive) {
+                theta[l] = UNLIMITED;
+            } else {
+                const int64_t expect = (prim[l] * n + b1 - 1) / b1;   // ceil(prim * n / seen)
+                theta[l] = cap - expect > 0 ? cap - expect : 0;
+            }
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        const float et = et2[t];
+        // (3) replicas
+        if (omega > 1) {
+            for (int64_t c0 = b0; c0 < b1; c0 += 64) {
+                const int64_t i = c0 + l;
+                const bool valid = i < b1;
+                float d[SMAX];
+                load_row(i, d);
+                const int pc = valid ? assign[i * omega] : 0;
+                int out[8];
+                int got = valid ? propose(d, pc, et, out) : 1;
+                for (int k = 1; k < got; ++k) atomicAdd(&cnt[out[k]], 1);
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+                bool over = false;
+                if (l < S && cnt[l] > 0)
+                    over = (cap > 0 && size[l] + cnt[l] > cap) || rep[l] + cnt[l] > theta[l];
+                const bool serial = __builtin_amdgcn_ballot_w64(over) != 0;
+                if (!serial) {
+                    if (l < S) {
+                        size[l] += cnt[l];
+                        rep[l] += cnt[l];
+                    }
+                } else {
+                    for (int j = 0; j < 64; ++j) {
+                        if (l == j && valid) {
+                            got = propose(d, pc, et, out);
+                            for (int k = 1; k < got; ++k) {
+                                size[out[k]] += 1;
+                                rep[out[k]] += 1;
+                            }
+                        }
+                        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+                    }
+                }
+                if (valid)
+                    for (int k = 1; k < got; ++k) assign[i * omega + k] = out[k];
+                if (l < SMAX) cnt[l] = 0;
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            }
+        }
+    }
+}
+
 // per (shard, block) member counts, written shard-major: cm[s * nb + b]
 __global__ __launch_bounds__(MEM_BLOCK) void member_count_kernel(const int32_t* __restrict__ assign,
                                                                  int64_t n, int omega, int S, int nb,
@@ -302,6 +506,115 @@ inline Layout layout(int64_t n, int d, int S, int omega) {
     return L;
 }
 
+// Blockwise extra: squared distances of every row (n x S FP32) and the
+// per-block eps^2 tau_t^2 table.
+inline size_t blockwise_extra(int64_t n, int S, int64_t block_rows) {
+    const int64_t nblocks = (n + block_rows - 1) / block_rows;
+    return align_up((size_t)n * S * 4, 256) + align_up((size_t)nblocks * 4, 256) + 512;
+}
+
+// The workspace pieces both entry points share.
+struct Bufs {
+    float* Cf;
+    int32_t* label;
+    double* partial;
+    int64_t* pcount;
+    unsigned int* rbits;
+    int32_t* assign;
+    int64_t* cm;
+    int64_t* cmoff;
+    void* scan_tmp;
+    int64_t* init_d;
+    int64_t ncm;
+};
+
+inline Bufs carve(Carver& cv, const Layout& L, int64_t n, int d, int S, int omega) {
+    Bufs B;
+    B.Cf = cv.take<float>((size_t)S * d);
+    B.label = cv.take<int32_t>(n);
+    B.partial = cv.take<double>((size_t)L.nb_sum * S * d);
+    B.pcount = cv.take<int64_t>((size_t)L.nb_sum * S);
+    B.rbits = cv.take<unsigned int>(S);
+    B.assign = cv.take<int32_t>((size_t)n * omega);
+    B.ncm = (int64_t)S * L.nb_mem;
+    B.cm = cv.take<int64_t>(B.ncm + 1);
+    B.cmoff = cv.take<int64_t>(B.ncm + 1);
+    B.scan_tmp = cv.take<char>(exclusive_scan_tmp_bytes(B.ncm));
+    B.init_d = cv.take<int64_t>(S);
+    return B;
+}
+
+inline int smax_of(int S) { return S <= 8 ? 8 : S <= 16 ? 16 : S <= 32 ? 32 : 64; }
+
+#define SG_BY_SMAX(KERNEL, ...)                                                        \
+    do {                                                                               \
+        switch (::sg::part::smax_of(S)) {                                              \
+            case 8: part::KERNEL<8><<<rg, part::AR, 0, s>>>(__VA_ARGS__); break;       \
+            case 16: part::KERNEL<16><<<rg, part::AR, 0, s>>>(__VA_ARGS__); break;     \
+            case 32: part::KERNEL<32><<<rg, part::AR, 0, s>>>(__VA_ARGS__); break;     \
+            default: part::KERNEL<64><<<rg, part::AR, 0, s>>>(__VA_ARGS__); break;     \
+        }                                                                              \
+        SG_LAUNCH_CHECK();                                                             \
+    } while (0)
+
+// Lloyd k-means (FP64 centroids, fixed-order sums), leaving the FP32 copy of
+// the final centroids in B.Cf.
+inline void run_kmeans(const void* X, int dtype, int64_t n, int d, int64_t ld, int S, int iters,
+                       const int64_t* init_idx_h, double* centroids, const Layout& L, const Bufs& B,
+                       hipStream_t s) {
+    SG_HIP(hipMemcpyAsync(B.init_d, init_idx_h, S * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    init_centroids<<<cdiv((int64_t)S * d, 256), 256, 0, s>>>(X, dtype, ld, d, S, B.init_d, centroids);
+    SG_LAUNCH_CHECK();
+    const unsigned rg = (unsigned)cdiv(n, AR);
+    const unsigned cg = (unsigned)cdiv((int64_t)S * d, 256);
+    for (int it = 0; it < iters; ++it) {
+        to_f32<<<cg, 256, 0, s>>>(centroids, B.Cf, S * d);
+        SG_BY_SMAX(assign_kernel, X, dtype, n, d, ld, B.Cf, S, B.label);
+        dim3 sgrid((unsigned)L.nb_sum, (unsigned)cdiv(d, DSLICE));
+        sum_kernel<<<sgrid, DSLICE, 0, s>>>(X, dtype, n, d, ld, B.label, S, B.partial, B.pcount);
+        finalize_kernel<<<cg, 256, 0, s>>>(B.partial, B.pcount, L.nb_sum, S, d, centroids);
+        SG_LAUNCH_CHECK();
+    }
+    to_f32<<<cg, 256, 0, s>>>(centroids, B.Cf, S * d);
+    SG_LAUNCH_CHECK();
+}
+
+// CSR membership from the n x omega assignment, then the shard offsets on
+// the host (synchronises s).
+inline void run_membership(int64_t n, int S, int omega, int64_t capacity, int32_t* member_ids,
+                           int64_t* shard_offsets_h, const Layout& L, const Bufs& B, hipStream_t s) {
+    member_count_kernel<<<(unsigned)L.nb_mem, MEM_BLOCK, 0, s>>>(B.assign, n, omega, S, L.nb_mem, B.cm);
+    SG_LAUNCH_CHECK();
+    exclusive_scan_i64(B.cm, B.cmoff, B.ncm, B.scan_tmp, s);
+    member_write_kernel<<<(unsigned)L.nb_mem, MEM_BLOCK, 0, s>>>(B.assign, n, omega, S, L.nb_mem, B.cmoff,
+                                                                  capacity, member_ids);
+    SG_LAUNCH_CHECK();
+    std::vector<int64_t> all((size_t)B.ncm + 1);
+    SG_HIP(hipMemcpyAsync(all.data(), B.cmoff, (B.ncm + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SG_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < S; ++c) shard_offsets_h[c] = all[(size_t)c * L.nb_mem];
+    shard_offsets_h[S] = all[(size_t)B.ncm];
+    if (shard_offsets_h[S] > capacity) {
+        set_error("sg_partition: membership (" + std::to_string(shard_offsets_h[S]) + ") exceeds capacity");
+        throw Fail{SG_ERR_ARG};
+    }
+}
+
+inline void check_common(const void* X, int dtype, int64_t n, int d, int64_t ld, int S, int omega, int iters,
+                         float epsilon, const int64_t* init_idx_h, const double* centroids, const int32_t* primary,
+                         const int64_t* shard_offsets_h, const int32_t* member_ids) {
+    SG_REQUIRE(n >= 1 && n < (1ll << 31), "n out of range");
+    SG_REQUIRE(d >= 1 && d <= 4096, "d must be in 1..4096");
+    SG_REQUIRE(ld >= d, "ld must be >= d");
+    SG_REQUIRE(S >= 1 && S <= MAX_S, "S must be in 1..64");
+    SG_REQUIRE(omega >= 1 && omega <= S && omega <= MAX_OMEGA, "omega must be in 1..min(S, 8)");
+    SG_REQUIRE(iters >= 0, "iters must be >= 0");
+    SG_REQUIRE(dtype >= SG_F32 && dtype <= SG_U8, "unknown dtype");
+    SG_REQUIRE(!(epsilon != epsilon), "epsilon must not be NaN");
+    SG_REQUIRE(X && init_idx_h && centroids && primary && shard_offsets_h && member_ids, "NULL pointer");
+    for (int c = 0; c < S; ++c) SG_REQUIRE(init_idx_h[c] >= 0 && init_idx_h[c] < n, "init_idx out of range");
+}
+
 }  // namespace part
 }  // namespace sg
 
@@ -322,18 +635,9 @@ extern "C" sg_status sg_partition(const void* X, sg_dtype dtype, int64_t n, int3
                                   int64_t* shard_offsets_h, int32_t* member_ids, int64_t capacity,
                                   void* ws, size_t ws_bytes, void* stream) {
     return guarded([&] {
-        SG_REQUIRE(n >= 1 && n < (1ll << 31), "n out of range");
-        SG_REQUIRE(d >= 1 && d <= 4096, "d must be in 1..4096");
-        SG_REQUIRE(ld >= d, "ld must be >= d");
-        SG_REQUIRE(S >= 1 && S <= part::MAX_S, "S must be in 1..64");
-        SG_REQUIRE(omega >= 1 && omega <= S && omega <= part::MAX_OMEGA, "omega must be in 1..min(S, 8)");
-        SG_REQUIRE(iters >= 0, "iters must be >= 0");
-        SG_REQUIRE(dtype >= SG_F32 && dtype <= SG_U8, "unknown dtype");
-        SG_REQUIRE(!(epsilon != epsilon) && !(tau != tau), "epsilon and tau must not be NaN");
-        SG_REQUIRE(X && init_idx_h && centroids && primary && shard_offsets_h && member_ids,
-                   "NULL pointer");
-        for (int c = 0; c < S; ++c)
-            SG_REQUIRE(init_idx_h[c] >= 0 && init_idx_h[c] < n, "init_idx out of range");
+        part::check_common(X, dtype, n, d, ld, S, omega, iters, epsilon, init_idx_h, centroids, primary,
+                           shard_offsets_h, member_ids);
+        SG_REQUIRE(!(tau != tau), "tau must not be NaN");
         part::Layout L = part::layout(n, d, S, omega);
         if (ws == nullptr || ws_bytes < L.total) {
             set_error("sg_partition: workspace too small (need " + std::to_string(L.total) + " bytes)");
@@ -341,68 +645,77 @@ extern "C" sg_status sg_partition(const void* X, sg_dtype dtype, int64_t n, int3
         }
         hipStream_t s = as_stream(stream);
         Carver cv(ws);
-        float* Cf = cv.take<float>((size_t)S * d);
-        int32_t* label = cv.take<int32_t>(n);
-        double* partial = cv.take<double>((size_t)L.nb_sum * S * d);
-        int64_t* pcount = cv.take<int64_t>((size_t)L.nb_sum * S);
-        unsigned int* rbits = cv.take<unsigned int>(S);
-        int32_t* assign = cv.take<int32_t>((size_t)n * omega);
-        const int64_t ncm = (int64_t)S * L.nb_mem;
-        int64_t* cm = cv.take<int64_t>(ncm + 1);
-        int64_t* cmoff = cv.take<int64_t>(ncm + 1);
-        void* scan_tmp = cv.take<char>(exclusive_scan_tmp_bytes(ncm));
-        int64_t* init_d = cv.take<int64_t>(S);
-
-        SG_HIP(hipMemcpyAsync(init_d, init_idx_h, S * sizeof(int64_t), hipMemcpyHostToDevice, s));
-        part::init_centroids<<<cdiv((int64_t)S * d, 256), 256, 0, s>>>(X, dtype, ld, d, S, init_d, centroids);
-        SG_LAUNCH_CHECK();
+        const part::Bufs B = part::carve(cv, L, n, d, S, omega);
+        part::run_kmeans(X, dtype, n, d, ld, S, iters, init_idx_h, centroids, L, B, s);
         const unsigned rg = (unsigned)cdiv(n, part::AR);
-        const unsigned cg = (unsigned)cdiv((int64_t)S * d, 256);
-        const int smax = S <= 8 ? 8 : S <= 16 ? 16 : S <= 32 ? 32 : 64;
-#define SG_BY_SMAX(KERNEL, ...)                                                        \
-        do {                                                                           \
-            switch (smax) {                                                            \
-                case 8: part::KERNEL<8><<<rg, part::AR, 0, s>>>(__VA_ARGS__); break;   \
-                case 16: part::KERNEL<16><<<rg, part::AR, 0, s>>>(__VA_ARGS__); break; \
-                case 32: part::KERNEL<32><<<rg, part::AR, 0, s>>>(__VA_ARGS__); break; \
-                default: part::KERNEL<64><<<rg, part::AR, 0, s>>>(__VA_ARGS__); break; \
-            }                                                                          \
-            SG_LAUNCH_CHECK();                                                         \
-        } while (0)
-        for (int it = 0; it < iters; ++it) {
-            part::to_f32<<<cg, 256, 0, s>>>(centroids, Cf, S * d);
-            SG_BY_SMAX(assign_kernel, X, dtype, n, d, ld, Cf, S, label);
-            dim3 sgrid((unsigned)L.nb_sum, (unsigned)cdiv(d, part::DSLICE));
-            part::sum_kernel<<<sgrid, part::DSLICE, 0, s>>>(X, dtype, n, d, ld, label, S, partial, pcount);
-            part::finalize_kernel<<<cg, 256, 0, s>>>(partial, pcount, L.nb_sum, S, d, centroids);
-            SG_LAUNCH_CHECK();
-        }
-        part::to_f32<<<cg, 256, 0, s>>>(centroids, Cf, S * d);
-        SG_BY_SMAX(assign_kernel, X, dtype, n, d, ld, Cf, S, label);
-        fill<unsigned int>(rbits, 0u, S, s);
-        SG_BY_SMAX(radius_kernel, X, dtype, n, d, ld, Cf, S, label, rbits);
+        SG_BY_SMAX(assign_kernel, X, dtype, n, d, ld, B.Cf, S, B.label);
+        fill<unsigned int>(B.rbits, 0u, S, s);
+        SG_BY_SMAX(radius_kernel, X, dtype, n, d, ld, B.Cf, S, B.label, B.rbits);
         const int accept_all = std::isinf(epsilon) && epsilon > 0;
-        SG_BY_SMAX(replica_kernel, X, dtype, n, d, ld, Cf, S, label, rbits, omega, epsilon, tau, accept_all,
-                   assign);
-#undef SG_BY_SMAX
-        part::member_count_kernel<<<(unsigned)L.nb_mem, part::MEM_BLOCK, 0, s>>>(assign, n, omega, S,
-                                                                                 L.nb_mem, cm);
-        SG_LAUNCH_CHECK();
-        exclusive_scan_i64(cm, cmoff, ncm, scan_tmp, s);
-        part::member_write_kernel<<<(unsigned)L.nb_mem, part::MEM_BLOCK, 0, s>>>(
-            assign, n, omega, S, L.nb_mem, cmoff, capacity, member_ids);
-        SG_LAUNCH_CHECK();
-        SG_HIP(hipMemcpyAsync(primary, label, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        // shard offsets: the scanned count matrix at each shard's first block
-        std::vector<int64_t> all((size_t)ncm + 1);
-        SG_HIP(hipMemcpyAsync(all.data(), cmoff, (ncm + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        SG_HIP(hipStreamSynchronize(s));
-        for (int c = 0; c < S; ++c) shard_offsets_h[c] = all[(size_t)c * L.nb_mem];
-        shard_offsets_h[S] = all[(size_t)ncm];
-        if (shard_offsets_h[S] > capacity) {
-            set_error("sg_partition: membership (" + std::to_string(shard_offsets_h[S]) +
-                      ") exceeds capacity");
-            throw Fail{SG_ERR_ARG};
+        SG_BY_SMAX(replica_kernel, X, dtype, n, d, ld, B.Cf, S, B.label, B.rbits, omega, epsilon, tau, accept_all,
+                   B.assign);
+        SG_HIP(hipMemcpyAsync(primary, B.label, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        part::run_membership(n, S, omega, capacity, member_ids, shard_offsets_h, L, B, s);
+    });
+}
+
+extern "C" sg_status sg_partition_blockwise_workspace_size(int64_t n, int32_t d, int32_t S, int32_t omega,
+                                                           int64_t block_rows, size_t* bytes) {
+    return guarded([&] {
+        SG_REQUIRE(bytes != nullptr, "bytes is NULL");
+        SG_REQUIRE(n >= 1 && d >= 1 && S >= 1 && omega >= 1 && block_rows >= 1, "bad sizes");
+        *bytes = part::layout(n, d, S, omega).total + part::blockwise_extra(n, S, block_rows);
+    });
+}
+
+extern "C" sg_status sg_partition_blockwise(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64_t ld,
+                                            int32_t S, int32_t omega, int32_t iters, float epsilon, float tau0,
+                                            int64_t block_rows, int64_t shard_cap, int32_t adaptive,
+                                            const int64_t* init_idx_h, double* centroids, int32_t* primary,
+                                            int64_t* shard_offsets_h, int32_t* member_ids, int64_t capacity,
+                                            void* ws, size_t ws_bytes, void* stream) {
+    return guarded([&] {
+        part::check_common(X, dtype, n, d, ld, S, omega, iters, epsilon, init_idx_h, centroids, primary,
+                           shard_offsets_h, member_ids);
+        SG_REQUIRE(tau0 >= 1.0f, "tau0 must be >= 1 (and not NaN)");
+        SG_REQUIRE(block_rows >= 1, "block_rows must be >= 1");
+        SG_REQUIRE(shard_cap >= 0, "shard_cap must be >= 0 (0: no limit)");
+        SG_REQUIRE(adaptive == 0 || adaptive == 1, "adaptive must be 0 or 1");
+        part::Layout L = part::layout(n, d, S, omega);
+        const size_t need = L.total + part::blockwise_extra(n, S, block_rows);
+        if (ws == nullptr || ws_bytes < need) {
+            set_error("sg_partition_blockwise: workspace too small (need " + std::to_string(need) + " bytes)");
+            throw Fail{SG_ERR_WORKSPACE};
         }
+        hipStream_t s = as_stream(stream);
+        Carver cv(ws);
+        const part::Bufs B = part::carve(cv, L, n, d, S, omega);
+        const int64_t nblocks = (n + block_rows - 1) / block_rows;
+        float* D2 = cv.take<float>((size_t)n * S);
+        float* et2_d = cv.take<float>((size_t)nblocks);
+        part::run_kmeans(X, dtype, n, d, ld, S, iters, init_idx_h, centroids, L, B, s);
+        const unsigned rg = (unsigned)cdiv(n, part::AR);
+        SG_BY_SMAX(sqdist_kernel, X, dtype, n, d, ld, B.Cf, S, D2);
+        // eps^2 and eps^2 tau_t^2 per block, in FP32 on the host:
+        // tau_t = 1 + (tau0 - 1) / t for block t = 1, 2, ...
+        const int accept_all = std::isinf(epsilon) && epsilon > 0;
+        const float eps2 = accept_all ? 0.f : epsilon * epsilon;
+        std::vector<float> et2((size_t)nblocks);
+        for (int64_t t = 1; t <= nblocks; ++t) {
+            const float tau_t = 1.0f + (tau0 - 1.0f) / (float)t;
+            et2[(size_t)t - 1] = eps2 * (tau_t * tau_t);
+        }
+        SG_HIP(hipMemcpyAsync(et2_d, et2.data(), (size_t)nblocks * sizeof(float), hipMemcpyHostToDevice, s));
+        switch (part::smax_of(S)) {
+#define SG_BW(SM)                                                                                              \
+            case SM:                                                                                           \
+                part::blockwise_kernel<SM><<<1, 64, 0, s>>>(D2, n, S, omega, eps2, et2_d, block_rows, shard_cap, \
+                                                            adaptive, accept_all, B.assign, primary);          \
+                break;
+            SG_BW(8) SG_BW(16) SG_BW(32) SG_BW(64)
+#undef SG_BW
+        }
+        SG_LAUNCH_CHECK();
+        part::run_membership(n, S, omega, capacity, member_ids, shard_offsets_h, L, B, s);
     });
 }

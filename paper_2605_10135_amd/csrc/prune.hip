@@ -3,7 +3,8 @@
 // The graph-optimisation stage of the CAGRA-style shard build (Sec. II-A,
 // Sec. IV step 2), as integer passes:
 //  * Rows are visited in the caller's order (a permutation of the rows, e.g.
-//    the locality order of the kNN build) or in row order, and each XCD takes
+//    the locality order of the kNN build; anything else is detected on the
+//    device and replaced by row order) or in row order, and each XCD takes
 //    one contiguous range of that order, so that the rows one L2 serves at a
 //    time are neighbours and share neighbour lists; the results do not depend
 //    on the order.
@@ -48,12 +49,30 @@ __device__ inline uint32_t cuckoo_h0(uint32_t m) { return ((m * 0x9E3779u) >> 8)
 template <int CT>
 __device__ inline uint32_t cuckoo_h1(uint32_t m) { return ((m * 0x85EBCBu) >> 16) & (CT - 1); }
 
+// Flags *bad unless order[0..n) is a permutation of 0..n-1: every entry in
+// range and no row seen twice (n entries, so none is then missing).  seen
+// (n counters) and *bad start at zero.
+__global__ void order_check_kernel(const int32_t* __restrict__ order, int64_t n, int32_t* __restrict__ seen,
+                                   int32_t* __restrict__ bad) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t x = order[i];
+        if (x < 0 || x >= n || atomicAdd(&seen[x], 1) != 0) *bad = 1;
+    }
+}
+
+// The row a wave at position `slot` of the visiting order handles: order[slot]
+// when the caller's order passed the check, else the row at that position.
+__device__ inline int64_t visit_row(const int32_t* order, const int32_t* order_bad, int64_t slot) {
+    return (order && *order_bad == 0) ? (int64_t)order[slot] : slot;
+}
+
 // KP: list entries per lane (ceil(K/64)); CT: slots per cuckoo table (power of
 // two, 4 * 64 * KP).  Also counts the in-degree of every row in P (cnt,
 // zeroed by the caller).
 template <int KP, int CT>
 __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__ knn, int64_t n,
                                                      int K, int R, const int32_t* __restrict__ order,
+                                                     const int32_t* __restrict__ order_bad,
                                                      int32_t* __restrict__ P, int32_t* __restrict__ rslot,
                                                      int64_t* __restrict__ cnt) {
     __shared__ uint64_t s_t[WAVES][2 * CT];
@@ -63,8 +82,7 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
     const int w = threadIdx.x >> 6;
     const int64_t slot = xcd_contiguous(blockIdx.x, gridDim.x) * WAVES + w;
     if (slot >= n) return;
-    const int64_t x = order ? order[slot] : slot;
-    if (x < 0 || x >= n) return;
+    const int64_t x = visit_row(order, order_bad, slot);
     uint64_t* T0 = s_t[w];
     uint64_t* T1 = s_t[w] + CT;
     int32_t* det = s_det[w];
@@ -246,13 +264,13 @@ __global__ __launch_bounds__(256) void combine_kernel(const int32_t* __restrict_
                                                       const int64_t* __restrict__ off,
                                                       const uint32_t* __restrict__ rev,
                                                       const int32_t* __restrict__ order,
+                                                      const int32_t* __restrict__ order_bad,
                                                       int32_t* __restrict__ F) {
     const int l = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int64_t slot = xcd_contiguous(blockIdx.x, gridDim.x) * WAVES + w;
     if (slot >= n) return;
-    const int64_t y = order ? order[slot] : slot;
-    if (y < 0 || y >= n) return;
+    const int64_t y = visit_row(order, order_bad, slot);
     const int h = (R + 1) / 2;
     const int64_t b = off[y], cnt = off[y + 1] - off[y];
     // the 64 smallest reverse keys, ascending, one per lane
@@ -293,7 +311,7 @@ __global__ __launch_bounds__(256) void combine_kernel(const int32_t* __restrict_
 }
 
 struct Layout {
-    size_t P, rslot, cnt, off, rev, scan, total;
+    size_t P, rslot, cnt, off, rev, scan, seen, total;
 };
 
 inline Layout layout(int64_t n, int R) {
@@ -304,7 +322,8 @@ inline Layout layout(int64_t n, int R) {
     L.off = align_up((size_t)(n + 1) * 8, 256);
     L.rev = align_up((size_t)n * R * 4, 256);
     L.scan = align_up(exclusive_scan_tmp_bytes(n), 256);
-    L.total = L.P + L.rslot + L.cnt + L.off + L.rev + L.scan + 1024;
+    L.seen = align_up((size_t)(n + 64) * 4, 256);   // order check: per-row counters + flag
+    L.total = L.P + L.rslot + L.cnt + L.off + L.rev + L.scan + L.seen + 1024;
     return L;
 }
 
@@ -342,22 +361,30 @@ extern "C" sg_status sg_prune(const int32_t* knn, int64_t n, int32_t K, int32_t 
         int64_t* off = cv.take<int64_t>(n + 1);
         uint32_t* rev = cv.take<uint32_t>((size_t)n * R);
         void* scan_tmp = cv.take<char>(exclusive_scan_tmp_bytes(n));
+        int32_t* seen = cv.take<int32_t>(n + 64);
+        int32_t* order_bad = seen + n;
 
         unsigned grid = (unsigned)cdiv(n, prune::WAVES);
         fill<int64_t>(cnt, 0, n + 1, s);
+        if (order) {   // a non-permutation falls back to row order (same result)
+            fill<int32_t>(seen, 0, n + 1, s);
+            prune::order_check_kernel<<<(unsigned)std::min<int64_t>(cdiv(n, 256), 4096), 256, 0, s>>>(
+                order, n, seen, order_bad);
+            SG_LAUNCH_CHECK();
+        }
         if (K <= 64)
-            prune::detour_kernel<1, 256><<<grid, 256, 0, s>>>(knn, n, K, R, order, P, rslot, cnt);
+            prune::detour_kernel<1, 256><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt);
         else if (K <= 128)
-            prune::detour_kernel<2, 512><<<grid, 256, 0, s>>>(knn, n, K, R, order, P, rslot, cnt);
+            prune::detour_kernel<2, 512><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt);
         else
-            prune::detour_kernel<4, 1024><<<grid, 256, 0, s>>>(knn, n, K, R, order, P, rslot, cnt);
+            prune::detour_kernel<4, 1024><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt);
         SG_LAUNCH_CHECK();
         int64_t total = n * (int64_t)R;
         unsigned eg = (unsigned)std::min<int64_t>(cdiv(total, 256), 8192);
         exclusive_scan_i64(cnt, off, n, scan_tmp, s);
         prune::scatter_kernel<<<eg, 256, 0, s>>>(P, rslot, total, R, off, rev);
         SG_LAUNCH_CHECK();
-        prune::combine_kernel<<<grid, 256, 0, s>>>(P, n, R, off, rev, order, out);
+        prune::combine_kernel<<<grid, 256, 0, s>>>(P, n, R, off, rev, order, order_bad, out);
         SG_LAUNCH_CHECK();
     });
 }

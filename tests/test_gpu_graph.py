@@ -186,3 +186,24 @@ def test_knn_order_is_permutation_and_prune_order_free():
     small = torch.empty(500, dtype=torch.int32, device=DEV)
     sg.sg_knn_graph(Xg[:500], 16, "l2", "f16", dist=False, order_out=small)
     assert np.array_equal(small.cpu().numpy(), np.arange(500))
+
+
+def test_prune_order_that_is_not_a_permutation_is_ignored():
+    """sg_prune visits rows in the caller's order only when it is a
+    permutation; repeated, missing or out-of-range entries are detected on the
+    device and the rows are visited in row order: the result is unchanged."""
+    n, K, R = 900, 32, 16
+    knn = synthdata.local_graph(n, K, seed=41)
+    ref = oracle.prune(knn, R)
+    kd = torch.from_numpy(knn).to(DEV)
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(n).astype(np.int32)
+    dup = perm.copy()
+    dup[10] = dup[11]                       # a repeat (and so a missing row)
+    oob = perm.copy()
+    oob[5] = n + 7                          # out of range
+    neg = perm.copy()
+    neg[0] = -3
+    for order in (perm, dup, oob, neg, np.zeros(n, np.int32)):
+        out = sg.sg_prune(kd, R, order=torch.from_numpy(order).to(DEV))
+        np.testing.assert_array_equal(out.cpu().numpy(), ref)

@@ -264,3 +264,19 @@ def test_knn_locality_order_f32_and_rerank():
     nb2, d2 = sg.sg_knn_graph(Xg, 32, "ip", "bf16", rerank=64)
     torch.cuda.synchronize()
     assert recall(nb2.cpu().numpy(), onbr) >= 0.99
+
+
+@pytest.mark.parametrize("n,levels", [(6000, 256), (5000, 4)])
+def test_knn_order_is_deterministic_and_a_permutation(n, levels):
+    """The locality order sg_knn_graph returns is a stable sort by pivot: the
+    same call gives the same order, bit for bit, and it is a permutation."""
+    X = _u8(n, 32, seed=n, levels=levels)
+    Xg = torch.from_numpy(X).to(DEV)
+    o1 = torch.empty(n, dtype=torch.int32, device=DEV)
+    o2 = torch.empty(n, dtype=torch.int32, device=DEV)
+    a, _ = sg.sg_knn_graph(Xg, 16, "l2", "f16", order_out=o1)
+    b, _ = sg.sg_knn_graph(Xg, 16, "l2", "f16", order_out=o2)
+    torch.cuda.synchronize()
+    assert torch.equal(o1, o2)
+    assert torch.equal(a, b)
+    assert np.array_equal(np.sort(o1.cpu().numpy()), np.arange(n))

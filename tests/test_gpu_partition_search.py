@@ -109,3 +109,63 @@ def test_search_medoid_entry_and_wide_graph():
         ids2, _ = sg.sg_search(torch.from_numpy(X).to(DEV), torch.from_numpy(wide).to(DEV),
                                torch.from_numpy(Q).to(DEV), 10, 40, entry=ent)
         np.testing.assert_array_equal(ids2.cpu().numpy(), oids)
+
+
+def _blockwise_pair(X, S, omega, iters, init, eps, tau0, block_rows, cap, adaptive):
+    got = sg.sg_partition_blockwise(torch.from_numpy(X).to(DEV), S, omega, iters, init, eps, tau0, block_rows,
+                                    cap, adaptive)
+    want = oracle.partition_blockwise(oracle.widen(X), S, omega, iters, init, eps, tau0, block_rows, cap, adaptive)
+    return got, want
+
+
+def _assert_same(got, want):
+    C, prim, off, mem = got
+    oC, oprim, ooff, omem = want
+    np.testing.assert_array_equal(C.cpu().numpy(), oC)
+    np.testing.assert_array_equal(prim.cpu().numpy(), oprim)
+    np.testing.assert_array_equal(off.numpy(), ooff)
+    np.testing.assert_array_equal(mem.cpu().numpy(), omem)
+
+
+@pytest.mark.parametrize("block_rows,cap,adaptive", [(1, 2, False), (1, 2, True), (3, 3, True), (6, 0, True)])
+def test_blockwise_fig2_rows(block_rows, cap, adaptive):
+    """The Fig. 2 vectors first, then the three centroid rows (the initial
+    centroids), in blocks: identical to the oracle, and with one vector per
+    block, capacity 2 and no thresholds the v-rows show the lock-out of the
+    paper's example (with thresholds, n = 6 rows make theta decline v3's
+    replica, a different but equally checked outcome)."""
+    with open(os.path.join(GOLD, "blockwise_capacity.json")) as f:
+        g = json.load(f)["fig2"]
+    X = np.array(g["vectors"] + g["centroids"], np.float32)
+    got, want = _blockwise_pair(X, 3, 2, 0, [3, 4, 5], float("inf"), 1.0, block_rows, cap, adaptive)
+    _assert_same(got, want)
+    if block_rows == 1 and cap == 2 and not adaptive:
+        assign = [[s for s in range(3) if i in want[3][want[2][s]:want[2][s + 1]]] for i in range(3)]
+        exp = [sorted(r) for r in g["expected_one_vector_per_block"]]
+        assert assign == exp
+
+
+@pytest.mark.parametrize("iters", [0, 1])
+@pytest.mark.parametrize("S,omega,eps,tau0,block_rows,cap,adaptive", [
+    (4, 2, float("inf"), 1.0, 3000, 0, True),            # one block, no limit: the single-block rule
+    (6, 3, float(np.float32(1.2)), 2.0, 500, 0, True),   # many blocks, radius factor falling
+    (6, 2, float("inf"), 1.0, 257, 700, True),           # capacity binds, thresholds on
+    (6, 2, float("inf"), 1.0, 257, 700, False),          # capacity binds, thresholds off
+    (8, 3, float(np.float32(1.5)), 3.0, 1000, 450, True),  # everything at once, primaries overflow
+    (5, 2, float(np.float32(1.5)), 2.0, 1, 800, True),   # one row per block
+])
+def test_blockwise_u8_exact(iters, S, omega, eps, tau0, block_rows, cap, adaptive):
+    n = 3000 if block_rows > 1 else 700
+    X = synthdata.sift_like_u8(n=n, d=16, seed=S * 10 + omega + cap, n_comp=12)
+    init = synthdata.init_rows(n, S, seed=S + 1)
+    got, want = _blockwise_pair(X, S, omega, iters, init, eps, tau0, block_rows, cap, adaptive)
+    _assert_same(got, want)
+
+
+def test_blockwise_float_rows_exact():
+    """Float rows with the initial centroids (no Lloyd step): both sides form
+    the same FP32 distances in the same order, so every decision agrees."""
+    X = synthdata.mixture(5000, 24, 10, 0.4, seed=12)
+    init = synthdata.init_rows(5000, 10, seed=3)
+    got, want = _blockwise_pair(X, 10, 3, 0, init, float(np.float32(1.3)), 2.5, 640, 1400, True)
+    _assert_same(got, want)
