@@ -1326,20 +1326,10 @@ struct Kern {
     near_fn near = nullptr;       // nearest-candidate kernel on the same operands
 };
 
-template <int P, int NSTEP, int W, int QB = 1, int CBQ = CB, int BCR = 0>
-topk_fn pick_ksel(int ksel) {
-    switch (ksel) {
-        case 32: return dist_topk_kernel<P, NSTEP, 32, W, QB, CBQ, BCR>;
-        case 64: return dist_topk_kernel<P, NSTEP, 64, W, QB, CBQ, BCR>;
-        case 128: return dist_topk_kernel<P, NSTEP, 128, W, QB, CBQ, BCR>;
-        default: return dist_topk_kernel<P, NSTEP, 256, W, QB, CBQ, BCR>;
-    }
-}
-
-template <int P, int NSTEP, int W, int QB = 1, int CBQ = CB, int BCR = 0>
-Kern resident(int ksel) {
+template <int P, int NSTEP, int W, int QB, int CBQ, int BCR, int KSEL>
+Kern resident() {
     Kern k;
-    k.fn = pick_ksel<P, NSTEP, W, QB, CBQ, BCR>(ksel);
+    k.fn = dist_topk_kernel<P, NSTEP, KSEL, W, QB, CBQ, BCR>;
     k.DP = 2 * NSTEP * Tr<P>::VEC;
     k.nq_block = 32 * W * QB;
     k.threads = 64 * W;
@@ -1359,74 +1349,42 @@ Kern resident(int ksel) {
 // keep the MFMA and VALU units busy while one waits at its tile barrier or on
 // a merge.  Returns false if no resident kernel serves the row length (FP32
 // rows wider than 128 use the k-streamed kernel).
+// Each precision's table is instantiated in a translation unit of its own
+// (shapes_*.hip), one per selection width, so that the kernels compile in
+// parallel; the definition is in shapes.hpp.
+template <int PR, class M>
+bool for_shapes_p(int d, M& m);
+
 template <class M>
 bool for_shapes(int prec, int d, M& m) {
-    const int need = nstep_for(prec, padded_d(prec, d));
-#define SG_ONE(PR, NS, W0) m.template add<PR, NS, W0, 1, CB, 0>()
-#define SG_THREE(PR, NS, W0)                     \
-    do {                                         \
-        m.template add<PR, NS, W0, 1, CB, 0>();  \
-        m.template add<PR, NS, 4, 1, CB, 64>();  \
-        m.template add<PR, NS, 4, 1, CB, 32>();  \
-    } while (0)
-// ... and, for short 16-bit / FP8 rows, 16-entry buffers with 32-row tiles
-// (four workgroups per CU)
-#define SG_FOUR(PR, NS, W0)                      \
-    do {                                         \
-        SG_THREE(PR, NS, W0);                    \
-        m.template add<PR, NS, 4, 1, 16, 32>();  \
-    } while (0)
     switch (prec) {
-        case SG_PREC_FP32:
-            if (need <= 16) SG_THREE(SG_PREC_FP32, 16, TWAVES);
-            else if (need <= 32) SG_THREE(SG_PREC_FP32, 32, TWAVES);
-            else if (need <= 48) SG_ONE(SG_PREC_FP32, 48, TWAVES);
-            else if (need <= 64) SG_ONE(SG_PREC_FP32, 64, TWAVES);
-            else return false;
-            return true;
-        case SG_PREC_F16:
-            if (need <= 2) SG_ONE(SG_PREC_F16, 2, TWAVES);
-            else if (need <= 4) SG_FOUR(SG_PREC_F16, 4, TWAVES);
-            else if (need <= 6) SG_FOUR(SG_PREC_F16, 6, TWAVES);
-            else if (need <= 8) SG_FOUR(SG_PREC_F16, 8, TWAVES);
-            else if (need <= 12) SG_ONE(SG_PREC_F16, 12, TWAVES);
-            else if (need <= 16) SG_ONE(SG_PREC_F16, 16, TWAVES);
-            else if (need <= 24) SG_ONE(SG_PREC_F16, 24, 4);
-            else if (need <= 32) SG_ONE(SG_PREC_F16, 32, 4);
-            else if (need <= 48) SG_ONE(SG_PREC_F16, 48, 4);
-            else return false;
-            return true;
-        case SG_PREC_BF16:
-            if (need <= 2) SG_ONE(SG_PREC_BF16, 2, TWAVES);
-            else if (need <= 4) SG_FOUR(SG_PREC_BF16, 4, TWAVES);
-            else if (need <= 6) SG_FOUR(SG_PREC_BF16, 6, TWAVES);
-            else if (need <= 8) SG_FOUR(SG_PREC_BF16, 8, TWAVES);
-            else if (need <= 12) SG_ONE(SG_PREC_BF16, 12, TWAVES);
-            else if (need <= 16) SG_ONE(SG_PREC_BF16, 16, TWAVES);
-            else if (need <= 24) SG_ONE(SG_PREC_BF16, 24, 4);
-            else if (need <= 32) SG_ONE(SG_PREC_BF16, 32, 4);
-            else if (need <= 48) SG_ONE(SG_PREC_BF16, 48, 4);
-            else return false;
-            return true;
-        default:
-            if (need <= 1) SG_FOUR(SG_PREC_FP8, 1, TWAVES);
-            else if (need <= 2) SG_FOUR(SG_PREC_FP8, 2, TWAVES);
-            else if (need <= 4) SG_ONE(SG_PREC_FP8, 4, TWAVES);
-            else if (need <= 8) SG_ONE(SG_PREC_FP8, 8, 4);
-            else if (need <= 16) SG_ONE(SG_PREC_FP8, 16, 4);
-            else return false;
-            return true;
+        case SG_PREC_FP32: return for_shapes_p<SG_PREC_FP32>(d, m);
+        case SG_PREC_F16: return for_shapes_p<SG_PREC_F16>(d, m);
+        case SG_PREC_BF16: return for_shapes_p<SG_PREC_BF16>(d, m);
+        default: return for_shapes_p<SG_PREC_FP8>(d, m);
     }
-#undef SG_ONE
-#undef SG_THREE
 }
 
+template <int KSEL>
 struct ResidentMaker {
-    int ksel;
     std::vector<Kern> v;
     template <int P, int NSTEP, int W, int QB, int CBQ, int BCR>
-    void add() { v.push_back(resident<P, NSTEP, W, QB, CBQ, BCR>(ksel)); }
+    void add() { v.push_back(resident<P, NSTEP, W, QB, CBQ, BCR, KSEL>()); }
 };
+
+// Every table slice is instantiated explicitly in its own translation unit;
+// these declarations keep the other units (and each slice, for the other
+// slices) from instantiating them implicitly.
+#define SG_EXTERN_SLICE(PR, MAKER) extern template bool for_shapes_p<PR, MAKER>(int, MAKER&);
+#define SG_EXTERN_SLICES(MAKER_T, K)                  \
+    SG_EXTERN_SLICE(SG_PREC_FP32, MAKER_T<K>)         \
+    SG_EXTERN_SLICE(SG_PREC_F16, MAKER_T<K>)          \
+    SG_EXTERN_SLICE(SG_PREC_BF16, MAKER_T<K>)         \
+    SG_EXTERN_SLICE(SG_PREC_FP8, MAKER_T<K>)
+SG_EXTERN_SLICES(ResidentMaker, 32)
+SG_EXTERN_SLICES(ResidentMaker, 64)
+SG_EXTERN_SLICES(ResidentMaker, 128)
+SG_EXTERN_SLICES(ResidentMaker, 256)
 
 inline Kern kstream_kernel(int d, int ksel) {
     Kern k;
@@ -1444,8 +1402,15 @@ inline Kern kstream_kernel(int d, int ksel) {
 
 // Every distance kernel for (prec, d, ksel), default first (empty if none).
 inline std::vector<Kern> kernel_variants(int prec, int d, int ksel) {
-    ResidentMaker m{ksel, {}};
-    if (for_shapes(prec, d, m)) return m.v;
+    bool ok = false;
+    std::vector<Kern> v;
+    switch (ksel) {
+        case 32: { ResidentMaker<32> m; ok = for_shapes(prec, d, m); v = m.v; break; }
+        case 64: { ResidentMaker<64> m; ok = for_shapes(prec, d, m); v = m.v; break; }
+        case 128: { ResidentMaker<128> m; ok = for_shapes(prec, d, m); v = m.v; break; }
+        default: { ResidentMaker<256> m; ok = for_shapes(prec, d, m); v = m.v; break; }
+    }
+    if (ok) return v;
     if (prec == SG_PREC_FP32 && d <= 1024) return {kstream_kernel(d, ksel)};
     return {};
 }
