@@ -237,9 +237,9 @@ sg_status sg_knn_rows(const void* X, sg_dtype dtype, int64_t n, int32_t d, int64
  * shard), followed by sg_prune to degree R:
  *    graphs[offsets_h[s] + i][0..R)  pruned list of local row i of shard s,
  *    knn   [offsets_h[s] + i][0..k)  its kNN list (knn may be NULL).
- * k in 1..128, R in 1..min(k, 64); rows need a register-resident distance
+ * k in 1..256, R in 1..min(k, 128); rows need a register-resident distance
  * kernel (FP32 d <= 128, 16-bit d <= 768, FP8 d <= 1024).  rerank: 0, or a
- * candidate width c in k..128 as in sg_knn_graph (the c best by the prec
+ * candidate width c in k..256 as in sg_knn_graph (the c best by the prec
  * key, re-ranked by exact FP32 distance to the k lists).  The distance work
  * of all shards is one persistent launch (largest shards first); the launch
  * shape is the one sg_knn_autotune recorded for the largest shard, else the
@@ -338,7 +338,7 @@ sg_status sg_knn_graph_learned(const void* X, sg_dtype dtype, int32_t d, int64_t
  *            ++ (P(y)[h:R] entries not yet present), cut at R.
  *  knn : n x K int32, each row's valid ids distinct, in [0, n), != the row,
  *        followed by any SG_NONE padding (as sg_knn_graph writes it).
- *  K   : 1..256;  R: 1..min(K, 64).   out: n x R int32 (SG_NONE padded).
+ *  K   : 1..256;  R: 1..min(K, 128).  out: n x R int32 (SG_NONE padded).
  *  Ids outside [0, n) in knn are treated as SG_NONE.
  *  order: NULL, or n device int32 giving the order in which rows are
  *        processed, e.g. the order sg_knn_graph returns, so that rows

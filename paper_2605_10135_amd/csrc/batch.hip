@@ -96,9 +96,9 @@ Plan make_plan(const int64_t* off, int S, int d, int k, int R, int prec, int rer
     SG_REQUIRE(off != nullptr, "offsets_h is NULL");
     SG_REQUIRE(off[0] == 0, "offsets_h[0] must be 0");
     SG_REQUIRE(d >= 1 && d <= 1024, "d out of range");
-    SG_REQUIRE(k >= 1 && k <= 128, "k must be in 1..128 for the batched build");
-    SG_REQUIRE(rerank == 0 || (rerank >= k && rerank <= 128), "rerank must be 0 or in k..128 for the batched build");
-    SG_REQUIRE(R >= 1 && R <= k && R <= 64, "R must be in 1..min(k, 64)");
+    SG_REQUIRE(k >= 1 && k <= 256, "k must be in 1..256");
+    SG_REQUIRE(rerank == 0 || (rerank >= k && rerank <= 256), "rerank must be 0 or in k..256");
+    SG_REQUIRE(R >= 1 && R <= k && R <= 128, "R must be in 1..min(k, 128)");
     SG_REQUIRE(prec >= SG_PREC_FP32 && prec <= SG_PREC_FP8, "unknown precision");
     Plan p;
     p.S = S;

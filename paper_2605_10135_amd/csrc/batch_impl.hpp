@@ -128,18 +128,23 @@ struct BatchedMaker {
 namespace knn {
 SG_EXTERN_SLICES(batch::BatchedMaker, 64)
 SG_EXTERN_SLICES(batch::BatchedMaker, 128)
+SG_EXTERN_SLICES(batch::BatchedMaker, 256)
 }  // namespace knn
 namespace batch {
 
-// The launch shapes of a batched call with selection width ksel (64 or 128).
+// The launch shapes of a batched call with selection width ksel (64, 128 or 256).
 inline bool batched_shapes(int prec, int d, int ksel, std::vector<BKern>& v) {
     bool ok;
     if (ksel <= 64) {
         BatchedMaker<64> m;
         ok = for_shapes(prec, d, m);
         v = m.v;
-    } else {
+    } else if (ksel <= 128) {
         BatchedMaker<128> m;
+        ok = for_shapes(prec, d, m);
+        v = m.v;
+    } else {
+        BatchedMaker<256> m;
         ok = for_shapes(prec, d, m);
         v = m.v;
     }

@@ -216,29 +216,60 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
     }
 }
 
-// Reverse-edge keys (p, x) ordered by p, then x, as 32-bit (p << 26 | x):
-// p < R <= 64 and x < MAX_ROWS < 2^26 - 1, so no key equals the all-ones
-// empty marker.  Half the bytes of a 64-bit (p << 32 | x) key for the
-// scatter, and half the sorting work for the combine pass.
+// Reverse-edge keys (p, x) ordered by p, then x.  For R <= 64 they are
+// 32-bit (p << 26 | x): p < 64 and x < MAX_ROWS < 2^26 - 1, so no key equals
+// the all-ones empty marker, and the scatter moves and the combine sorts half
+// the bytes of a 64-bit key.  Wider rows (R <= 128) use (p << 32 | x).
 constexpr int REV_XBITS = 26;
 static_assert(MAX_ROWS < (int64_t(1) << REV_XBITS) - 1, "row ids must fit the reverse key");
-constexpr uint32_t REV_EMPTY = ~0u;
-__device__ inline uint32_t rev_key(int p, int64_t x) { return ((uint32_t)p << REV_XBITS) | (uint32_t)x; }
-__device__ inline int32_t rev_source(uint32_t k) { return (int32_t)(k & ((1u << REV_XBITS) - 1)); }
+template <typename KT>
+struct RevKey;
+template <>
+struct RevKey<uint32_t> {
+    static constexpr uint32_t EMPTY = ~0u;
+    __device__ static uint32_t make(int p, int64_t x) { return ((uint32_t)p << REV_XBITS) | (uint32_t)x; }
+    __device__ static int32_t source(uint32_t k) { return (int32_t)(k & ((1u << REV_XBITS) - 1)); }
+    __device__ static uint32_t sort(uint32_t k) { return wave_sort_u32(k); }
+    __device__ static uint32_t xor_lane(uint32_t k, int j) { return lane_xor(k, j); }
+    __device__ static uint32_t from_lane(uint32_t k, int src) { return (uint32_t)__shfl((int)k, src, 64); }
+};
+template <>
+struct RevKey<uint64_t> {
+    static constexpr uint64_t EMPTY = ~0ull;
+    __device__ static uint64_t make(int p, int64_t x) { return ((uint64_t)(uint32_t)p << 32) | (uint64_t)x; }
+    __device__ static int32_t source(uint64_t k) { return (int32_t)(uint32_t)k; }
+    __device__ static uint64_t sort(uint64_t k) { return wave_sort_u64(k); }
+    __device__ static uint64_t xor_lane(uint64_t k, int j) { return lane_xor_u64(k, j); }
+    __device__ static uint64_t from_lane(uint64_t k, int src) { return shfl_u64(k, src); }
+};
+
+// Ascending order of a bitonic sequence of one key per lane (the merge
+// stages of a bitonic sort).
+template <typename KT>
+__device__ inline KT bitonic_finish(KT x) {
+    const int l = lane_id();
+#pragma unroll
+    for (int j = 32; j > 0; j >>= 1) {
+        const KT o = RevKey<KT>::xor_lane(x, j);
+        x = (o < x) == ((l & j) == 0) ? o : x;
+    }
+    return x;
+}
 
 // Edge e = x * R + p (P[e] = y) goes to rev[off[y] + rslot[e]]: rslot[e] is the
 // in-degree count of y that the edge read when the detour pass counted it, so
 // the slots of y's edges are 0 .. in-degree(y) - 1, each taken once.
+template <typename KT>
 __global__ void scatter_kernel(const int32_t* __restrict__ P, const int32_t* __restrict__ rslot,
                                int64_t total, int R, const int64_t* __restrict__ off,
-                               uint32_t* __restrict__ rev) {
+                               KT* __restrict__ rev) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         int32_t y = P[e];
         if (y == SG_NONE) continue;
         int64_t x = e / R;
         int p = (int)(e - x * R);
-        rev[off[y] + rslot[e]] = rev_key(p, x);
+        rev[off[y] + rslot[e]] = RevKey<KT>::make(p, x);
     }
 }
 
@@ -260,12 +291,18 @@ __device__ inline int span_of(int32_t v) {
     return m ? 64 - __builtin_clzll(m) : 0;
 }
 
+// NB: the reverse list is cut to its 64 * NB smallest keys (NB = 1 for
+// R <= 64, 2 for R <= 128), which always suffices: h = ceil(R/2) <= 32 * NB
+// entries of P(y) come first, so at most that many of the smallest keys are
+// repeats, and the rest fill the R - h places left before P(y)[h:R] is reached.
+template <typename KT, int NB>
 __global__ __launch_bounds__(256) void combine_kernel(const int32_t* __restrict__ P, int64_t n, int R,
                                                       const int64_t* __restrict__ off,
-                                                      const uint32_t* __restrict__ rev,
+                                                      const KT* __restrict__ rev,
                                                       const int32_t* __restrict__ order,
                                                       const int32_t* __restrict__ order_bad,
                                                       int32_t* __restrict__ F) {
+    using RK = RevKey<KT>;
     const int l = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int64_t slot = xcd_contiguous(blockIdx.x, gridDim.x) * WAVES + w;
@@ -273,46 +310,76 @@ __global__ __launch_bounds__(256) void combine_kernel(const int32_t* __restrict_
     const int64_t y = visit_row(order, order_bad, slot);
     const int h = (R + 1) / 2;
     const int64_t b = off[y], cnt = off[y + 1] - off[y];
-    // the 64 smallest reverse keys, ascending, one per lane
-    uint32_t best = l < cnt ? rev[b + l] : REV_EMPTY;
-    best = wave_sort_u32(best);
-    for (int64_t c0 = 64; c0 < cnt; c0 += 64) {
-        uint32_t v = c0 + l < cnt ? rev[b + c0 + l] : REV_EMPTY;
-        v = wave_sort_u32(v);
-        // bitonic merge of two ascending runs: reverse one, take elementwise min, sort
-        const uint32_t vr = (uint32_t)__shfl((int)v, 63 - l, 64);
-        best = wave_sort_u32(best < vr ? best : vr);
+    // the 64 * NB smallest reverse keys, ascending: element p * 64 + l in best[p]
+    KT best[NB];
+    best[0] = RK::sort(l < cnt ? rev[b + l] : RK::EMPTY);
+    if constexpr (NB == 2) {
+        // two sorted runs; the second reversed makes the pair one bitonic sequence
+        const KT v = RK::sort(64 + l < cnt ? rev[b + 64 + l] : RK::EMPTY);
+        best[1] = RK::from_lane(v, 63 - l);
+        const KT lo = best[0] < best[1] ? best[0] : best[1], hi = best[0] < best[1] ? best[1] : best[0];
+        best[0] = bitonic_finish(lo);
+        best[1] = bitonic_finish(hi);
+    }
+    for (int64_t c0 = 64 * NB; c0 < cnt; c0 += 64) {
+        const KT v = RK::sort(c0 + l < cnt ? rev[b + c0 + l] : RK::EMPTY);
+        // the element-wise minimum of the list's last run and the reversed new
+        // run leaves the 64 * NB smallest of both as a bitonic sequence
+        const KT vr = RK::from_lane(v, 63 - l);
+        best[NB - 1] = best[NB - 1] < vr ? best[NB - 1] : vr;
+        if constexpr (NB == 2) {
+            const KT lo = best[0] < best[1] ? best[0] : best[1], hi = best[0] < best[1] ? best[1] : best[0];
+            best[0] = bitonic_finish(lo);
+            best[1] = bitonic_finish(hi);
+        } else {
+            best[0] = bitonic_finish(best[0]);
+        }
     }
     // the sequence P(y)[0:h] ++ Rev(y) ++ P(y)[h:R], deduplicated in order
-    // and cut at R: segment A in lanes 0..h-1, B (the 64 smallest reverse
-    // keys' sources, by (p, x)) in lanes 0..63, C in lanes 0..R-h-1
+    // and cut at R: segment A in lanes 0..h-1, B (the smallest reverse keys'
+    // sources, by (p, x)) in lanes 0..63 of each best[], C in lanes 0..R-h-1
     const int32_t va = l < h ? P[y * R + l] : SG_NONE;
-    const int32_t vb = best != REV_EMPTY ? rev_source(best) : SG_NONE;
     const int32_t vc = l < R - h ? P[y * R + h + l] : SG_NONE;
-    const bool ka = va != SG_NONE;
-    const bool kb = first_occurrence(vb, va, span_of(va));
-    const bool kc = first_occurrence(vc, vb, span_of(vb));
+    const int spa = span_of(va);
+    int32_t vb[NB];
+    bool kb[NB];
+    bool kc = vc != SG_NONE;
+#pragma unroll
+    for (int p = 0; p < NB; ++p) {
+        vb[p] = best[p] != RK::EMPTY ? RK::source(best[p]) : SG_NONE;
+        kb[p] = first_occurrence(vb[p], va, spa);
+        kc = kc && first_occurrence(vc, vb[p], span_of(vb[p]));
+    }
     const uint64_t below = (1ull << l) - 1;
-    const uint64_t ma = __builtin_amdgcn_ballot_w64(ka), mb = __builtin_amdgcn_ballot_w64(kb),
-                   mc = __builtin_amdgcn_ballot_w64(kc);
-    const int ca = __builtin_popcountll(ma), cb = __builtin_popcountll(mb), cc = __builtin_popcountll(mc);
+    const bool ka = va != SG_NONE;
+    const uint64_t ma = __builtin_amdgcn_ballot_w64(ka), mc = __builtin_amdgcn_ballot_w64(kc);
     int32_t* row = F + y * R;
+    int pos0 = __builtin_popcountll(ma);
     if (ka) row[__builtin_popcountll(ma & below)] = va;              // ca <= h <= R
-    if (kb) {
-        const int pos = ca + __builtin_popcountll(mb & below);
-        if (pos < R) row[pos] = vb;
+#pragma unroll
+    for (int p = 0; p < NB; ++p) {
+        const uint64_t mb = __builtin_amdgcn_ballot_w64(kb[p]);
+        if (kb[p]) {
+            const int pos = pos0 + __builtin_popcountll(mb & below);
+            if (pos < R) row[pos] = vb[p];
+        }
+        pos0 += __builtin_popcountll(mb);
     }
     if (kc) {
-        const int pos = ca + cb + __builtin_popcountll(mc & below);
+        const int pos = pos0 + __builtin_popcountll(mc & below);
         if (pos < R) row[pos] = vc;
     }
-    const int total = ca + cb + cc;
-    if (l >= total && l < R) row[l] = SG_NONE;
+    const int total = pos0 + __builtin_popcountll(mc);
+    for (int r = l; r < R; r += 64)
+        if (r >= total) row[r] = SG_NONE;
 }
 
 struct Layout {
     size_t P, rslot, cnt, off, rev, scan, seen, total;
 };
+
+// Reverse keys are 4 bytes for R <= 64, 8 beyond.
+inline size_t rev_bytes(int R) { return R <= 64 ? 4 : 8; }
 
 inline Layout layout(int64_t n, int R) {
     Layout L;
@@ -320,11 +387,65 @@ inline Layout layout(int64_t n, int R) {
     L.rslot = align_up((size_t)n * R * 4, 256);
     L.cnt = align_up((size_t)(n + 1) * 8, 256);
     L.off = align_up((size_t)(n + 1) * 8, 256);
-    L.rev = align_up((size_t)n * R * 4, 256);
+    L.rev = align_up((size_t)n * R * rev_bytes(R), 256);
     L.scan = align_up(exclusive_scan_tmp_bytes(n), 256);
     L.seen = align_up((size_t)(n + 64) * 4, 256);   // order check: per-row counters + flag
     L.total = L.P + L.rslot + L.cnt + L.off + L.rev + L.scan + L.seen + 1024;
     return L;
+}
+
+inline void check_args(const int32_t* knn, int64_t n, int K, int R, int32_t* out) {
+    SG_REQUIRE(n >= 0 && n <= MAX_ROWS, "n out of range (at most 2^26 - 1024 rows)");
+    SG_REQUIRE(K >= 1 && K <= 256, "K must be in 1..256");
+    SG_REQUIRE(R >= 1 && R <= K && R <= 128, "R must be in 1..min(K, 128)");
+    SG_REQUIRE(n == 0 || (knn != nullptr && out != nullptr), "NULL pointer");
+}
+
+// The prune's launches on a workspace of layout(n, R).total bytes at ws
+// (arguments already checked, n > 0).  Every buffer the kernels read is
+// written or cleared here first, so the workspace may hold anything.
+inline void enqueue(const int32_t* knn, int64_t n, int K, int R, const int32_t* order, int32_t* out, void* ws,
+                    hipStream_t s) {
+    Carver cv(ws);
+    int32_t* P = cv.take<int32_t>((size_t)n * R);
+    int32_t* rslot = cv.take<int32_t>((size_t)n * R);
+    int64_t* cnt = cv.take<int64_t>(n + 1);
+    int64_t* off = cv.take<int64_t>(n + 1);
+    void* rev = cv.take<char>((size_t)n * R * rev_bytes(R));
+    void* scan_tmp = cv.take<char>(exclusive_scan_tmp_bytes(n));
+    int32_t* seen = cv.take<int32_t>(n + 64);
+    int32_t* order_bad = seen + n;
+
+    unsigned grid = (unsigned)cdiv(n, WAVES);
+    fill<int64_t>(cnt, 0, n + 1, s);
+    if (order) {   // a non-permutation falls back to row order (same result)
+        fill<int32_t>(seen, 0, n + 1, s);
+        order_check_kernel<<<(unsigned)std::min<int64_t>(cdiv(n, 256), 4096), 256, 0, s>>>(order, n, seen,
+                                                                                          order_bad);
+        SG_LAUNCH_CHECK();
+    }
+    if (K <= 64)
+        detour_kernel<1, 256><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt);
+    else if (K <= 128)
+        detour_kernel<2, 512><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt);
+    else
+        detour_kernel<4, 1024><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt);
+    SG_LAUNCH_CHECK();
+    int64_t total = n * (int64_t)R;
+    unsigned eg = (unsigned)std::min<int64_t>(cdiv(total, 256), 8192);
+    exclusive_scan_i64(cnt, off, n, scan_tmp, s);
+    if (R <= 64) {
+        scatter_kernel<uint32_t><<<eg, 256, 0, s>>>(P, rslot, total, R, off, static_cast<uint32_t*>(rev));
+        SG_LAUNCH_CHECK();
+        combine_kernel<uint32_t, 1><<<grid, 256, 0, s>>>(P, n, R, off, static_cast<const uint32_t*>(rev), order,
+                                                         order_bad, out);
+    } else {
+        scatter_kernel<uint64_t><<<eg, 256, 0, s>>>(P, rslot, total, R, off, static_cast<uint64_t*>(rev));
+        SG_LAUNCH_CHECK();
+        combine_kernel<uint64_t, 2><<<grid, 256, 0, s>>>(P, n, R, off, static_cast<const uint64_t*>(rev), order,
+                                                         order_bad, out);
+    }
+    SG_LAUNCH_CHECK();
 }
 
 }  // namespace prune
@@ -343,48 +464,13 @@ extern "C" sg_status sg_prune_workspace_size(int64_t n, int32_t K, int32_t R, si
 extern "C" sg_status sg_prune(const int32_t* knn, int64_t n, int32_t K, int32_t R, const int32_t* order,
                               int32_t* out, void* ws, size_t ws_bytes, void* stream) {
     return guarded([&] {
-        SG_REQUIRE(n >= 0 && n <= MAX_ROWS, "n out of range (at most 2^26 - 1024 rows)");
-        SG_REQUIRE(K >= 1 && K <= 256, "K must be in 1..256");
-        SG_REQUIRE(R >= 1 && R <= K && R <= 64, "R must be in 1..min(K, 64)");
+        prune::check_args(knn, n, K, R, out);
         if (n == 0) return;
-        SG_REQUIRE(knn != nullptr && out != nullptr, "NULL pointer");
-        prune::Layout L = prune::layout(n, R);
+        const prune::Layout L = prune::layout(n, R);
         if (ws == nullptr || ws_bytes < L.total) {
             set_error("sg_prune: workspace too small (need " + std::to_string(L.total) + " bytes)");
             throw Fail{SG_ERR_WORKSPACE};
         }
-        hipStream_t s = as_stream(stream);
-        Carver cv(ws);
-        int32_t* P = cv.take<int32_t>((size_t)n * R);
-        int32_t* rslot = cv.take<int32_t>((size_t)n * R);
-        int64_t* cnt = cv.take<int64_t>(n + 1);
-        int64_t* off = cv.take<int64_t>(n + 1);
-        uint32_t* rev = cv.take<uint32_t>((size_t)n * R);
-        void* scan_tmp = cv.take<char>(exclusive_scan_tmp_bytes(n));
-        int32_t* seen = cv.take<int32_t>(n + 64);
-        int32_t* order_bad = seen + n;
-
-        unsigned grid = (unsigned)cdiv(n, prune::WAVES);
-        fill<int64_t>(cnt, 0, n + 1, s);
-        if (order) {   // a non-permutation falls back to row order (same result)
-            fill<int32_t>(seen, 0, n + 1, s);
-            prune::order_check_kernel<<<(unsigned)std::min<int64_t>(cdiv(n, 256), 4096), 256, 0, s>>>(
-                order, n, seen, order_bad);
-            SG_LAUNCH_CHECK();
-        }
-        if (K <= 64)
-            prune::detour_kernel<1, 256><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt);
-        else if (K <= 128)
-            prune::detour_kernel<2, 512><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt);
-        else
-            prune::detour_kernel<4, 1024><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt);
-        SG_LAUNCH_CHECK();
-        int64_t total = n * (int64_t)R;
-        unsigned eg = (unsigned)std::min<int64_t>(cdiv(total, 256), 8192);
-        exclusive_scan_i64(cnt, off, n, scan_tmp, s);
-        prune::scatter_kernel<<<eg, 256, 0, s>>>(P, rslot, total, R, off, rev);
-        SG_LAUNCH_CHECK();
-        prune::combine_kernel<<<grid, 256, 0, s>>>(P, n, R, off, rev, order, order_bad, out);
-        SG_LAUNCH_CHECK();
+        prune::enqueue(knn, n, K, R, order, out, ws, as_stream(stream));
     });
 }

@@ -128,8 +128,32 @@ def test_batched_argument_errors():
     with pytest.raises(sg.SgError):
         sg.sg_knn_graph_batched(Xg, [5, 50, 100], 8, 4)           # offsets[0] != 0
     with pytest.raises(sg.SgError):
-        sg.sg_knn_graph_batched(Xg, [0, 50, 100], 200, 4)         # k > 128
+        sg.sg_knn_graph_batched(Xg, [0, 50, 100], 300, 4)         # k > 256
     with pytest.raises(sg.SgError):
-        sg.sg_knn_graph_batched(Xg, [0, 50, 100], 32, 4, rerank=256)   # re-rank wider than 128
+        sg.sg_knn_graph_batched(Xg, [0, 50, 100], 32, 4, rerank=300)   # re-rank wider than 256
+    with pytest.raises(sg.SgError):
+        sg.sg_knn_graph_batched(Xg, [0, 50, 100], 256, 129)       # R > 128
     with pytest.raises(sg.SgError):
         sg.sg_knn_graph_batched(Xg, list(range(0, 66)), 8, 4)     # S > 64
+
+
+@pytest.mark.parametrize("k,R", [(128, 64), (256, 128)])
+def test_batched_high_degree_equals_per_shard_and_oracle(k, R):
+    # the paper's default (degree 64 from 128 candidates) and stress (128 from
+    # 256) settings: lists and pruned graphs as the single-shard path, kNN
+    # lists as the oracle on integer rows
+    sizes = [1800, 600, 2600]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    X = synthdata.sift_like_u8(n=int(offs[-1]), d=128, seed=41, n_comp=12)
+    Xg = torch.from_numpy(X).to(DEV)
+    graphs, knn = sg.sg_knn_graph_batched(Xg, offs, k, R, "l2", "f16")
+    torch.cuda.synchronize()
+    g_ref, k_ref = _per_shard(Xg, offs, k, R, "l2", "f16")
+    assert torch.equal(knn, k_ref)
+    assert torch.equal(graphs, g_ref)
+    knn_h, g_h = knn.cpu().numpy(), graphs.cpu().numpy()
+    for s in range(len(sizes)):
+        a, b = offs[s], offs[s + 1]
+        onbr, _ = oracle.knn(oracle.widen(X[a:b]), k)
+        np.testing.assert_array_equal(knn_h[a:b], onbr, err_msg="shard %d" % s)
+        np.testing.assert_array_equal(g_h[a:b], oracle.prune(onbr, R), err_msg="shard %d" % s)

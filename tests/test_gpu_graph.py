@@ -44,7 +44,8 @@ def test_reverse_combine_worked_example_through_prune():
 
 
 @pytest.mark.parametrize("n,K,R", [(300, 32, 16), (1000, 64, 32), (257, 64, 64), (500, 20, 7),
-                                   (130, 128, 64), (600, 256, 33)])
+                                   (130, 128, 64), (600, 256, 33), (700, 128, 65), (900, 256, 128),
+                                   (300, 96, 96), (1100, 256, 99)])
 def test_prune_on_random_graphs(n, K, R):
     knn = synthdata.local_graph(n, K, seed=n + K + R) if n > 2 * K + 2 else synthdata.random_graph(n, K, seed=n)
     np.testing.assert_array_equal(_prune_gpu(knn, R), oracle.prune(knn, R))
@@ -55,26 +56,31 @@ def test_prune_with_padding():
     np.testing.assert_array_equal(_prune_gpu(knn, 12), oracle.prune(knn, 12))
 
 
-@pytest.mark.parametrize("n,d,K,R", [(2000, 128, 64, 32), (3000, 96, 32, 16), (40, 8, 64, 32)])
+@pytest.mark.parametrize("n,d,K,R", [(2000, 128, 64, 32), (3000, 96, 32, 16), (40, 8, 64, 32),
+                                     (2500, 128, 128, 64), (2500, 128, 256, 128), (200, 16, 256, 128)])
 def test_prune_on_exact_knn(n, d, K, R):
     X = synthdata.sift_like_u8(n=n, d=d, seed=n, n_comp=max(2, n // 100))
     knn, _ = oracle.knn(oracle.widen(X), K)
     np.testing.assert_array_equal(_prune_gpu(knn, R), oracle.prune(knn, R))
 
 
-def test_prune_hub_in_degree():
-    # many rows point at a few hubs: in-degree >> 64 exercises the chunked selection
+@pytest.mark.parametrize("K,R", [(16, 8), (160, 100)])
+def test_prune_hub_in_degree(K, R):
+    # many rows point at a few hubs: in-degree >> 64 (>> 128 for R > 64)
+    # exercises the chunked selection of the smallest reverse keys
     rng = np.random.default_rng(0)
-    n, K = 3000, 16
+    n = 3000
     knn = np.empty((n, K), np.int32)
     for i in range(n):
         hubs = [h for h in range(8) if h != i][:4]
-        rest = rng.choice([j for j in range(n) if j != i and j not in hubs][:200], K - 4, replace=False)
+        rest = rng.choice([j for j in range(n) if j != i and j not in hubs][:max(200, 2 * K)], K - 4,
+                          replace=False)
         knn[i] = np.concatenate([hubs, rest])
-    np.testing.assert_array_equal(_prune_gpu(knn, 8), oracle.prune(knn, 8))
+    np.testing.assert_array_equal(_prune_gpu(knn, R), oracle.prune(knn, R))
 
 
-@pytest.mark.parametrize("n,half,R", [(500, 8, 8), (500, 8, 16), (130, 32, 21), (70, 32, 64)])
+@pytest.mark.parametrize("n,half,R", [(500, 8, 8), (500, 8, 16), (130, 32, 21), (70, 32, 64),
+                                      (400, 64, 128), (300, 64, 77), (260, 128, 128)])
 def test_prune_symmetric_graph(n, half, R):
     # circulant graph, offsets +-1..+-half by |offset|: every edge is mutual, so
     # Rev(y) repeats most of P(y) and the in-order deduplication decides F(y)
