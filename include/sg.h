@@ -66,11 +66,16 @@ typedef enum { SG_F32 = 0, SG_F16 = 1, SG_BF16 = 2, SG_U8 = 3 } sg_dtype;
  *  SG_PREC_FP8  : rows scaled per row by a power of two and rounded to OCP FP8
  *                 E4M3 (nearest even, saturating), FP8 MFMA, FP32
  *                 accumulation; followed by an FP32 re-rank when rerank > k.
+ *  SG_PREC_I8   : U8 input only, d <= 256: rows shifted by -128 to INT8, INT8
+ *                 MFMA with exact INT32 sums; the keys (L2: ||c'||^2 -
+ *                 2 q'.c', IP: -q'.c' - 128 sum(c'), with x' = x - 128) are
+ *                 integers below 2^24, so the result equals the FP32 build and
+ *                 the exact kNN bit for bit, at twice the FP16 MFMA rate.
  *  With BF16 / FP8 and the IP metric the candidate key is the L2 key of the
  *  rounded rows with the candidate's exact squared norm put back,
  *  ||c~||^2 - ||c||^2 - 2 q~.c~: the same ranking as -q.c up to rounding, with
  *  a rounding error that scales with ||q - c||. */
-typedef enum { SG_PREC_FP32 = 0, SG_PREC_F16 = 1, SG_PREC_BF16 = 2, SG_PREC_FP8 = 3 } sg_prec;
+typedef enum { SG_PREC_FP32 = 0, SG_PREC_F16 = 1, SG_PREC_BF16 = 2, SG_PREC_FP8 = 3, SG_PREC_I8 = 4 } sg_prec;
 
 const char* sg_status_str(sg_status s);   /* static text for a status code            */
 const char* sg_last_error(void);          /* detail of this thread's last failing call */
@@ -446,6 +451,49 @@ sg_status sg_mlp_project_workspace_size(int32_t D, int32_t H, int32_t E, size_t*
  * ---------------------------------------------------------------------- */
 sg_status sg_profile_begin(void);
 sg_status sg_profile_end(double* kernel_ms, int64_t* launches);
+
+/* ------------------------------------------------------------------------
+ * Scheduling shard builds on cloud GPU instances, and their cost
+ * (Sec. IV, "Cloud Instance Task Scheduler" and "Spot instance cost
+ * analysis").  Host-only calls: pointers ending in _h are host memory, no
+ * device is touched.
+ *
+ * sg_cost_model: cost = (overall_time + transfer_time) * cpu_price
+ *                      + (gpu_active_time + transfer_time) * gpu_price.
+ *
+ * sg_sched_fit_linear: least-squares line time = a + b * size through m >= 1
+ * sampled builds (the paper estimates a shard's build time from small sampled
+ * builds, build time being linear in shard size).
+ *
+ * sg_sched_simulate: T shard-build tasks (est_h: the scheduler's estimate,
+ * actual_h > 0: the real time) on G instances.  Instance g is active in
+ * [ready, end) (end = +inf: never terminated); its end becomes known to the
+ * scheduler at `notice` (<= ready: known from the start, e.g. a guaranteed
+ * duration; +inf: never told).  Availability-based policy: a task goes only
+ * to an idle active instance.  Time-based policy (time_based = 1): an
+ * instance whose end is known takes only tasks with transfer + est <= its
+ * remaining lifetime.  A task occupies its instance for transfer + actual;
+ * one whose instance terminates first returns to the head of the task list
+ * and runs again.  At one time, terminations, then completions, then one
+ * assignment pass over idle instances in index order, each taking the first
+ * task in the list that fits (none: it stays idle).
+ *  Outputs (nullable except summary_h): task_instance_h[T] (the instance that
+ *  completed the task, -1 if it never did), task_start_h / task_end_h[T] (of
+ *  the completing run, NaN if none), attempts_h[T] (runs started);
+ *  summary_h[4] = { makespan, GPU active time (every occupation, lost work
+ *  included), preemptions, tasks completed }.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double ready;    /* activation time, >= 0                                  */
+    double end;      /* termination time (> ready; +inf: never)                */
+    double notice;   /* time from which `end` is known (+inf: never)           */
+} sg_instance;
+sg_status sg_cost_model(double overall_time, double gpu_active_time, double transfer_time, double cpu_price,
+                        double gpu_price, double* cost);
+sg_status sg_sched_fit_linear(const double* sizes_h, const double* times_h, int32_t m, double* a, double* b);
+sg_status sg_sched_simulate(const double* est_h, const double* actual_h, int32_t T, const sg_instance* inst_h,
+                            int32_t G, int32_t time_based, double transfer, int32_t* task_instance_h,
+                            double* task_start_h, double* task_end_h, int32_t* attempts_h, double* summary_h);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libsg.so")
 
 SG_NONE = -1
 METRICS = {"l2": 0, "ip": 1}
-PRECS = {"fp32": 0, "f16": 1, "bf16": 2, "fp8": 3}
+PRECS = {"fp32": 0, "f16": 1, "bf16": 2, "fp8": 3, "i8": 4}
 _DTYPES = {torch.float32: 0, torch.float16: 1, torch.bfloat16: 2, torch.uint8: 3}
 
 _lib = None
@@ -89,6 +89,10 @@ _SIGS = {
     "sg_mlp_train": (i32, [vp, i64, i32, i64, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp,
                            f32, f32, f32, f32, f32, vp, i32, vp, sz, vp]),
     "sg_mlp_project": (i32, [vp, i64, i32, i64, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+    "sg_cost_model": (i32, [C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                            C.POINTER(C.c_double)]),
+    "sg_sched_fit_linear": (i32, [vp, vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "sg_sched_simulate": (i32, [vp, vp, i32, vp, i32, i32, C.c_double, vp, vp, vp, vp, vp]),
     "sg_profile_begin": (i32, []),
     "sg_profile_end": (i32, [C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "sg_search": (i32, [vp, i32, i64, i32, i64, i32, vp, i32, vp, i64, i64, i32, i32, i64, vp, vp,
@@ -189,14 +193,14 @@ def sg_knn_graph(X, k, metric="l2", prec="fp32", rerank=0, dist=True, stream=Non
     return nbr, dd
 
 
-_OPERAND_DTYPES = {0: torch.float32, 1: torch.float16, 2: torch.int16, 3: torch.uint8}
+_OPERAND_DTYPES = {0: torch.float32, 1: torch.float16, 2: torch.int16, 3: torch.uint8, 4: torch.int8}
 
 
 def sg_quantize_rows(X, prec="fp32", ldo=None, stream=None):
     """Operand rows of `prec` as the distance kernel prepares them:
-    (rows [n, ldo] -- float32, float16, BF16 bits as int16 or FP8 E4M3 codes as
-    uint8 --, scale exponents int32 [n] for FP8 else None, squared norms
-    float32 [n])."""
+    (rows [n, ldo] -- float32, float16, BF16 bits as int16, FP8 E4M3 codes as
+    uint8 or U8 values - 128 as int8 --, scale exponents int32 [n] for FP8 else
+    None, squared norms of the operand rows float32 [n])."""
     L = lib()
     dt, n, d, ld = _rows(X)
     p = PRECS[prec]
@@ -511,3 +515,49 @@ def sg_mlp_project(X, net, stream=None):
         _ptr(X), n, D, X.stride(0), net.H, net.E, _ptr(net.W1), _ptr(net.b1), _ptr(net.W2), _ptr(net.b2),
         _ptr(net.mu), _ptr(net.sigma), _ptr(F), _ptr(ws), ws.numel(), _stream(stream)))
     return F
+
+
+# ---------------------------------------------------------------------------
+# scheduling shard builds on cloud GPU instances (host-only calls)
+# ---------------------------------------------------------------------------
+class SgInstance(C.Structure):
+    _fields_ = [("ready", C.c_double), ("end", C.c_double), ("notice", C.c_double)]
+
+
+def sg_cost_model(overall_time, gpu_active_time, transfer_time, cpu_price, gpu_price):
+    """Cost of a build: (overall + transfer) x CPU price + (GPU active + transfer) x GPU price."""
+    out = C.c_double(0.0)
+    _check("sg_cost_model", lib().sg_cost_model(overall_time, gpu_active_time, transfer_time, cpu_price,
+                                                gpu_price, C.byref(out)))
+    return out.value
+
+
+def sg_sched_fit_linear(sizes, times):
+    """(a, b) of the least-squares line time = a + b * size."""
+    x = np.ascontiguousarray(sizes, np.float64)
+    y = np.ascontiguousarray(times, np.float64)
+    a, b = C.c_double(0.0), C.c_double(0.0)
+    _check("sg_sched_fit_linear", lib().sg_sched_fit_linear(x.ctypes.data, y.ctypes.data, len(x), C.byref(a),
+                                                            C.byref(b)))
+    return a.value, b.value
+
+
+def sg_sched_simulate(est, actual, instances, time_based=True, transfer=0.0):
+    """Simulate the task scheduler.  instances: sequence of (ready, end,
+    notice).  Returns a dict: task_instance, task_start, task_end, attempts
+    (numpy arrays), makespan, gpu_active, preemptions, completed."""
+    est = np.ascontiguousarray(est, np.float64)
+    actual = np.ascontiguousarray(actual, np.float64)
+    T, G = len(est), len(instances)
+    arr = (SgInstance * max(G, 1))(*[SgInstance(*map(float, t)) for t in instances])
+    ti = np.empty(T, np.int32)
+    t0 = np.empty(T, np.float64)
+    t1 = np.empty(T, np.float64)
+    att = np.empty(T, np.int32)
+    summ = np.empty(4, np.float64)
+    _check("sg_sched_simulate", lib().sg_sched_simulate(est.ctypes.data, actual.ctypes.data, T, C.cast(arr, C.c_void_p),
+                                                        G, int(bool(time_based)), float(transfer), ti.ctypes.data,
+                                                        t0.ctypes.data, t1.ctypes.data, att.ctypes.data,
+                                                        summ.ctypes.data))
+    return dict(task_instance=ti, task_start=t0, task_end=t1, attempts=att, makespan=float(summ[0]),
+                gpu_active=float(summ[1]), preemptions=int(summ[2]), completed=int(summ[3]))

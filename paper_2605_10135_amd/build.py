@@ -24,7 +24,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
 
 # Slices of the distance-kernel shape table (shapes.hip is compiled once per
 # slice): precision x selection width, single-shard and batched.
-PRECS = ("SG_PREC_FP32", "SG_PREC_F16", "SG_PREC_BF16", "SG_PREC_FP8")
+PRECS = ("SG_PREC_FP32", "SG_PREC_F16", "SG_PREC_BF16", "SG_PREC_FP8", "SG_PREC_I8")
 SLICES = [(p, k, 0) for p in PRECS for k in (32, 64, 128, 256)] + \
          [(p, k, 1) for p in PRECS for k in (64, 128, 256)]
 

@@ -99,7 +99,7 @@ Plan make_plan(const int64_t* off, int S, int d, int k, int R, int prec, int rer
     SG_REQUIRE(k >= 1 && k <= 256, "k must be in 1..256");
     SG_REQUIRE(rerank == 0 || (rerank >= k && rerank <= 256), "rerank must be 0 or in k..256");
     SG_REQUIRE(R >= 1 && R <= k && R <= 128, "R must be in 1..min(k, 128)");
-    SG_REQUIRE(prec >= SG_PREC_FP32 && prec <= SG_PREC_FP8, "unknown precision");
+    SG_REQUIRE(prec >= SG_PREC_FP32 && prec <= SG_PREC_I8, "unknown precision");
     Plan p;
     p.S = S;
     p.sh.S = S;

@@ -246,7 +246,7 @@ extern "C" sg_status sg_knn_variant_count(sg_prec prec, int32_t d, int32_t k, in
     return guarded([&] {
         SG_REQUIRE(count != nullptr, "count is NULL");
         SG_REQUIRE(d >= 1 && d <= 1024 && k >= 1 && k <= 256, "bad sizes");
-        SG_REQUIRE(prec >= SG_PREC_FP32 && prec <= SG_PREC_FP8, "unknown precision");
+        SG_REQUIRE(prec >= SG_PREC_FP32 && prec <= SG_PREC_I8, "unknown precision");
         *count = (int32_t)knn::kernel_variants(prec, d, knn::ksel_for(k)).size();
     });
 }

@@ -8,6 +8,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -21,6 +22,7 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int intx8 __attribute__((ext_vector_type(8)));
 typedef int intx4 __attribute__((ext_vector_type(4)));
+typedef int intx16 __attribute__((ext_vector_type(16)));
 
 constexpr int TWAVES = 8;        // waves per workgroup of the distance kernel
 constexpr int TQB = 1;           // 32-query blocks per wave
@@ -36,15 +38,16 @@ template <> struct Tr<SG_PREC_FP32> { static constexpr int EB = 4, VEC = 1; };
 template <> struct Tr<SG_PREC_F16> { static constexpr int EB = 2, VEC = 8; };
 template <> struct Tr<SG_PREC_BF16> { static constexpr int EB = 2, VEC = 8; };
 template <> struct Tr<SG_PREC_FP8> { static constexpr int EB = 1, VEC = 32; };
+template <> struct Tr<SG_PREC_I8> { static constexpr int EB = 1, VEC = 16; };
 
 // padded row length (elements) for a given d: two lane-halves, each a whole
 // number of MFMA steps
 __host__ __device__ inline int padded_d(int prec, int d) {
-    int g = 2 * (prec == SG_PREC_FP32 ? 2 : prec == SG_PREC_FP8 ? 32 : 8);
+    int g = 2 * (prec == SG_PREC_FP32 ? 2 : prec == SG_PREC_FP8 ? 32 : prec == SG_PREC_I8 ? 16 : 8);
     return (d + g - 1) / g * g;
 }
 __host__ __device__ inline int elem_bytes(int prec) {
-    return prec == SG_PREC_FP32 ? 4 : prec == SG_PREC_FP8 ? 1 : 2;
+    return prec == SG_PREC_FP32 ? 4 : (prec == SG_PREC_FP8 || prec == SG_PREC_I8) ? 1 : 2;
 }
 
 // ---------------------------------------------------------------------------
@@ -111,6 +114,10 @@ __device__ inline float fp8_value(uint8_t c) {
 //   L2             key = ||c~||^2 - 2 q~.c~            dist = key + ||q~||^2
 //   IP, FP32/F16   key = -q.c                           dist = key
 //   IP, BF16/FP8   key = ||c~||^2 - ||c||^2 - 2 q~.c~   dist = (key + ||q~||^2 - ||q||^2) / 2
+//   L2, I8         key = ||c'||^2 - 2 q'.c'            dist = key + ||q'||^2
+//   IP, I8         key = -128 S(c') - q'.c'             dist = key - 128 S(q') - 16384 d
+// (x' = x - 128 for U8 rows, S = the sum of the elements; every term is an
+// integer below 2^24, so the FP32 key is exact)
 // (x~ = the rounded operand row).  The reduced-precision IP key is the L2 key
 // of the rounded rows with the exact norm put back: its rounding error scales
 // with ||q - c|| instead of ||q|| ||c||, which keeps near neighbours apart.
@@ -166,6 +173,13 @@ static __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_
         float v = t < d ? load_elem(X, dtype, base + t) : 0.f;
         float q;
         switch (prec) {
+            case SG_PREC_I8: {   // U8 rows shifted by -128 (padding elements 0)
+                const int c = t < d ? (int)v - 128 : 0;
+                out[t] = (uint8_t)(int8_t)c;
+                q = (float)c;
+                ssx += q;        // the element sum S (exact: |S| < 2^24)
+                break;
+            }
             case SG_PREC_FP32:
                 reinterpret_cast<float*>(out)[t] = v;
                 q = v;
@@ -190,16 +204,21 @@ static __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_
             }
         }
         ssq += q * q;
-        ssx += v * v;
+        if (prec != SG_PREC_I8) ssx += v * v;
     }
     for (int o = 32; o > 0; o >>= 1) {
         ssq += __shfl_xor(ssq, o, 64);
         ssx += __shfl_xor(ssx, o, 64);
     }
     if (l == 0) {
-        const float term = metric == SG_L2 ? ssq : norm_corrected_ip(metric, prec) ? ssq - ssx : 0.f;
+        float term = metric == SG_L2 ? ssq : norm_corrected_ip(metric, prec) ? ssq - ssx : 0.f;
+        float oterm = term;
+        if (prec == SG_PREC_I8 && metric == SG_IP) {
+            term = -128.f * ssx;
+            oterm = term - 16384.f * (float)d;
+        }
         if (ninit) ninit[row] = term;
-        if (nout) nout[row] = term;
+        if (nout) nout[row] = oterm;
         if (sexp) sexp[row] = sx;
     }
 }
@@ -230,6 +249,15 @@ template <int NSTEP>
 struct Frag<SG_PREC_FP8, NSTEP> {
     intx8 v[NSTEP];
 };
+template <int NSTEP>
+struct Frag<SG_PREC_I8, NSTEP> {
+    intx4 v[NSTEP];   // 16 signed bytes per MFMA step
+};
+
+// Accumulator of one 32x32 subtile: FP32, or exact INT32 for I8 operands
+// (converted to the FP32 key when the subtile is selected).
+template <int P>
+using AccT = typename std::conditional<P == SG_PREC_I8, intx16, floatx16>::type;
 
 // Load lane l's half-row (elements [h*DH, (h+1)*DH)) from a byte row.
 template <int P, int NSTEP>
@@ -248,6 +276,9 @@ __device__ inline void load_frag(Frag<P, NSTEP>& f, const uint8_t* rowp) {
             intx4 b = *reinterpret_cast<const intx4*>(rowp + s * 32 + 16);
             f.v[s] = intx8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
         }
+    } else if constexpr (P == SG_PREC_I8) {
+#pragma unroll
+        for (int s = 0; s < NSTEP; ++s) f.v[s] = *reinterpret_cast<const intx4*>(rowp + s * 16);
     } else {
 #pragma unroll
         for (int s = 0; s < NSTEP; ++s) {
@@ -265,7 +296,10 @@ __device__ inline void load_frag(Frag<P, NSTEP>& f, const uint8_t* rowp) {
 // the x2 in the scale exponent.
 template <int P, int NSTEP>
 __device__ inline void scale_query(Frag<P, NSTEP>& f, float qmul) {
-    if constexpr (P == SG_PREC_FP8) {
+    if constexpr (P == SG_PREC_I8) {
+        (void)f;   // INT8 keys take the factor when they are converted (subtile_keys)
+        (void)qmul;
+    } else if constexpr (P == SG_PREC_FP8) {
 #pragma unroll
         for (int s = 0; s < NSTEP; ++s)
 #pragma unroll
@@ -354,6 +388,34 @@ __device__ inline floatx16 mfma_tile(const uint8_t* arow, const Frag<P, NSTEP>& 
         }
     }
     return acc;
+}
+
+// acc = A(32 candidate rows at arow, LDS) x Q(32 queries) over the padded
+// row with INT8 operands: exact INT32 sums from zero (the accumulator start
+// and the query factor are applied when the keys are formed, i8_keys).
+template <int NSTEP, int GMAX = 8>
+__device__ inline intx16 mfma_tile_i8(const uint8_t* arow, const Frag<SG_PREC_I8, NSTEP>& q) {
+    intx16 acc = {};
+    constexpr int G = group_of(NSTEP, GMAX);
+#pragma unroll
+    for (int g = 0; g < NSTEP; g += G) {
+        intx4 a[G];
+#pragma unroll
+        for (int s = 0; s < G; ++s) a[s] = *reinterpret_cast<const intx4*>(arow + (g + s) * 16);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s = 0; s < G; ++s) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[s], q.v[g + s], acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// FP32 ranking keys of an INT8 subtile: start + qmul * acc, exact (every
+// value is an integer below 2^24); a NaN start (padding row) stays NaN.
+__device__ inline floatx16 i8_keys(const intx16& acc, const floatx4 (&nv)[4], float qmul) {
+    floatx16 k;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) k[i] = __builtin_fmaf(qmul, (float)acc[i], nv[i >> 2][i & 3]);
+    return k;
 }
 
 template <int P, int NSTEP, int BCR = 0>
@@ -748,36 +810,59 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
             if constexpr (P == SG_PREC_FP8) sm.sexp[buf][tid] = pre_sexp[r];
         }
     };
-    auto compute = [&](floatx16 (&acc)[QB], int buf, int sub) {
-        floatx4 nv[4];
+    using Acc = AccT<P>;
+    // the accumulator starts of the lane's 16 candidate rows of a subtile
+    auto starts = [&](floatx4 (&nv)[4], int buf, int sub) {
 #pragma unroll
         for (int g = 0; g < 4; ++g)
             nv[g] = *reinterpret_cast<const floatx4*>(&sm.norm[buf][sub * 32 + g * 8 + h * 4]);
-        int a_scale = 127;
-        if constexpr (P == SG_PREC_FP8) a_scale = 127 + sm.sexp[buf][sub * 32 + ql];
+    };
+    auto compute = [&](Acc (&acc)[QB], int buf, int sub) {
         const uint8_t* arow = &sm.tile[buf][(sub * 32 + ql) * RS + h * (RB / 2)];
+        if constexpr (P == SG_PREC_I8) {
+            for (int b = 0; b < QB; ++b) acc[b] = mfma_tile_i8<NSTEP, GMAX>(arow, qf[b]);
+        } else {
+            floatx4 nv[4];
+            starts(nv, buf, sub);
+            int a_scale = 127;
+            if constexpr (P == SG_PREC_FP8) a_scale = 127 + sm.sexp[buf][sub * 32 + ql];
 #pragma unroll
-        for (int b = 0; b < QB; ++b) {
+            for (int b = 0; b < QB; ++b) {
 #pragma unroll
-            for (int i = 0; i < 16; ++i) acc[b][i] = nv[i >> 2][i & 3];
+                for (int i = 0; i < 16; ++i) acc[b][i] = nv[i >> 2][i & 3];
+            }
+            for (int b = 0; b < QB; ++b)
+                acc[b] = mfma_tile<P, NSTEP, GMAX>(arow, qf[b], acc[b], a_scale, q_scale[b]);
         }
-        for (int b = 0; b < QB; ++b)
-            acc[b] = mfma_tile<P, NSTEP, GMAX>(arow, qf[b], acc[b], a_scale, q_scale[b]);
     };
 
+    // selection of a computed subtile (INT8 sums become FP32 keys here, after
+    // the next subtile's MFMAs have been issued)
+    auto select = [&](Acc (&acc)[QB], int buf, int sub, int64_t cb, const int32_t* tp) {
+        if constexpr (P == SG_PREC_I8) {
+            floatx4 nv[4];
+            starts(nv, buf, sub);
+            floatx16 kf[QB];
+#pragma unroll
+            for (int b = 0; b < QB; ++b) kf[b] = i8_keys(acc[b], nv, A.qmul);
+            sel.admit(kf, cb, tp);
+        } else {
+            sel.admit(acc, cb, tp);
+        }
+    };
     auto body = [&](int t, int buf) {
         const int j0 = tile_row(t);
         const int32_t* tp = A.cpid ? sm.pid[buf] : nullptr;
-        floatx16 accA[QB], accB[QB];
+        Acc accA[QB], accB[QB];
         compute(accA, buf, 0);
 #pragma unroll
         for (int sub = 0; sub < NSUB; ++sub) {
             if (sub % 2 == 0) {
                 if (sub + 1 < NSUB) compute(accB, buf, sub + 1);
-                sel.admit(accA, j0 + sub * 32, tp ? tp + sub * 32 : nullptr);
+                select(accA, buf, sub, j0 + sub * 32, tp ? tp + sub * 32 : nullptr);
             } else {
                 if (sub + 1 < NSUB) compute(accA, buf, sub + 1);
-                sel.admit(accB, j0 + sub * 32, tp ? tp + sub * 32 : nullptr);
+                select(accB, buf, sub, j0 + sub * 32, tp ? tp + sub * 32 : nullptr);
             }
         }
     };
@@ -1008,10 +1093,16 @@ __device__ void nearest_block(int64_t blk, const uint8_t* __restrict__ ops, cons
         }
         __syncthreads();
         floatx16 acc;
+        if constexpr (P == SG_PREC_I8) {
+            const intx16 ai = mfma_tile_i8<NSTEP>(&tile[ql * RS + h * (RB / 2)], qf);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) acc[i] = norm[out_row(i, l)];
-        const int a_scale = P == SG_PREC_FP8 ? 127 + tsexp[ql] : 127;
-        acc = mfma_tile<P, NSTEP>(&tile[ql * RS + h * (RB / 2)], qf, acc, a_scale, q_scale);
+            for (int i = 0; i < 16; ++i) acc[i] = __builtin_fmaf(qmul, (float)ai[i], norm[out_row(i, l)]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[i] = norm[out_row(i, l)];
+            const int a_scale = P == SG_PREC_FP8 ? 127 + tsexp[ql] : 127;
+            acc = mfma_tile<P, NSTEP>(&tile[ql * RS + h * (RB / 2)], qf, acc, a_scale, q_scale);
+        }
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int32_t r = j0 + out_row(i, l);
@@ -1284,7 +1375,7 @@ inline int ksel_for(int k) { return k <= 32 ? 32 : k <= 64 ? 64 : k <= 128 ? 128
 // Largest resident query half-row supported: the query fragment of 32 rows
 // lives in 64 VGPRs per lane at most.
 inline int nstep_for(int prec, int DP) {
-    int vec = prec == SG_PREC_FP32 ? 1 : prec == SG_PREC_FP8 ? 32 : 8;
+    int vec = prec == SG_PREC_FP32 ? 1 : prec == SG_PREC_FP8 ? 32 : prec == SG_PREC_I8 ? 16 : 8;
     return DP / 2 / vec;
 }
 
@@ -1361,6 +1452,7 @@ bool for_shapes(int prec, int d, M& m) {
         case SG_PREC_FP32: return for_shapes_p<SG_PREC_FP32>(d, m);
         case SG_PREC_F16: return for_shapes_p<SG_PREC_F16>(d, m);
         case SG_PREC_BF16: return for_shapes_p<SG_PREC_BF16>(d, m);
+        case SG_PREC_I8: return for_shapes_p<SG_PREC_I8>(d, m);
         default: return for_shapes_p<SG_PREC_FP8>(d, m);
     }
 }
@@ -1380,7 +1472,8 @@ struct ResidentMaker {
     SG_EXTERN_SLICE(SG_PREC_FP32, MAKER_T<K>)         \
     SG_EXTERN_SLICE(SG_PREC_F16, MAKER_T<K>)          \
     SG_EXTERN_SLICE(SG_PREC_BF16, MAKER_T<K>)         \
-    SG_EXTERN_SLICE(SG_PREC_FP8, MAKER_T<K>)
+    SG_EXTERN_SLICE(SG_PREC_FP8, MAKER_T<K>)          \
+    SG_EXTERN_SLICE(SG_PREC_I8, MAKER_T<K>)
 SG_EXTERN_SLICES(ResidentMaker, 32)
 SG_EXTERN_SLICES(ResidentMaker, 64)
 SG_EXTERN_SLICES(ResidentMaker, 128)
@@ -1466,8 +1559,10 @@ inline void check_args(const void* X, int dtype, int64_t n, int d, int64_t ld, i
     SG_REQUIRE(k >= 1 && k <= 256, "k must be in 1..256");
     SG_REQUIRE(metric == SG_L2 || metric == SG_IP, "unknown metric");
     SG_REQUIRE(dtype >= SG_F32 && dtype <= SG_U8, "unknown dtype");
-    SG_REQUIRE(prec >= SG_PREC_FP32 && prec <= SG_PREC_FP8, "unknown precision");
+    SG_REQUIRE(prec >= SG_PREC_FP32 && prec <= SG_PREC_I8, "unknown precision");
     SG_REQUIRE(rerank == 0 || (rerank >= k && rerank <= 256), "rerank must be 0 or in k..256");
+    SG_REQUIRE(!(prec == SG_PREC_I8 && dtype != SG_U8), "SG_PREC_I8 needs U8 input");
+    SG_REQUIRE(!(prec == SG_PREC_I8 && d > 256), "SG_PREC_I8 is exact on U8 input only for d <= 256");
     SG_REQUIRE(!(prec == SG_PREC_F16 && dtype != SG_F16 && dtype != SG_U8),
                "SG_PREC_F16 needs F16 or U8 input");
     SG_REQUIRE(!(prec == SG_PREC_F16 && dtype == SG_U8 && d > 128),

@@ -340,6 +340,8 @@ __global__ __launch_bounds__(256) void combine_kernel(const int32_t* __restrict_
     // sources, by (p, x)) in lanes 0..63 of each best[], C in lanes 0..R-h-1
     const int32_t va = l < h ? P[y * R + l] : SG_NONE;
     const int32_t vc = l < R - h ? P[y * R + h + l] : SG_NONE;
+    // (every ballot and lane read below runs with all lanes active: a span
+    // taken under a lane condition would miss the other lanes' values)
     const int spa = span_of(va);
     int32_t vb[NB];
     bool kb[NB];
@@ -347,8 +349,10 @@ __global__ __launch_bounds__(256) void combine_kernel(const int32_t* __restrict_
 #pragma unroll
     for (int p = 0; p < NB; ++p) {
         vb[p] = best[p] != RK::EMPTY ? RK::source(best[p]) : SG_NONE;
+        const int spb = span_of(vb[p]);
         kb[p] = first_occurrence(vb[p], va, spa);
-        kc = kc && first_occurrence(vc, vb[p], span_of(vb[p]));
+        const bool c_new = first_occurrence(vc, vb[p], spb);
+        kc = kc & c_new;
     }
     const uint64_t below = (1ull << l) - 1;
     const bool ka = va != SG_NONE;

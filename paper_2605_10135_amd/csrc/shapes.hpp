@@ -42,6 +42,12 @@ bool for_shapes_p(int d, M& m) {
         else if (need <= 32) SG_ONE(PR, 32, 4);
         else if (need <= 48) SG_ONE(PR, 48, 4);
         else return false;
+    } else if constexpr (PR == SG_PREC_I8) {
+        if (need <= 1) SG_FOUR(SG_PREC_I8, 1, TWAVES);
+        else if (need <= 2) SG_FOUR(SG_PREC_I8, 2, TWAVES);
+        else if (need <= 4) SG_FOUR(SG_PREC_I8, 4, TWAVES);
+        else if (need <= 8) SG_FOUR(SG_PREC_I8, 8, TWAVES);
+        else return false;
     } else {
         if (need <= 1) SG_FOUR(SG_PREC_FP8, 1, TWAVES);
         else if (need <= 2) SG_FOUR(SG_PREC_FP8, 2, TWAVES);

@@ -45,7 +45,7 @@ def test_reverse_combine_worked_example_through_prune():
 
 @pytest.mark.parametrize("n,K,R", [(300, 32, 16), (1000, 64, 32), (257, 64, 64), (500, 20, 7),
                                    (130, 128, 64), (600, 256, 33), (700, 128, 65), (900, 256, 128),
-                                   (300, 96, 96), (1100, 256, 99)])
+                                   (300, 96, 96), (1100, 256, 99), (1800, 64, 64), (1800, 64, 32)])
 def test_prune_on_random_graphs(n, K, R):
     knn = synthdata.local_graph(n, K, seed=n + K + R) if n > 2 * K + 2 else synthdata.random_graph(n, K, seed=n)
     np.testing.assert_array_equal(_prune_gpu(knn, R), oracle.prune(knn, R))
