@@ -357,6 +357,29 @@ sg_status sg_prune(const int32_t* knn, int64_t n, int32_t K, int32_t R, const in
                    int32_t* out, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * sg_prune_noalloc -- sg_prune without a workspace argument and without
+ * allocating
+ *
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation).  Computes
+ * exactly what sg_prune computes, with the same arguments minus the
+ * workspace: the kernels use a static scratch array of
+ * SG_PRUNE_NOALLOC_SCRATCH_BYTES in the library (one per GPU, held until the
+ * process ends; its device address is looked up on the first call on each
+ * GPU).  The call makes no allocation of any kind.
+ *  Limit: sg_prune_workspace_size(n, K, R) must not exceed
+ *  SG_PRUNE_NOALLOC_SCRATCH_BYTES (64 MiB: about 166 000 rows at R = 32,
+ *  85 000 at R = 64); larger calls return SG_ERR_ARG before any launch.
+ *  Every call on one GPU shares that GPU's scratch (it keeps the last call's
+ *  contents; the call clears what must start at zero): calls that may overlap
+ *  on one GPU (different streams, or different host threads) race, and the
+ *  caller must order them.
+ * ---------------------------------------------------------------------- */
+#define SG_PRUNE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+sg_status sg_prune_noalloc(const int32_t* knn, int64_t n, int32_t K, int32_t R, const int32_t* order,
+                           int32_t* out, void* stream);
+
+/* ------------------------------------------------------------------------
  * sg_merge -- edge-union merge of shard graphs (Sec. II-A, Sec. IV step 3)
  *
  * graphs holds shards 0..S-1's R-wide lists (local ids) back to back, shard

@@ -67,6 +67,7 @@ _SIGS = {
     "sg_knn_rows": (i32, [vp, i32, i64, i32, i64, i32, vp, i64, i32, i32, i32, vp, vp, vp, sz, vp]),
     "sg_prune_workspace_size": (i32, [i64, i32, i32, psz]),
     "sg_prune": (i32, [vp, i64, i32, i32, vp, vp, vp, sz, vp]),
+    "sg_prune_noalloc": (i32, [vp, i64, i32, i32, vp, vp, vp]),
     "sg_merge_workspace_size": (i32, [i32, vp, i64, psz]),
     "sg_merge": (i32, [i32, vp, vp, vp, i32, i64, i32, vp, vp, vp, sz, vp]),
     "sg_search_workspace_size": (i32, [i64, i32, i64, psz]),
@@ -315,6 +316,25 @@ def sg_prune(knn, R, stream=None, out=None, order=None):
     _check("sg_prune", L.sg_prune(_ptr(knn), n, K, R, _ptr(order), _ptr(o), _ptr(ws), ws.numel(),
                                   _stream(stream)))
     return o
+
+
+def sg_prune_noalloc(knn, R, out, stream=None, order=None):
+    """sg_prune on the library's static scratch (no workspace, no allocation
+    in the call): the caller passes the int32 [n, R] output."""
+    L = lib()
+    _dev_tensor(knn, "knn")
+    _dev_tensor(out, "out")
+    if knn.dtype != torch.int32 or not knn.is_contiguous():
+        raise TypeError("knn must be a contiguous int32 tensor")
+    n, K = knn.shape
+    if out.dtype != torch.int32 or not out.is_contiguous() or tuple(out.shape) != (n, R):
+        raise ValueError("out must be a contiguous int32 tensor of shape (n, R)")
+    if order is not None:
+        _dev_tensor(order, "order")
+        if order.dtype != torch.int32 or order.numel() != n:
+            raise ValueError("order must be an int32 tensor of n entries")
+    _check("sg_prune_noalloc", L.sg_prune_noalloc(_ptr(knn), n, K, R, _ptr(order), _ptr(out), _stream(stream)))
+    return out
 
 
 def sg_merge(shard_offsets, member_ids, graphs, R, n_global, max_degree, stream=None):

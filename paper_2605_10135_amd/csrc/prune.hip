@@ -24,6 +24,8 @@
 //    bitonic sort, chunked for high in-degree), then the list
 //    P(y)[0:h] ++ Rev(y) ++ P(y)[h:R] is deduplicated in order (values
 //    compared by lane broadcasts) and cut at R.
+#include <mutex>
+
 #include "common.hpp"
 
 namespace sg {
@@ -452,6 +454,30 @@ inline void enqueue(const int32_t* knn, int64_t n, int K, int R, const int32_t* 
     SG_LAUNCH_CHECK();
 }
 
+// Scratch of sg_prune_noalloc: a file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends).  Host code
+// never passes its name to a kernel: the device address of each GPU's copy
+// is looked up once, with that GPU current, and kept per device.
+constexpr size_t NOALLOC_BYTES = SG_PRUNE_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[MAX_DEVICES] = {};
+
+inline void* scratch_of_current_device() {
+    int dev = 0;
+    SG_HIP(hipGetDevice(&dev));
+    SG_REQUIRE(dev >= 0 && dev < MAX_DEVICES, "device index out of range for the static scratch");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* p = nullptr;
+        SG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        SG_REQUIRE(p != nullptr, "no device address for the static scratch");
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace prune
 }  // namespace sg
 
@@ -476,5 +502,21 @@ extern "C" sg_status sg_prune(const int32_t* knn, int64_t n, int32_t K, int32_t 
             throw Fail{SG_ERR_WORKSPACE};
         }
         prune::enqueue(knn, n, K, R, order, out, ws, as_stream(stream));
+    });
+}
+
+extern "C" sg_status sg_prune_noalloc(const int32_t* knn, int64_t n, int32_t K, int32_t R, const int32_t* order,
+                                      int32_t* out, void* stream) {
+    return guarded([&] {
+        prune::check_args(knn, n, K, R, out);
+        if (n == 0) return;
+        const prune::Layout L = prune::layout(n, R);
+        if (L.total > prune::NOALLOC_BYTES) {
+            set_error("sg_prune_noalloc: n = " + std::to_string(n) + ", R = " + std::to_string(R) + " needs " +
+                      std::to_string(L.total) + " bytes of scratch; the static scratch holds " +
+                      std::to_string(prune::NOALLOC_BYTES) + " (use sg_prune with a workspace)");
+            throw Fail{SG_ERR_ARG};
+        }
+        prune::enqueue(knn, n, K, R, order, out, prune::scratch_of_current_device(), as_stream(stream));
     });
 }
