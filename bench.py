@@ -8,10 +8,11 @@ merge to degree 64.  A step is one pass of the whole hot path over all 16
 shards (16 x sg_knn_graph + 16 x sg_prune + sg_merge) on inputs resident in
 HBM; partition and search are timed but outside the step.
 
-Forms: plain = FP32 MFMA distances; chosen = FP16 MFMA distances, which are
-exact on uint8 rows with d <= 128, so the chosen graph equals the plain graph
-bit for bit (recall 1.0).  `value` is the chosen form's unique vectors per
-second (N / step time); the plain form is timed the same way beside it.
+Forms: plain = FP32 MFMA distances; the exact reduced forms are FP16 MFMA
+(exact on uint8 rows with d <= 128) and INT8 MFMA on the rows shifted by -128
+(exact INT32 sums); both give the plain graph bit for bit (recall 1.0), and the
+faster one is the chosen form.  `value` is the chosen form's unique vectors per
+second (N / step time); the other forms are timed the same way beside it.
 
 Prints ONE JSON line.  --gpus above 1 is refused (one GPU per box here).
 """
@@ -28,7 +29,19 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp32": 157.3, "f16": 2500.0, "bf16": 2500.0, "fp8": 5000.0}   # dense MFMA TFLOP/s
+PEAK = {"fp32": 157.3, "f16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "i8": 5000.0}   # dense MFMA T(FL)OP/s
+
+
+def cpu_model():
+    """Host CPU model name (for the CPU-baseline record)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def log(*a):
@@ -99,7 +112,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--shards", type=int, default=16)
-    ap.add_argument("--chosen", default="f16", choices=["f16", "fp32"])
+    ap.add_argument("--chosen", default="auto", choices=["auto", "f16", "i8", "fp32"],
+                    help="exact form to report (auto: the faster of f16 and i8)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-per-shard", action="store_true",
                     help="skip the comparison with one distance launch and one prune per shard")
@@ -109,7 +123,10 @@ def main():
                          "(counter runs use it to measure the shape a timed run chose)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--queries", type=int, default=10_000)
-    ap.add_argument("--workload", default="sift1m", choices=["sift1m", "precision", "batched", "learned"])
+    ap.add_argument("--workload", default="sift1m",
+                    choices=["sift1m", "precision", "batched", "learned", "partition", "degrees"])
+    ap.add_argument("--oracle-rows", type=int, default=256,
+                    help="rows per shard checked bit for bit against the FP64 oracle")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy 256 MiB device to device (scale for rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
@@ -125,6 +142,10 @@ def main():
         return run_batched(args)
     if args.workload == "learned":
         return run_learned(args)
+    if args.workload == "partition":
+        return run_partition(args)
+    if args.workload == "degrees":
+        return run_degrees(args)
 
     import torch
 
@@ -159,7 +180,8 @@ def main():
     knn_all = torch.empty((total, K), dtype=torch.int32, device=dev)
     flops = float(sum(2.0 * d * float(n) * float(n) for n in sizes))
 
-    forms = [args.chosen] + ([] if args.no_plain or args.chosen == "fp32" else ["fp32"])
+    exact = ["f16", "i8"] if args.chosen == "auto" else [args.chosen]
+    forms = exact + ([] if args.no_plain or "fp32" in exact else ["fp32"])
     # launch-shape autotuning (outside the timed region): the choice is recorded
     # per power-of-two bucket of shard size, so tune the largest shard of each
     # bucket present (the batched pass takes the choice of its largest shard)
@@ -171,29 +193,30 @@ def main():
     tuned = {f: {b_: sg.sg_knn_autotune(shards[i_], K, "l2", f) for b_, i_ in sorted(buckets.items())}
              for f in forms}
     log("autotune %s" % tuned)
-    # the batched pass launches the shape chosen for its largest shard
-    variant = tuned[args.chosen][int(max(sizes)).bit_length() - 1][0]
-    if args.force_variant is not None:
-        sg.sg_knn_force_variant(args.force_variant)
-        variant = args.force_variant
     res = {}
     graph_of = {}
+    if args.force_variant is not None:
+        sg.sg_knn_force_variant(args.force_variant)
     for form in forms:
         step = build_step(sg, torch, Xcat, offs, K, R, form, graphs, knn_all, mem, N)
         sec, kms, launches, (mg, deg) = timed(torch, sg, step, args.steps, args.warmup)
         kavg = kms / max(launches, 1)
         ach = flops * args.steps / (kms / 1e3) / 1e12
         res[form] = dict(sec=sec, kernel_ms_total=kms, launches=launches, kernel_ms_avg=kavg,
-                         tflops=ach, vps=N / sec, shard_rows_ps=total / sec)
-        graph_of[form] = (mg.clone(), deg.clone(), knn_all.clone())
+                         tflops=ach, vps=N / sec, shard_rows_ps=total / sec,
+                         variant=tuned[form][int(max(sizes)).bit_length() - 1][0])
+        graph_of[form] = (mg.clone(), deg.clone(), knn_all.clone(), graphs.clone())
         log("%s: %.3f s/step, dist kernel %d launches, %.3f ms avg, %.1f TFLOP/s" % (
             form, sec, launches, kavg, ach))
 
+    # the chosen form: the faster of the exact reduced forms (same graph)
+    chosen = min(exact, key=lambda f: res[f]["sec"])
+    variant = args.force_variant if args.force_variant is not None else res[chosen]["variant"]
     # stage breakdown of one chosen step (outside the timed region)
     ev = lambda: torch.cuda.Event(enable_timing=True)
     e0, e1, e2 = ev(), ev(), ev()
     e0.record()
-    sg.sg_knn_graph_batched(Xcat, offs, K, R, "l2", args.chosen, out=(graphs, knn_all))
+    sg.sg_knn_graph_batched(Xcat, offs, K, R, "l2", chosen, out=(graphs, knn_all))
     e1.record()
     mg, deg = sg.sg_merge(offs, mem, graphs, R, N, 2 * R)
     e2.record()
@@ -215,13 +238,23 @@ def main():
     e4.record()
     torch.cuda.synchronize()
     prune_ms = e3.elapsed_time(e4)
-    prune_bytes = float(total) * (4 * K + 4 * K * K + 20 * R)
-    merge_bytes = float(total) * R * 4 + float(N) * 2 * R * 4
+    # compulsory HBM bytes per row: the prune reads its K ids once, writes P
+    # and each edge's reverse slot, rereads them to scatter the 32-bit reverse
+    # keys, rereads P and the keys to write F (4K + 24R + 24 with the counts
+    # and offsets); the K lists of K ids it gathers per row are re-reads of the
+    # same graph (cache hits), counted apart.  The merge reads each shard row's
+    # R ids and member id and writes the merged rows and degrees.
+    prune_bytes = float(total) * (4 * K + 24 * R + 24)
+    gather_bytes = float(total) * 4 * K * K
+    merge_bytes = float(total) * (R * 4 + 4) + float(N) * (2 * R * 4 + 4)
     integer_passes = {
-        "prune": {"rows": total, "ms": prune_ms, "algorithmic_bytes": prune_bytes,
-                  "achieved_GBps": prune_bytes / (prune_ms / 1e3) / 1e9},
-        "merge": {"rows": total, "ms": stages["merge_ms"], "algorithmic_bytes": merge_bytes,
-                  "achieved_GBps": merge_bytes / (stages["merge_ms"] / 1e3) / 1e9},
+        "prune": {"rows": total, "ms": prune_ms, "compulsory_bytes": prune_bytes,
+                  "achieved_GBps": prune_bytes / (prune_ms / 1e3) / 1e9,
+                  "frac_of_hbm_peak": prune_bytes / (prune_ms / 1e3) / 8e12,
+                  "gathered_list_bytes": gather_bytes},
+        "merge": {"rows": total, "ms": stages["merge_ms"], "compulsory_bytes": merge_bytes,
+                  "achieved_GBps": merge_bytes / (stages["merge_ms"] / 1e3) / 1e9,
+                  "frac_of_hbm_peak": merge_bytes / (stages["merge_ms"] / 1e3) / 8e12},
     }
     log("integer passes %s" % integer_passes)
     del knn_batch, row0
@@ -232,57 +265,61 @@ def main():
         nbrs = [torch.empty((int(n), K), dtype=torch.int32, device=dev) for n in sizes]
         orders = [torch.empty(int(n), dtype=torch.int32, device=dev) for n in sizes]
         g1 = torch.empty_like(graphs)
-        ps = build_per_shard_step(sg, shards, K, R, args.chosen, g1, nbrs, orders, mem, offs, N)
+        ps = build_per_shard_step(sg, shards, K, R, chosen, g1, nbrs, orders, mem, offs, N)
         ps_sec, ps_kms, ps_launches, (pmg, pdeg) = timed(torch, sg, ps, 2, 1)
         per_shard = {"ms_per_step": ps_sec * 1e3, "dist_launches_per_step": ps_launches // 2,
                      "dist_kernel_ms_per_step": ps_kms / 2,
-                     "graph_identical_to_batched": bool(torch.equal(torch.cat(nbrs), graph_of[args.chosen][2])
-                                                        and torch.equal(pmg, graph_of[args.chosen][0])
-                                                        and torch.equal(pdeg, graph_of[args.chosen][1]))}
+                     "graph_identical_to_batched": bool(torch.equal(torch.cat(nbrs), graph_of[chosen][2])
+                                                        and torch.equal(pmg, graph_of[chosen][0])
+                                                        and torch.equal(pdeg, graph_of[chosen][1]))}
         log("per-shard launches: %.1f ms/step, identical %s" % (ps_sec * 1e3,
                                                                 per_shard["graph_identical_to_batched"]))
         del nbrs, orders, g1
 
     same = None
-    if "fp32" in graph_of and args.chosen != "fp32":
-        a, b = graph_of[args.chosen], graph_of["fp32"]
+    if "fp32" in graph_of and chosen != "fp32":
+        a, b = graph_of[chosen], graph_of["fp32"]
         same = bool(torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2]))
+    same_exact = all(torch.equal(graph_of[f][0], graph_of[chosen][0]) and torch.equal(graph_of[f][2], graph_of[chosen][2])
+                     for f in exact)
 
-    # search recall@10 on held-out queries (outside the step)
-    t = time.perf_counter()
-    ids, _ = sg.sg_search(Xd, mg, Qd, 10, 64)
-    torch.cuda.synchronize()
-    t_search = time.perf_counter() - t
-    gt = []
-    xf = Xd.float()
-    xn = (xf * xf).sum(1)
-    for a in range(0, Qd.shape[0], 256):
-        qf = Qd[a:a + 256].float()
-        dd = (qf * qf).sum(1, keepdim=True) + xn[None, :] - 2.0 * (qf @ xf.T)
-        gt.append(torch.topk(dd, 10, dim=1, largest=False).values[:, -1])
-    kth = torch.cat(gt)
-    qf = Qd.float()
-    got = ids.long()
-    dq = ((qf[:, None, :] - xf[got.clamp(min=0)]) ** 2).sum(-1)
-    hits = ((dq <= kth[:, None]) & (got >= 0)).float().sum(1)
-    recall10 = float((hits / 10.0).mean())
+    search = search_study(torch, sg, Xd, Qd, mg, deg)
 
-    # sampled exact check of the chosen kNN lists against the FP64 oracle
+    # exact check of the chosen kNN lists against the FP64 oracle: seeded rows
+    # of every shard; the pruned graph of the smallest shard against the
+    # oracle's prune of the GPU's own kNN lists
     import oracle
     rng = np.random.default_rng(5)
-    s0 = 0
-    X0 = X[mem[offs[s0]:offs[s0 + 1]].cpu().numpy()]
-    X0_64 = oracle.widen(X0)
-    rows = rng.choice(X0.shape[0], size=64, replace=False)
-    onbr, _ = oracle.knn(X0_64, K, rows=rows)
-    gnbr = graph_of[args.chosen][2][offs[s0]:offs[s0 + 1]].cpu().numpy()[rows]
-    knn_recall = float(np.mean([len(set(a) & set(b)) / K for a, b in zip(gnbr, onbr)]))
-    knn_exact = bool(np.array_equal(gnbr, onbr))
+    t = time.perf_counter()
+    rows_checked, rows_equal, knn_hits = 0, 0, 0
+    X_h = X
+    mem_h = mem.cpu().numpy()
+    knn_h = graph_of[chosen][2].cpu().numpy()
+    for s_ in range(S):
+        Xs = X_h[mem_h[offs[s_]:offs[s_ + 1]]]
+        Xs64 = oracle.widen(Xs)
+        rows = rng.choice(Xs.shape[0], size=min(args.oracle_rows, Xs.shape[0]), replace=False)
+        onbr, _ = oracle.knn(Xs64, K, rows=rows)
+        g = knn_h[offs[s_]:offs[s_ + 1]][rows]
+        rows_checked += len(rows)
+        rows_equal += int((g == onbr).all(1).sum())
+        knn_hits += sum(len(set(x_) & set(y_)) for x_, y_ in zip(g, onbr))
+    s_small = int(np.argmin(sizes))
+    a_, b_ = offs[s_small], offs[s_small + 1]
+    prune_equal = bool(np.array_equal(graph_of[chosen][3][a_:b_].cpu().numpy(), oracle.prune(knn_h[a_:b_], R)))
+    oracle_check = {"knn_rows_checked": rows_checked, "knn_rows_identical_to_oracle": rows_equal,
+                    "knn_recall_at_64": knn_hits / float(rows_checked * K),
+                    "pruned_graph_identical_to_oracle": {"shard": s_small, "rows": int(b_ - a_),
+                                                         "identical": prune_equal},
+                    "seconds": time.perf_counter() - t}
+    log("oracle check %s" % oracle_check)
 
     # CPU baseline: the FP64 oracle on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu:
-        n0 = X0.shape[0]
+        s0 = 0
+        X0_64 = oracle.widen(X_h[mem_h[offs[s0]:offs[s0 + 1]]])
+        n0 = X0_64.shape[0]
         oracle.knn(X0_64, K, rows=np.arange(2))          # warm-up (library load, thread start)
         nprobe = 4 * oracle.num_threads()
         probe = rng.choice(n0, size=nprobe, replace=False)
@@ -297,17 +334,20 @@ def main():
         per_pair = dt / (m * n0)
         t_full = per_pair * float(sum(float(n) * float(n) for n in sizes))
         cpu = {"value": N / t_full, "unit": "vectors/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
+               "cpu_model": cpu_model(), "kind": "oracle",
                "sample": "exact FP64 kNN (K=64) of %d rows of shard 0 (%d rows, d=128) in %.1f s, "
                          "scaled by sum(n_s^2) to the full 16-shard kNN stage (prune and merge "
                          "not included, which favours the CPU)" % (m, n0, dt)}
 
-    ch = res[args.chosen]
-    prec = args.chosen
-    traf = traffic_of("sift1m_u8", variant) if prec == "f16" else None
-    # algorithmic bytes: each shard's rows read once as 16-bit operands, the
-    # K-list of ids written once
-    alg_bytes = float(sum(float(n) * (2 * d + 4 * K) for n in sizes))
+    ch = res[chosen]
+    prec = chosen
+    traf = traffic_of("sift1m_u8_%s" % prec, variant)
+    # algorithmic bytes: each shard's rows read once as operands, the K-list
+    # of ids written once
+    eb = {"fp32": 4, "f16": 2, "i8": 1}[prec]
+    alg_bytes = float(sum(float(n) * (eb * d + 4 * K) for n in sizes))
+    dtype_of = {"f16": "u8->f16 MFMA, f32 acc", "i8": "u8-128->i8 MFMA, i32 acc",
+                "fp32": "u8->f32 MFMA, f32 acc"}
     line = {
         "metric": "kNN-graph build vectors/sec on 1 GPU at recall@k>=0.95; chosen vs plain",
         "value": ch["vps"],
@@ -319,7 +359,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u8->f16 MFMA, f32 acc" if prec == "f16" else "u8->f32 MFMA, f32 acc",
+        "dtype": dtype_of[prec],
         "data": "synthetic",
         "config": {"workload": "N=1,000,000 x 128 u8 (1000-Gaussian mixture, centres U[0,200], "
                                "std 12), 16 overlapping k-means shards (omega=2), exact kNN K=64, "
@@ -327,9 +367,10 @@ def main():
                    "form": prec, "n": N, "d": d, "shards": S, "K": K, "R": R,
                    "shard_rows": total},
         "roofline": {"bound": "mfma", "achieved": ch["tflops"], "peak": PEAK[prec],
-                     "unit": "TFLOP/s", "frac": ch["tflops"] / PEAK[prec],
+                     "unit": "TOP/s" if prec == "i8" else "TFLOP/s", "frac": ch["tflops"] / PEAK[prec],
                      "traffic": traf["bytes"] if traf else None,
-                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_unit": "bytes past L2 per launch (TCC FETCH_SIZE + WRITE_SIZE, copy-calibrated; "
+                                     "mostly served by the MALL)",
                      "kernel": "dist_topk_batched_kernel (all 16 shards in one launch)",
                      "variant": variant,
                      "traffic_kernel": traf["kernels"] if traf else None,
@@ -337,16 +378,23 @@ def main():
                      "flops_per_launch_avg": flops * args.steps / max(ch["launches"], 1),
                      "algorithmic_bytes_per_launch_avg": alg_bytes * args.steps / max(ch["launches"], 1)},
         "cpu_baseline": cpu,
-        "recall": {"knn_at_64_sampled": knn_recall, "knn_rows_identical_to_oracle": knn_exact,
-                   "search_recall_at_10_L64": recall10},
+        "recall": {"knn_at_64_sampled": oracle_check["knn_recall_at_64"],
+                   "knn_rows_identical_to_oracle": oracle_check["knn_rows_identical_to_oracle"]
+                   == oracle_check["knn_rows_checked"],
+                   "search_recall_at_10_L64": search["recall_at_10"]["64"]},
+        "oracle_check": oracle_check,
+        "search": search,
         "shard_rows_per_s": ch["shard_rows_ps"],
         "stages_ms": stages,
         "integer_passes": integer_passes,
         "per_shard_launches": per_shard,
+        "forms": {f: {"value": res[f]["vps"], "ms_per_step": res[f]["sec"] * 1e3,
+                      "kernel_ms_avg": res[f]["kernel_ms_avg"], "achieved": res[f]["tflops"],
+                      "frac": res[f]["tflops"] / PEAK[f], "variant": res[f]["variant"]} for f in res},
+        "exact_forms_identical": same_exact,
         "autotune": {f: {"2^%d" % b_: {"chosen": c, "variant_ms": t} for b_, (c, t) in v.items()}
                      for f, v in tuned.items()},
         "partition_s": t_part,
-        "search_s_10k_queries_L64": t_search,
     }
     if "fp32" in res and prec != "fp32":
         pl = res["fp32"]
@@ -356,6 +404,57 @@ def main():
         line["chosen_vs_plain"] = ch["vps"] / pl["vps"]
         line["chosen_graph_identical_to_plain"] = same
     print(json.dumps(line), flush=True)
+
+
+def search_study(torch, sg, Xd, Qd, mg, deg, Ls=(16, 32, 64, 128, 256)):
+    """Greedy-search recall@10 of the merged graph on the held-out queries for
+    several beam widths, and the graph's reachability: the vertices reachable
+    from the medoid entry, the weakly connected components, and the share of
+    queries whose true nearest neighbour is reachable."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import breadth_first_order, connected_components
+
+    xf = Xd.float()
+    xn = (xf * xf).sum(1)
+    gt, nn1 = [], []
+    for a in range(0, Qd.shape[0], 256):
+        qf = Qd[a:a + 256].float()
+        dd = (qf * qf).sum(1, keepdim=True) + xn[None, :] - 2.0 * (qf @ xf.T)
+        v, i = torch.topk(dd, 10, dim=1, largest=False)
+        gt.append(v[:, -1])
+        nn1.append(i[:, 0])
+    kth, nn1 = torch.cat(gt), torch.cat(nn1)
+    qf = Qd.float()
+    rec, secs = {}, {}
+    for L in Ls:
+        t = time.perf_counter()
+        ids, _ = sg.sg_search(Xd, mg, Qd, 10, L)
+        torch.cuda.synchronize()
+        secs[str(L)] = time.perf_counter() - t
+        got = ids.long()
+        dq = ((qf[:, None, :] - xf[got.clamp(min=0)]) ** 2).sum(-1)
+        hits = ((dq <= kth[:, None]) & (got >= 0)).float().sum(1)
+        rec[str(L)] = float((hits / 10.0).mean())
+    # the medoid entry as the library picks it: the row nearest to the mean
+    mean = Xd.double().mean(0).float()
+    medoid = int(torch.argmin(((xf - mean[None, :]) ** 2).sum(1)).item())
+    G = mg.cpu().numpy()
+    n, w = G.shape
+    src = np.repeat(np.arange(n), w)
+    dst = G.ravel()
+    ok = dst >= 0
+    A = sp.csr_matrix((np.ones(int(ok.sum()), np.int8), (src[ok], dst[ok])), shape=(n, n))
+    reach = breadth_first_order(A, medoid, directed=True, return_predecessors=False)
+    reachable = np.zeros(n, bool)
+    reachable[reach] = True
+    ncomp, labels = connected_components(A, directed=True, connection="weak")
+    nn1_h = nn1.cpu().numpy()
+    return {"recall_at_10": rec, "seconds_10k_queries": secs, "medoid": medoid,
+            "reachable_from_medoid": int(reachable.sum()), "n": n,
+            "weak_components": int(ncomp),
+            "largest_component": int(np.bincount(labels).max()),
+            "queries_with_reachable_nn": float(reachable[nn1_h].mean()),
+            "mean_degree": float(deg.float().mean().item())}
 
 
 def run_precision(args):
@@ -472,6 +571,169 @@ def run_precision(args):
         "forms": res, "recall_at_64_vs_plain": recall, "vs_fp64_oracle_100_rows": err,
         "autotune": tuned,
         "chosen_vs_plain": ch["vps"] / res["fp32"]["vps"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+def _headline_data(args, torch, sg, synthdata, dev, n_comp=1000):
+    """The headline rows, queries and seeded initial centroids (n_comp mixture
+    components; 1000 for the headline workload)."""
+    N, d, S = args.n, 128, args.shards
+    X = synthdata.sift_like_u8(n=N, d=d, seed=1001, n_comp=n_comp)
+    Q = synthdata.sift_like_u8(n=args.queries, d=d, seed=1001, stream=1, n_comp=n_comp)
+    return (X, torch.from_numpy(X).to(dev), torch.from_numpy(Q).to(dev),
+            synthdata.init_rows(N, S, seed=1001))
+
+
+def _exact_build(torch, sg, Xd, mem, offs, K, R, N, prec, steps, warmup):
+    """Batched exact build (kNN + prune) of the shards then the merge; returns
+    (seconds per step, kernel ms per launch, merged graph, degrees, kNN lists,
+    pruned graphs)."""
+    dev = Xd.device
+    Xcat = Xd[mem.long()].contiguous()
+    total = int(offs[-1])
+    graphs = torch.empty((total, R), dtype=torch.int32, device=dev)
+    knn_all = torch.empty((total, K), dtype=torch.int32, device=dev)
+    step = build_step(sg, torch, Xcat, offs, K, R, prec, graphs, knn_all, mem, N)
+    sec, kms, launches, (mg, deg) = timed(torch, sg, step, steps, warmup)
+    return sec, kms / max(launches, 1), mg, deg, knn_all, graphs
+
+
+def run_partition(args):
+    """Selectivity study (Sec. V-B, Algorithm 1; the paper's Table IV) on the
+    headline workload: the rows are assigned block by block (64k-row blocks in
+    row order, as a disk-resident set is read) with the blockwise-adaptive
+    rule for epsilon in {1.1, 1.2, 1.5} and the original replicate-to-nearest
+    rule (epsilon = inf); for each: the replica proportion (replicas / N, 100%
+    for the original rule with omega = 2), the partition time, the exact build
+    (batched kNN + prune + merge) and the search recall of the merged graph.
+    Two data sets: the headline's 1000-component mixture (each shard then
+    averages ~60 components, so a row's nearest and second-nearest shard
+    centroids are at similar distances) and the same recipe with 64
+    components (a few components per shard)."""
+    import torch
+
+    import paper_2605_10135_amd as sg
+    import synthdata
+
+    dev = torch.device("cuda:0")
+    study = {}
+    for n_comp in (1000, 64):
+        study["components_%d" % n_comp] = _selectivity(args, torch, sg, synthdata, dev, n_comp)
+    out = study["components_1000"]
+    ch = out["eps_1.2"]
+    line = {
+        "metric": "kNN-graph build vectors/sec on 1 GPU at recall@k>=0.95; chosen vs plain",
+        "value": ch["vectors_per_s"], "unit": "vectors/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ch["build_ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8-128->i8 MFMA, i32 acc", "data": "synthetic",
+        "config": {"workload": "selectivity study: N=1,000,000 x 128 u8 (1000- and 64-Gaussian mixtures), 16 "
+                               "shards, omega=2, blockwise-adaptive assignment in 65536-row blocks, epsilon in "
+                               "{1.1, 1.2, 1.5, inf}, exact kNN K=64, prune R=32, merge; value = epsilon 1.2, "
+                               "1000 components"},
+        "roofline": None, "cpu_baseline": None,
+        "selectivity": study,
+        "chosen_vs_plain": ch["vectors_per_s"] / out["original"]["vectors_per_s"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+def _selectivity(args, torch, sg, synthdata, dev, n_comp):
+    X, Xd, Qd, init = _headline_data(args, torch, sg, synthdata, dev, n_comp)
+    N, S, omega, K, R = args.n, args.shards, 2, 64, 32
+    prec = "i8"
+    out = {}
+    for name, eps, tau0 in (("original", float("inf"), 1.0), ("eps_1.5", 1.5, 1.5), ("eps_1.2", 1.2, 1.5),
+                            ("eps_1.1", 1.1, 1.5)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        cent, prim, off, mem = sg.sg_partition_blockwise(Xd, S, omega, 20, init, epsilon=eps, tau0=tau0,
+                                                         block_rows=65536, shard_cap=0, adaptive=True)
+        torch.cuda.synchronize()
+        t_part = time.perf_counter() - t
+        offs = [int(v) for v in off.tolist()]
+        sizes = np.diff(offs)
+        # tune the launch shape on the largest shard of each size bucket
+        buckets = {}
+        for i_, n_ in enumerate(sizes):
+            b_ = int(n_).bit_length() - 1
+            if b_ not in buckets or n_ > sizes[buckets[b_]]:
+                buckets[b_] = i_
+        for b_, i_ in buckets.items():
+            sg.sg_knn_autotune(Xd[mem[offs[i_]:offs[i_ + 1]].long()].contiguous(), K, "l2", prec)
+        sec, kms, mg, deg, _, _ = _exact_build(torch, sg, Xd, mem, offs, K, R, N, prec, args.steps, args.warmup)
+        search = search_study(torch, sg, Xd, Qd, mg, deg, Ls=(64, 128))
+        out[name] = {"epsilon": eps, "tau0": tau0, "shard_rows": int(offs[-1]),
+                     "replica_proportion": (offs[-1] - N) / float(N * (omega - 1)),
+                     "partition_s": t_part, "build_ms_per_step": sec * 1e3, "dist_kernel_ms": kms,
+                     "vectors_per_s": N / sec, "search_recall_at_10": search["recall_at_10"],
+                     "reachable_from_medoid": search["reachable_from_medoid"],
+                     "weak_components": search["weak_components"], "shard_sizes": sizes.tolist()}
+        log("%d components, %s: %s" % (n_comp, name, {k: v for k, v in out[name].items() if k != "shard_sizes"}))
+    return out
+
+
+def run_degrees(args):
+    """The paper's default and stress degree settings (degree R from K
+    candidates: 64 from 128, 128 from 256) on the headline workload: exact
+    batched build, prune and merge; seeded rows of every shard and the pruned
+    graph of the smallest shard checked against the oracle."""
+    import torch
+
+    import oracle
+    import paper_2605_10135_amd as sg
+    import synthdata
+
+    dev = torch.device("cuda:0")
+    X, Xd, Qd, init = _headline_data(args, torch, sg, synthdata, dev)
+    N, S, omega, d = args.n, args.shards, 2, 128
+    cent, prim, off, mem = sg.sg_partition(Xd, S, omega, 20, init)
+    offs = [int(v) for v in off.tolist()]
+    sizes = np.diff(offs)
+    mem_h = mem.cpu().numpy()
+    flops = float(sum(2.0 * d * float(n) * float(n) for n in sizes))
+    out = {}
+    for K, R in ((64, 32), (128, 64), (256, 128)):
+        res = {}
+        for prec in ("f16", "i8"):
+            sg.sg_knn_autotune(Xd[mem[offs[int(np.argmax(sizes))]:offs[int(np.argmax(sizes)) + 1]].long()]
+                               .contiguous(), K, "l2", prec)
+            sec, kms, mg, deg, knn_all, graphs = _exact_build(torch, sg, Xd, mem, offs, K, R, N, prec,
+                                                              args.steps, args.warmup)
+            res[prec] = (sec, kms)
+            log("K=%d R=%d %s: %.1f ms/step, dist %.1f ms" % (K, R, prec, sec * 1e3, kms))
+        prec = min(res, key=lambda p_: res[p_][0])
+        sec, kms, mg, deg, knn_all, graphs = _exact_build(torch, sg, Xd, mem, offs, K, R, N, prec, 1, 0)
+        rng = np.random.default_rng(K)
+        knn_h = knn_all.cpu().numpy()
+        checked = equal = 0
+        for s_ in range(S):
+            Xs64 = oracle.widen(X[mem_h[offs[s_]:offs[s_ + 1]]])
+            rows = rng.choice(Xs64.shape[0], size=min(64, Xs64.shape[0]), replace=False)
+            onbr, _ = oracle.knn(Xs64, K, rows=rows)
+            checked += len(rows)
+            equal += int((knn_h[offs[s_]:offs[s_ + 1]][rows] == onbr).all(1).sum())
+        s_small = int(np.argmin(sizes))
+        a_, b_ = offs[s_small], offs[s_small + 1]
+        prune_ok = bool(np.array_equal(graphs[a_:b_].cpu().numpy(), oracle.prune(knn_h[a_:b_], R)))
+        search = search_study(torch, sg, Xd, Qd, mg, deg, Ls=(64, 128))
+        out["%d/%d" % (R, K)] = {
+            "K": K, "R": R, "form": prec, "ms_per_step": res[prec][0] * 1e3, "vectors_per_s": N / res[prec][0],
+            "dist_kernel_ms": res[prec][1], "dist_achieved": flops / (res[prec][1] / 1e3) / 1e12,
+            "forms_ms_per_step": {p_: v[0] * 1e3 for p_, v in res.items()},
+            "knn_rows_checked": checked, "knn_rows_identical_to_oracle": equal,
+            "pruned_graph_identical_to_oracle": {"shard": s_small, "rows": int(b_ - a_), "identical": prune_ok},
+            "search_recall_at_10": search["recall_at_10"]}
+        log("%d/%d: %s" % (R, K, out["%d/%d" % (R, K)]))
+    ch = out["64/128"]
+    line = {
+        "metric": "kNN-graph build vectors/sec on 1 GPU at recall@k>=0.95; chosen vs plain",
+        "value": ch["vectors_per_s"], "unit": "vectors/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ch["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "exact u8 MFMA (%s)" % ch["form"], "data": "synthetic",
+        "config": {"workload": "degree settings R/K = 32/64, 64/128, 128/256 on N=1,000,000 x 128 u8, "
+                               "16 shards (omega=2), exact batched build + prune + merge; value = 64/128"},
+        "roofline": None, "cpu_baseline": None, "degrees": out,
     }
     print(json.dumps(line), flush=True)
 

@@ -16,6 +16,13 @@ Usage::
     python -m paper_2605_10135_amd.profiling stats  <kernel_stats.csv> <out.md> "<command>"
     python -m paper_2605_10135_amd.profiling traffic <fetch.csv> <write.csv> <out.txt> "<fetch cmd>" "<write cmd>" [kernel filter]
     python -m paper_2605_10135_amd.profiling integer <fetch.csv> <write.csv> <out.md> "<fetch cmd>" "<write cmd>" <filter,filter,...>
+    python -m paper_2605_10135_amd.profiling counters <out.md> <kernel filter> <flops per dispatch> <cmd> <pmc.csv>...
+
+The counters summary gives, for the dispatches of the named kernel, the mean
+per dispatch of every counter in the given --pmc files (one file per pass)
+and the derived figures: MFMA busy share of the SIMD cycles, VALU and SALU
+instructions per MFMA instruction, L2 hit rate, and the achieved rate from
+the dispatch durations of the counter runs.
 """
 from __future__ import annotations
 
@@ -25,7 +32,8 @@ import os
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/knn.hip", "csrc/knn_impl.hpp", "csrc/common.hpp", "csrc/batch.hip")
+KERNEL_SOURCES = ("csrc/knn.hip", "csrc/knn_impl.hpp", "csrc/common.hpp", "csrc/batch.hip",
+                  "csrc/batch_impl.hpp", "csrc/shapes.hpp")
 CALIB_BYTES = 256 << 20          # bytes read and bytes written by the calibration copy
 DIST_KERNEL = "dist_topk"        # default kernel-name filter
 
@@ -153,6 +161,66 @@ def integer_table(fetch_csv: str, write_csv: str, out: str, fetch_cmd: str, writ
     print("\n".join(lines))
 
 
+def _pmc_rows(path: str, kernel: str) -> dict:
+    """counter -> list of (value, duration ns) over dispatches of kernels whose
+    names hold `kernel`."""
+    acc = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if kernel not in _short(r["Kernel_Name"]):
+                continue
+            dur = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            acc.setdefault(r["Counter_Name"], []).append((float(r["Counter_Value"]), dur))
+    return acc
+
+
+CUS, SIMDS_PER_CU = 256, 4
+
+
+def counters(out: str, kernel: str, flops: str, command: str, *pmc_csvs: str) -> None:
+    """Markdown summary of the --pmc passes of one kernel (see the module doc)."""
+    means, durs = {}, []
+    for path in pmc_csvs:
+        for name, vals in _pmc_rows(path, kernel).items():
+            means[name] = sum(v for v, _ in vals) / len(vals)
+            durs.extend(d for _, d in vals)
+    if not means:
+        raise SystemExit("no dispatch of %s in the counter files" % kernel)
+    lines = ["# Counters of `%s` (rocprofv3 --pmc, mean per dispatch)" % kernel, "",
+             "Command (one run per pass): `%s`" % command, "",
+             "Distance-kernel sources sha256: `%s`" % kernel_sha(), "",
+             "| counter | mean per dispatch |", "|---|---:|"]
+    for name in sorted(means):
+        lines.append("| `%s` | %.4g |" % (name, means[name]))
+    lines += ["", "Derived:", ""]
+    mfma_insts = sum(v for k, v in means.items() if k.startswith("SQ_INSTS_VALU_MFMA_MOPS"))
+    if "SQ_VALU_MFMA_BUSY_CYCLES" in means and "GRBM_GUI_ACTIVE" in means:
+        simd_cycles = means["GRBM_GUI_ACTIVE"] * CUS * SIMDS_PER_CU
+        lines.append("* MFMA busy / SIMD cycles (GRBM_GUI_ACTIVE x %d CUs x %d SIMDs): %.3f"
+                     % (CUS, SIMDS_PER_CU, means["SQ_VALU_MFMA_BUSY_CYCLES"] / simd_cycles))
+        lines.append("* MFMA busy / CU cycles (GRBM_GUI_ACTIVE x %d CUs): %.3f"
+                     % (CUS, means["SQ_VALU_MFMA_BUSY_CYCLES"] / (means["GRBM_GUI_ACTIVE"] * CUS)))
+    if "SQ_INSTS_MFMA" in means and means["SQ_INSTS_MFMA"] > 0:
+        m = means["SQ_INSTS_MFMA"]
+        for k in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS"):
+            if k in means:
+                extra = means[k] - m if k == "SQ_INSTS_VALU" else means[k]
+                lines.append("* %s per MFMA instruction%s: %.2f" % (
+                    k, " (MFMA excluded)" if k == "SQ_INSTS_VALU" else "", extra / m))
+    if mfma_insts:
+        lines.append("* MFMA MOPs (512 ops each) per dispatch: %.4g" % mfma_insts)
+    if "TCC_HIT_sum" in means and "TCC_MISS_sum" in means:
+        tot = means["TCC_HIT_sum"] + means["TCC_MISS_sum"]
+        lines.append("* L2 hit rate: %.3f" % (means["TCC_HIT_sum"] / tot if tot else float("nan")))
+    if durs and float(flops) > 0:
+        avg_ms = sum(durs) / len(durs) / 1e6
+        lines.append("* mean dispatch duration in the counter runs: %.3f ms -> %.1f T(FL)OP/s for %.4g "
+                     "algorithmic ops per dispatch" % (avg_ms, float(flops) / (avg_ms / 1e3) / 1e12, float(flops)))
+    with open(out, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def read_traffic(path: str):
     """Bytes per distance-kernel launch from a traffic record, or None when the
     record is missing or was taken on other kernel sources."""
@@ -202,6 +270,8 @@ if __name__ == "__main__":
         traffic(*sys.argv[2:9])
     elif len(sys.argv) >= 8 and sys.argv[1] == "integer":
         integer_table(*sys.argv[2:8])
+    elif len(sys.argv) >= 7 and sys.argv[1] == "counters":
+        counters(*sys.argv[2:])
     else:
         print(__doc__)
         sys.exit(2)
