@@ -37,6 +37,14 @@
 namespace sg {
 namespace knn {
 
+// ||c'||^2 = -2 (e >> 1) + (e & 1) from the INT8 L2 start word e.
+__global__ void i8_norms_kernel(float* __restrict__ v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t e = __builtin_bit_cast(int32_t, v[i]);
+        v[i] = (float)(-2 * (e >> 1) + (e & 1));
+    }
+}
+
 std::mutex g_tune_mu;
 std::map<TuneKey, int> g_tune;
 thread_local int g_force_variant = -1;
@@ -353,5 +361,9 @@ extern "C" sg_status sg_quantize_rows(const void* X, sg_dtype dtype, int64_t n, 
                                                                SG_L2, static_cast<uint8_t*>(out), sqnorm, nullptr,
                                                                prec == SG_PREC_FP8 ? scale_exp : nullptr);
         SG_LAUNCH_CHECK();
+        if (prec == SG_PREC_I8 && sqnorm) {   // the INT8 start word back to the squared norm
+            knn::i8_norms_kernel<<<(unsigned)std::min<int64_t>(cdiv(n, 256), 4096), 256, 0, s>>>(sqnorm, n);
+            SG_LAUNCH_CHECK();
+        }
     });
 }

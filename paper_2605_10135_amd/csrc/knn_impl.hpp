@@ -117,7 +117,14 @@ __device__ inline float fp8_value(uint8_t c) {
 //   L2, I8         key = ||c'||^2 - 2 q'.c'            dist = key + ||q'||^2
 //   IP, I8         key = -128 S(c') - q'.c'             dist = key - 128 S(q') - 16384 d
 // (x' = x - 128 for U8 rows, S = the sum of the elements; every term is an
-// integer below 2^24, so the FP32 key is exact)
+// integer below 2^24, so the FP32 key is exact).  The INT8 accumulator starts
+// at a = -floor(||c'||^2 / 2) (L2) or 128 S(c') (IP), so that the key is
+// p - 2 acc (L2, p = ||c'||^2 mod 2) or -acc (IP): a subtile is rejected from
+// the largest accumulator alone (key >= -2 acc, resp. -acc), and p is needed
+// only for the candidates that pass.  A candidate's start and p travel as
+// e = 2a + p (int32 bits in the start array; a = e >> 1, p = e & 1).
+constexpr int32_t I8_PAD_E = -(1 << 30);   // padding rows: a = -2^29, keys near 2^30, never admitted
+constexpr int32_t I8_PAD_A = I8_PAD_E >> 1;
 // (x~ = the rounded operand row).  The reduced-precision IP key is the L2 key
 // of the rounded rows with the exact norm put back: its rounding error scales
 // with ||q - c|| instead of ||q|| ||c||, which keeps near neighbours apart.
@@ -147,7 +154,9 @@ static __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_
             else out[t] = 0;
         }
         if (l == 0) {
-            if (ninit) ninit[row] = __builtin_nanf("");   // never admitted: NaN fails every comparison
+            // never admitted: NaN fails every comparison (INT8: a start far
+            // beyond any key, turned into NaN where keys are formed)
+            if (ninit) ninit[row] = prec == SG_PREC_I8 ? __builtin_bit_cast(float, I8_PAD_E) : __builtin_nanf("");
             if (nout) nout[row] = 0.f;
             if (sexp) sexp[row] = 0;
         }
@@ -213,9 +222,13 @@ static __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_
     if (l == 0) {
         float term = metric == SG_L2 ? ssq : norm_corrected_ip(metric, prec) ? ssq - ssx : 0.f;
         float oterm = term;
-        if (prec == SG_PREC_I8 && metric == SG_IP) {
-            term = -128.f * ssx;
-            oterm = term - 16384.f * (float)d;
+        if (prec == SG_PREC_I8) {
+            // the accumulator start and parity of the row as a candidate (see
+            // the key table above); ssq and ssx are exact integers
+            const int32_t n2 = (int32_t)ssq, sx8 = (int32_t)ssx;
+            const int32_t e = metric == SG_L2 ? -2 * (n2 >> 1) + (n2 & 1) : 2 * 128 * sx8;
+            term = __builtin_bit_cast(float, e);
+            if (metric == SG_IP) oterm = -128.f * ssx - 16384.f * (float)d;
         }
         if (ninit) ninit[row] = term;
         if (nout) nout[row] = oterm;
@@ -390,12 +403,10 @@ __device__ inline floatx16 mfma_tile(const uint8_t* arow, const Frag<P, NSTEP>& 
     return acc;
 }
 
-// acc = A(32 candidate rows at arow, LDS) x Q(32 queries) over the padded
-// row with INT8 operands: exact INT32 sums from zero (the accumulator start
-// and the query factor are applied when the keys are formed, i8_keys).
+// acc += A(32 candidate rows at arow, LDS) x Q(32 queries) over the padded
+// row with INT8 operands: exact INT32 sums.
 template <int NSTEP, int GMAX = 8>
-__device__ inline intx16 mfma_tile_i8(const uint8_t* arow, const Frag<SG_PREC_I8, NSTEP>& q) {
-    intx16 acc = {};
+__device__ inline intx16 mfma_tile_i8(const uint8_t* arow, const Frag<SG_PREC_I8, NSTEP>& q, intx16 acc) {
     constexpr int G = group_of(NSTEP, GMAX);
 #pragma unroll
     for (int g = 0; g < NSTEP; g += G) {
@@ -409,13 +420,22 @@ __device__ inline intx16 mfma_tile_i8(const uint8_t* arow, const Frag<SG_PREC_I8
     return acc;
 }
 
-// FP32 ranking keys of an INT8 subtile: start + qmul * acc, exact (every
-// value is an integer below 2^24); a NaN start (padding row) stays NaN.
-__device__ inline floatx16 i8_keys(const intx16& acc, const floatx4 (&nv)[4], float qmul) {
+// Exact FP32 keys of an INT8 subtile, key = p + qmul * acc (qmul = -2 for
+// L2 with the rows' parities p, -1 for IP with p = 0); padding rows give NaN.
+__device__ inline floatx16 i8_keys(const intx16& acc, const intx4 (&par)[4], int qmul) {
     floatx16 k;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) k[i] = __builtin_fmaf(qmul, (float)acc[i], nv[i >> 2][i & 3]);
+    for (int i = 0; i < 16; ++i)
+        k[i] = acc[i] == I8_PAD_A ? __builtin_nanf("") : (float)(par[i >> 2][i & 3] + qmul * acc[i]);
     return k;
+}
+
+// Largest of a lane's 16 INT8 accumulators (eight 3-input maximums).
+__device__ inline int32_t max16(const intx16& a) {
+    const int32_t p0 = max(max(a[0], a[1]), a[2]), p1 = max(max(a[3], a[4]), a[5]);
+    const int32_t p2 = max(max(a[6], a[7]), a[8]), p3 = max(max(a[9], a[10]), a[11]);
+    const int32_t p4 = max(max(a[12], a[13]), a[14]);
+    return max(max(max(p0, p1), p2), max(max(p3, p4), a[15]));
 }
 
 template <int P, int NSTEP, int BCR = 0>
@@ -703,6 +723,7 @@ struct TopkSmem {
     __align__(16) float norm[2][S::BC];
     __align__(16) int32_t pid[2][S::BC];
     int32_t sexp[2][P == SG_PREC_FP8 ? S::BC : 1];
+    int32_t par[2][P == SG_PREC_I8 ? S::BC : 1];   // INT8 L2: parity of ||c'||^2
     uint64_t buf[NQ * CBQ];
 };
 
@@ -805,7 +826,13 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
             }
         }
         if (tid < BC) {
-            sm.norm[buf][tid] = pre_norm[r];
+            if constexpr (P == SG_PREC_I8) {
+                const int32_t e = __builtin_bit_cast(int32_t, pre_norm[r]);
+                sm.norm[buf][tid] = __builtin_bit_cast(float, e >> 1);
+                sm.par[buf][tid] = e & 1;
+            } else {
+                sm.norm[buf][tid] = pre_norm[r];
+            }
             sm.pid[buf][tid] = pre_pid[r];
             if constexpr (P == SG_PREC_FP8) sm.sexp[buf][tid] = pre_sexp[r];
         }
@@ -820,7 +847,18 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
     auto compute = [&](Acc (&acc)[QB], int buf, int sub) {
         const uint8_t* arow = &sm.tile[buf][(sub * 32 + ql) * RS + h * (RB / 2)];
         if constexpr (P == SG_PREC_I8) {
-            for (int b = 0; b < QB; ++b) acc[b] = mfma_tile_i8<NSTEP, GMAX>(arow, qf[b]);
+            // the INT8 starts are int32 words in the same LDS array (read as
+            // integers: a bit cast of a vector element is not used here)
+            intx4 iv[4];
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+                iv[g] = *reinterpret_cast<const intx4*>(&sm.norm[buf][sub * 32 + g * 8 + h * 4]);
+#pragma unroll
+            for (int b = 0; b < QB; ++b) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) acc[b][i] = iv[i >> 2][i & 3];
+            }
+            for (int b = 0; b < QB; ++b) acc[b] = mfma_tile_i8<NSTEP, GMAX>(arow, qf[b], acc[b]);
         } else {
             floatx4 nv[4];
             starts(nv, buf, sub);
@@ -840,11 +878,22 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
     // the next subtile's MFMAs have been issued)
     auto select = [&](Acc (&acc)[QB], int buf, int sub, int64_t cb, const int32_t* tp) {
         if constexpr (P == SG_PREC_I8) {
-            floatx4 nv[4];
-            starts(nv, buf, sub);
+            // reject the subtile when even the bound -2 max(acc) (IP: -max)
+            // of every lane exceeds its threshold; else form exact keys
+            const int qm = (int)A.qmul;
+            bool any = false;
+#pragma unroll
+            for (int b = 0; b < QB; ++b) any |= (float)(qm * max16(acc[b])) <= sel.thr[b];
+            if (!__builtin_amdgcn_ballot_w64(any)) return;
+            intx4 par[4] = {};
+            if (qm == -2) {
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+                    par[g] = *reinterpret_cast<const intx4*>(&sm.par[buf][sub * 32 + g * 8 + h * 4]);
+            }
             floatx16 kf[QB];
 #pragma unroll
-            for (int b = 0; b < QB; ++b) kf[b] = i8_keys(acc[b], nv, A.qmul);
+            for (int b = 0; b < QB; ++b) kf[b] = i8_keys(acc[b], par, qm);
             sel.admit(kf, cb, tp);
         } else {
             sel.admit(acc, cb, tp);
@@ -1094,9 +1143,16 @@ __device__ void nearest_block(int64_t blk, const uint8_t* __restrict__ ops, cons
         __syncthreads();
         floatx16 acc;
         if constexpr (P == SG_PREC_I8) {
-            const intx16 ai = mfma_tile_i8<NSTEP>(&tile[ql * RS + h * (RB / 2)], qf);
+            intx16 ai;
+            intx4 par[4];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) acc[i] = __builtin_fmaf(qmul, (float)ai[i], norm[out_row(i, l)]);
+            for (int i = 0; i < 16; ++i) {
+                const int32_t e = __builtin_bit_cast(int32_t, norm[out_row(i, l)]);
+                ai[i] = e >> 1;
+                par[i >> 2][i & 3] = e & 1;
+            }
+            ai = mfma_tile_i8<NSTEP>(&tile[ql * RS + h * (RB / 2)], qf, ai);
+            acc = i8_keys(ai, par, (int)qmul);
         } else {
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[i] = norm[out_row(i, l)];

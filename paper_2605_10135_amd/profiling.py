@@ -174,7 +174,7 @@ def _pmc_rows(path: str, kernel: str) -> dict:
     return acc
 
 
-CUS, SIMDS_PER_CU = 256, 4
+CUS, SIMDS_PER_CU, XCDS = 256, 4, 8
 
 
 def counters(out: str, kernel: str, flops: str, command: str, *pmc_csvs: str) -> None:
@@ -195,11 +195,16 @@ def counters(out: str, kernel: str, flops: str, command: str, *pmc_csvs: str) ->
     lines += ["", "Derived:", ""]
     mfma_insts = sum(v for k, v in means.items() if k.startswith("SQ_INSTS_VALU_MFMA_MOPS"))
     if "SQ_VALU_MFMA_BUSY_CYCLES" in means and "GRBM_GUI_ACTIVE" in means:
-        simd_cycles = means["GRBM_GUI_ACTIVE"] * CUS * SIMDS_PER_CU
-        lines.append("* MFMA busy / SIMD cycles (GRBM_GUI_ACTIVE x %d CUs x %d SIMDs): %.3f"
+        # GRBM_GUI_ACTIVE is summed over the XCDs: per-XCD cycles x CUs x SIMDs
+        cycles = means["GRBM_GUI_ACTIVE"] / XCDS
+        simd_cycles = cycles * CUS * SIMDS_PER_CU
+        lines.append("* GPU cycles per dispatch (GRBM_GUI_ACTIVE / %d XCDs): %.4g" % (XCDS, cycles))
+        lines.append("* MFMA busy share of the SIMD cycles (%d CUs x %d SIMDs): %.3f"
                      % (CUS, SIMDS_PER_CU, means["SQ_VALU_MFMA_BUSY_CYCLES"] / simd_cycles))
-        lines.append("* MFMA busy / CU cycles (GRBM_GUI_ACTIVE x %d CUs): %.3f"
-                     % (CUS, means["SQ_VALU_MFMA_BUSY_CYCLES"] / (means["GRBM_GUI_ACTIVE"] * CUS)))
+        if "SQ_INSTS_VALU" in means:
+            valu = means["SQ_INSTS_VALU"] - means.get("SQ_INSTS_MFMA", 0.0)
+            lines.append("* VALU issue share of the SIMD cycles (4 cycles per wave64 instruction, MFMA "
+                         "excluded): %.3f" % (4.0 * valu / simd_cycles))
     if "SQ_INSTS_MFMA" in means and means["SQ_INSTS_MFMA"] > 0:
         m = means["SQ_INSTS_MFMA"]
         for k in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS"):
