@@ -196,7 +196,11 @@ def main():
     tuned = {f: {b_: (sg.sg_knn_autotune(shards[i_], K, "l2", f) if not args.no_autotune else (0, []))
                  for b_, i_ in sorted(buckets.items())}
              for f in forms}
-    log("autotune %s" % tuned)
+    # the batched pass itself is tuned per form (the persistent launch over all
+    # shards can favour another shape than one launch of the largest shard)
+    btuned = {f: (sg.sg_knn_graph_batched_autotune(Xcat, offs, K, R, "l2", f) if not args.no_autotune else (0, []))
+              for f in forms}
+    log("autotune %s batched %s" % (tuned, btuned))
     res = {}
     graph_of = {}
     if args.force_variant is not None:
@@ -208,7 +212,7 @@ def main():
         ach = flops * args.steps / (kms / 1e3) / 1e12
         res[form] = dict(sec=sec, kernel_ms_total=kms, launches=launches, kernel_ms_avg=kavg,
                          tflops=ach, vps=N / sec, shard_rows_ps=total / sec,
-                         variant=tuned[form][int(max(sizes)).bit_length() - 1][0])
+                         variant=btuned[form][0])
         graph_of[form] = (mg.clone(), deg.clone(), knn_all.clone(), graphs.clone())
         log("%s: %.3f s/step, dist kernel %d launches, %.3f ms avg, %.1f TFLOP/s" % (
             form, sec, launches, kavg, ach))
@@ -399,6 +403,7 @@ def main():
         "exact_forms_identical": same_exact,
         "autotune": {f: {"2^%d" % b_: {"chosen": c, "variant_ms": t} for b_, (c, t) in v.items()}
                      for f, v in tuned.items()},
+        "autotune_batched": {f: {"chosen": c, "variant_ms": t} for f, (c, t) in btuned.items()},
         "partition_s": t_part,
     }
     if "fp32" in res and prec != "fp32":
@@ -491,7 +496,6 @@ def run_precision(args):
     total = int(sizes.sum())
     soffs = [0] + np.cumsum(sizes).tolist()
     graphs = torch.empty((total, R), dtype=torch.int32, device=dev)
-    nbrs = [torch.empty((int(n), K), dtype=torch.int32, device=dev) for n in sizes]
     mem_share = mem[:offs[share]]
     flops = float(sum(2.0 * d * float(n) * float(n) for n in sizes))
 
@@ -499,33 +503,17 @@ def run_precision(args):
     knn_share = torch.empty((total, K), dtype=torch.int32, device=dev)
 
     def make_step(prec, rerank):
-        if rerank <= 128:
-            # all shards of the share in one batched pass (re-rank included)
-            def step():
-                sg.sg_knn_graph_batched(Xshare, soffs, K, R, "ip", prec, out=(graphs, knn_share), rerank=rerank)
-                return sg.sg_merge(soffs, mem_share, graphs, R, N, omega * R)
-            return step
-
-        # a re-rank wider than the batched pass takes: one launch per shard
+        # all shards of the share in one batched pass (re-rank included)
         def step():
-            for s_, Xs in enumerate(shards):
-                sg.sg_knn_graph(Xs, K, "ip", prec, rerank=rerank, out=(nbrs[s_], None))
-                sg.sg_prune(nbrs[s_], R, out=graphs[soffs[s_]:soffs[s_ + 1]])
+            sg.sg_knn_graph_batched(Xshare, soffs, K, R, "ip", prec, out=(graphs, knn_share), rerank=rerank)
             return sg.sg_merge(soffs, mem_share, graphs, R, N, omega * R)
         return step
 
-    # launch-shape autotuning per form (outside the timed region), on the largest
-    # shard of each power-of-two size bucket present
-    buckets = {}
-    for i_, n_ in enumerate(sizes):
-        b_ = int(n_).bit_length() - 1
-        if b_ not in buckets or n_ > sizes[buckets[b_]]:
-            buckets[b_] = i_
     # reduced forms: (name, precision, re-rank width); FP8 also with a wider
-    # candidate list, which costs selection work but wins back recall
+    # candidate list, which costs selection work but wins back recall.  Each
+    # form's batched pass is tuned before it is timed.
     reduced = (("bf16", "bf16", C), ("fp8", "fp8", C), ("fp8_c256", "fp8", 2 * C))
-    tuned = {f: {"2^%d" % b_: sg.sg_knn_autotune(shards[i_], K, "ip", prec_, rerank=rr_)
-                 for b_, i_ in sorted(buckets.items())}
+    tuned = {f: sg.sg_knn_graph_batched_autotune(Xshare, soffs, K, R, "ip", prec_, rerank=rr_)
              for f, prec_, rr_ in reduced}
     log("autotune %s" % tuned)
 
@@ -536,8 +524,7 @@ def run_precision(args):
         ach = flops * steps / (kms / 1e3) / 1e12
         res[form] = dict(sec=sec, vps=N * (share / S) / sec, shard_rows_ps=total / sec, tflops=ach,
                          frac=ach / PEAK[prec], kernel_ms_avg=kms / max(launches, 1), prec=prec, rerank=rr)
-        lists[form] = ([knn_share[soffs[i]:soffs[i] + 2000].clone() for i in range(2)] if rr <= 128
-                       else [nb[:2000].clone() for nb in nbrs[:2]])
+        lists[form] = [knn_share[soffs[i]:soffs[i] + 2000].clone() for i in range(2)]
         log("%s: %.3f s/step, %.1f TFLOP/s" % (form, sec, ach))
 
     # recall@64 of the reduced forms against the plain FP32 build (same shards, sampled rows)
@@ -715,8 +702,7 @@ def _selectivity(args, torch, sg, synthdata, dev, n_comp):
             b_ = int(n_).bit_length() - 1
             if b_ not in buckets or n_ > sizes[buckets[b_]]:
                 buckets[b_] = i_
-        for b_, i_ in buckets.items():
-            sg.sg_knn_autotune(Xd[mem[offs[i_]:offs[i_ + 1]].long()].contiguous(), K, "l2", prec)
+        sg.sg_knn_graph_batched_autotune(Xd[mem.long()].contiguous(), offs, K, R, "l2", prec)
         sec, kms, mg, deg, _, _ = _exact_build(torch, sg, Xd, mem, offs, K, R, N, prec, args.steps, args.warmup)
         search = search_study(torch, sg, Xd, Qd, mg, deg, Ls=(64, 128))
         out[name] = {"epsilon": eps, "tau0": tau0, "shard_rows": int(offs[-1]),
@@ -752,8 +738,7 @@ def run_degrees(args):
     for K, R in ((64, 32), (128, 64), (256, 128)):
         res = {}
         for prec in ("f16", "i8"):
-            sg.sg_knn_autotune(Xd[mem[offs[int(np.argmax(sizes))]:offs[int(np.argmax(sizes)) + 1]].long()]
-                               .contiguous(), K, "l2", prec)
+            sg.sg_knn_graph_batched_autotune(Xd[mem.long()].contiguous(), offs, K, R, "l2", prec)
             sec, kms, mg, deg, knn_all, graphs = _exact_build(torch, sg, Xd, mem, offs, K, R, N, prec,
                                                               args.steps, args.warmup)
             res[prec] = (sec, kms)
@@ -841,6 +826,8 @@ def run_batched(args):
     knn = torch.empty((total, K), dtype=torch.int32, device=dev)
     stream = torch.cuda.Stream()
     plan = sg.BatchPlan()
+    tuned = sg.sg_knn_graph_batched_autotune(X, offs, K, R, "ip", "f16")
+    log("autotune (batched pass) %s" % (tuned,))
 
     def batched_step():
         with torch.cuda.stream(stream):

@@ -267,6 +267,21 @@ sg_status sg_knn_graph_batched(const void* X, sg_dtype dtype, int32_t d, int64_t
                                void* ws, size_t ws_bytes, void* stream, sg_batch_plan** plan);
 void sg_batch_plan_destroy(sg_batch_plan* plan);
 
+/* sg_knn_graph_batched_autotune -- times the whole batched pass (arguments as
+ * sg_knn_graph_batched without a plan; the outputs are written) once per
+ * launch shape of the distance kernel and records the fastest for batched
+ * calls of this precision, padded row length, selection width and
+ * power-of-two bucket of the largest shard; without such a record a batched
+ * call takes the shape recorded by sg_knn_autotune for its largest shard.  A
+ * persistent launch over many shards can favour another shape than one
+ * launch of its largest shard.  Synchronises `stream`.  chosen / times_ms as
+ * sg_knn_autotune. */
+sg_status sg_knn_graph_batched_autotune(const void* X, sg_dtype dtype, int32_t d, int64_t ld,
+                                        const int64_t* offsets_h, int32_t S, sg_metric metric, int32_t k,
+                                        int32_t R, sg_prec prec, int32_t rerank, int32_t* graphs, int32_t* knn,
+                                        void* ws, size_t ws_bytes, void* stream, int32_t* chosen, float* times_ms,
+                                        int32_t max_times);
+
 /* ------------------------------------------------------------------------
  * Distance-kernel variants and autotuning
  *

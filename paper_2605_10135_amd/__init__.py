@@ -80,6 +80,8 @@ _SIGS = {
     "sg_knn_graph_batched": (i32, [vp, i32, i32, i64, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, sz, vp,
                                    C.POINTER(C.c_void_p)]),
     "sg_batch_plan_destroy": (None, [vp]),
+    "sg_knn_graph_batched_autotune": (i32, [vp, i32, i32, i64, vp, i32, i32, i32, i32, i32, i32, vp, vp, vp, sz,
+                                            vp, C.POINTER(C.c_int32), vp, i32]),
     "sg_knn_graph_learned_workspace_size": (i32, [i64, i32, i32, psz]),
     "sg_knn_graph_learned": (i32, [vp, i32, i32, i64, i32, vp, i64, i32, i64, i32, i32, vp, vp, vp, sz, vp]),
     "sg_mlp_workspace_size": (i32, [i32, i32, i32, i32, psz]),
@@ -282,6 +284,29 @@ def sg_knn_graph_batched(X, offsets, k, R, metric="l2", prec="fp32", knn=True, o
                                                           _ptr(graphs),
                                                           _ptr(kn), _ptr(ws), ws.numel(), _stream(stream), pp))
     return graphs, kn
+
+
+def sg_knn_graph_batched_autotune(X, offsets, k, R, metric="l2", prec="fp32", rerank=0, stream=None):
+    """Time the batched pass per launch shape and record the fastest for
+    batched calls of this shape: (chosen index, per-shape milliseconds)."""
+    L = lib()
+    dt, n, d, ld = _rows(X)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    S = off.size - 1
+    offp = off.ctypes.data_as(C.c_void_p)
+    m, p = METRICS[metric], PRECS[prec]
+    nbytes = _size(L.sg_knn_graph_batched_workspace_size, offp, S, d, k, R, p, rerank)
+    ws = _ws.get(nbytes, X.device, "batched")
+    graphs = torch.empty((int(off[-1]), R), dtype=torch.int32, device=X.device)
+    kn = torch.empty((int(off[-1]), k), dtype=torch.int32, device=X.device)
+    nv = sg_knn_variant_count(d, rerank if rerank > k else k, prec)
+    times = (C.c_float * max(nv, 1))()
+    chosen = C.c_int32(-1)
+    _check("sg_knn_graph_batched_autotune",
+           L.sg_knn_graph_batched_autotune(_ptr(X), dt, d, ld, offp, S, m, k, R, p, rerank, _ptr(graphs), _ptr(kn),
+                                           _ptr(ws), ws.numel(), _stream(stream), C.byref(chosen),
+                                           C.cast(times, C.c_void_p), nv))
+    return chosen.value, list(times)[:nv]
 
 
 def sg_knn_rows(X, rows, k, metric="l2", prec="fp32", rerank=0, stream=None):

@@ -130,7 +130,18 @@ Plan make_plan(const int64_t* off, int S, int d, int k, int R, int prec, int rer
     p.sh.piv0[S] = piv;
     p.sh.ppad0[S] = ppad;
     p.n_all = off[S];
-    const int idx = chosen_variant(prec, d, p.ksel, p.n_max, (int)kv.size());
+    // the launch shape: a forced one, else the choice recorded for batched
+    // passes of this shape (sg_knn_graph_batched_autotune), else the choice
+    // recorded for single-shard builds of the largest shard's size
+    int idx = -1;
+    if (g_force_variant >= 0) {
+        idx = g_force_variant < (int)kv.size() ? g_force_variant : 0;
+    } else {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune.find(batched_tune_key(prec, d, p.ksel, p.n_max));
+        if (it != g_tune.end() && it->second < (int)kv.size()) idx = it->second;
+    }
+    if (idx < 0) idx = chosen_variant(prec, d, p.ksel, p.n_max, (int)kv.size());
     p.kern = kv[idx];
     p.DP = p.kern.DP;
     p.eb = elem_bytes(prec);
@@ -350,6 +361,62 @@ extern "C" sg_status sg_knn_graph_batched(const void* X, sg_dtype dtype, int32_t
         np->device = dev;
         *plan = np;
         SG_HIP(hipGraphLaunch(exec, s));
+    });
+}
+
+extern "C" sg_status sg_knn_graph_batched_autotune(const void* X, sg_dtype dtype, int32_t d, int64_t ld,
+                                                   const int64_t* offsets_h, int32_t S, sg_metric metric, int32_t k,
+                                                   int32_t R, sg_prec prec, int32_t rerank, int32_t* graphs,
+                                                   int32_t* knn, void* ws, size_t ws_bytes, void* stream,
+                                                   int32_t* chosen, float* times_ms, int32_t max_times) {
+    return guarded([&] {
+        const batch::Plan p0 = batch::make_plan(offsets_h, S, d, k, R, prec, rerank);
+        knn::check_args(X, dtype, p0.n_all, d, ld, metric, k, prec, p0.rerank);
+        SG_REQUIRE(graphs != nullptr, "graphs is NULL");
+        SG_REQUIRE(p0.n_all > 0, "autotuning needs rows");
+        SG_REQUIRE(max_times >= 0 && (max_times == 0 || times_ms != nullptr), "bad times_ms / max_times");
+        if (ws == nullptr || ws_bytes < p0.total) {
+            set_error("sg_knn_graph_batched_autotune: workspace too small (need " + std::to_string(p0.total) +
+                      " bytes)");
+            throw Fail{SG_ERR_WORKSPACE};
+        }
+        std::vector<batch::BKern> kv;
+        batch::batched_shapes(prec, d, p0.ksel, kv);
+        const int nv = (int)kv.size();
+        hipStream_t s = as_stream(stream);
+        const int saved = knn::g_force_variant;
+        std::vector<float> ms(nv, 0.f);
+        hipEvent_t e0, e1;
+        SG_HIP(hipEventCreate(&e0));
+        SG_HIP(hipEventCreate(&e1));
+        struct Restore {
+            int v;
+            hipEvent_t a, b;
+            ~Restore() {
+                knn::g_force_variant = v;
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+            }
+        } restore{saved, e0, e1};
+        for (int v = 0; v < nv; ++v) {
+            knn::g_force_variant = v;
+            const batch::Plan pv = batch::make_plan(offsets_h, S, d, k, R, prec, rerank);
+            batch::enqueue(pv, X, dtype, d, ld, metric, k, R, prec, graphs, knn, ws, s, false);
+            SG_HIP(hipEventRecord(e0, s));
+            batch::enqueue(pv, X, dtype, d, ld, metric, k, R, prec, graphs, knn, ws, s, false);
+            SG_HIP(hipEventRecord(e1, s));
+            SG_HIP(hipEventSynchronize(e1));
+            SG_HIP(hipEventElapsedTime(&ms[v], e0, e1));
+        }
+        int best = 0;
+        for (int v = 1; v < nv; ++v)
+            if (ms[v] < ms[best]) best = v;
+        {
+            std::lock_guard<std::mutex> g(knn::g_tune_mu);
+            knn::g_tune[knn::batched_tune_key(prec, d, p0.ksel, p0.n_max)] = best;
+        }
+        if (chosen) *chosen = best;
+        for (int v = 0; v < nv && v < max_times; ++v) times_ms[v] = ms[v];
     });
 }
 

@@ -1592,6 +1592,13 @@ inline TuneKey tune_key(int prec, int d, int ksel, int64_t n) {
     return TuneKey{prec, padded_d(prec, d), ksel, nlog_of(n)};
 }
 
+// The record of a batched pass whose largest shard has n_max rows (kept apart
+// from the single-shard records: the persistent launch of many shards can
+// prefer another shape than one launch of its largest shard).
+inline TuneKey batched_tune_key(int prec, int d, int ksel, int64_t n_max) {
+    return TuneKey{prec, padded_d(prec, d), ksel, 64 + nlog_of(n_max)};
+}
+
 // Index into the shape table for a call of this shape (count entries).
 int chosen_variant(int prec, int d, int ksel, int64_t n, int count);
 

@@ -157,3 +157,17 @@ def test_batched_high_degree_equals_per_shard_and_oracle(k, R):
         onbr, _ = oracle.knn(oracle.widen(X[a:b]), k)
         np.testing.assert_array_equal(knn_h[a:b], onbr, err_msg="shard %d" % s)
         np.testing.assert_array_equal(g_h[a:b], oracle.prune(onbr, R), err_msg="shard %d" % s)
+
+
+def test_batched_autotune_records_a_valid_choice_and_keeps_results():
+    sizes = [3000, 700, 4500, 1200]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    X = synthdata.sift_like_u8(n=int(offs[-1]), d=128, seed=37, n_comp=50)
+    Xg = torch.from_numpy(X).to(DEV)
+    ref_g, ref_k = sg.sg_knn_graph_batched(Xg, offs, 32, 16, "l2", "i8")
+    chosen, times = sg.sg_knn_graph_batched_autotune(Xg, offs, 32, 16, "l2", "i8")
+    assert 0 <= chosen < len(times) == sg.sg_knn_variant_count(128, 32, "i8")
+    assert all(t > 0 for t in times) and times[chosen] == min(times)
+    g, k = sg.sg_knn_graph_batched(Xg, offs, 32, 16, "l2", "i8")
+    torch.cuda.synchronize()
+    assert torch.equal(g, ref_g) and torch.equal(k, ref_k)
