@@ -41,15 +41,22 @@ constexpr int WAVES = 4;
 constexpr uint64_t EMPTY_SLOT = ~0ull;
 
 // The low 24 bits of the id with the high bits folded in; the two hashes are
-// bits of two 24-bit products (one full-rate multiply each).
+// bits of two 24-bit products (v_mul_u32_u24, full rate: a plain 32-bit
+// product would take the quarter-rate v_mul_lo_u32 although both factors fit
+// 24 bits; the low 32 bits of the product are the same).
 __device__ inline uint32_t mix_id(int32_t z) {
     const uint32_t u = (uint32_t)z;
     return (u ^ (u >> 15)) & 0xFFFFFFu;
 }
+__device__ inline uint32_t mul_u24(uint32_t c, uint32_t m) {
+    uint32_t r;
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "s"(c), "v"(m));
+    return r;
+}
 template <int CT>
-__device__ inline uint32_t cuckoo_h0(uint32_t m) { return ((m * 0x9E3779u) >> 8) & (CT - 1); }
+__device__ inline uint32_t cuckoo_h0(uint32_t m) { return (mul_u24(0x9E3779u, m) >> 8) & (CT - 1); }
 template <int CT>
-__device__ inline uint32_t cuckoo_h1(uint32_t m) { return ((m * 0x85EBCBu) >> 16) & (CT - 1); }
+__device__ inline uint32_t cuckoo_h1(uint32_t m) { return (mul_u24(0x85EBCBu, m) >> 16) & (CT - 1); }
 
 // Flags *bad unless order[0..n) is a permutation of 0..n-1: every entry in
 // range and no row seen twice (n entries, so none is then missing).  seen
