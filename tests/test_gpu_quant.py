@@ -16,7 +16,7 @@ import torch
 import oracle
 import paper_2605_10135_amd as sg
 import synthdata
-from parity import check_rows, gamma
+from parity import check_rows, fp8_group_truncation, gamma
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -106,16 +106,29 @@ def test_exact_types_on_u8(prec):
     np.testing.assert_array_equal(sq.cpu().numpy().astype(np.float64), (X.astype(np.float64) ** 2).sum(1))
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp8"])
-def test_reduced_key_knn_equals_exact_knn_of_dequantised_rows(prec):
+def _wide_range_rows(n, d, seed):
+    # a mixture whose columns are scaled by e^U(-4, 4): products within a
+    # group of 8 elements then span many binades
+    rng = np.random.default_rng(seed)
+    return (synthdata.mixture(n, d, 10, 0.5, seed=seed) * np.exp(rng.uniform(-4, 4, (1, d)))).astype(np.float32)
+
+
+@pytest.mark.parametrize("prec,family,d", [("bf16", "mixture", 64), ("fp8", "mixture", 64),
+                                           ("fp8", "wide", 80), ("fp8", "deep", 96), ("fp8", "laion", 768)])
+def test_reduced_key_knn_equals_exact_knn_of_dequantised_rows(prec, family, d):
     """Without a re-rank, the BF16 / FP8 distance kernel ranks the rows it
     quantised: its lists must be the exact kNN of the dequantised rows under
-    the FP32 rounding-bound rule (products of BF16 or scaled FP8 values are
-    exact in FP32, so only the accumulation rounds)."""
-    if prec == "fp8":
-        pytest.skip("the FP8 MFMA's block accumulation is not bounded by FP32 rounding alone; "
-                    "its bound is being measured before this case is enabled")
-    X = synthdata.mixture(2500, 64, 20, 0.3, seed=31)
+    the rounding-bound rule.  Products of BF16 or scaled FP8 values are exact;
+    BF16 sums round as FP32 does, the FP8 instruction adds its in-group
+    truncation (the rule's FP8 term)."""
+    if family == "mixture":
+        X = synthdata.mixture(2500, d, 20, 0.3, seed=31)
+    elif family == "wide":
+        X = _wide_range_rows(2500, d, seed=3)
+    elif family == "deep":
+        X = synthdata.deep_like_unit(3000, d, seed=23)
+    else:
+        X = synthdata.laion_like_f16(2000, d, seed=5, n_comp=40).astype(np.float32)
     K = 24
     nbr, dist = sg.sg_knn_graph(torch.from_numpy(X).to(DEV), K, "l2", prec)
     torch.cuda.synchronize()
@@ -125,5 +138,51 @@ def test_reduced_key_knn_equals_exact_knn_of_dequantised_rows(prec):
         oq, os_ = oracle.quant_rows_fp8(X)
         Xq = oracle.from_fp8(oq) * os_[:, None].astype(np.float64)
     onbr, odist = oracle.knn(Xq, K)
-    bad = check_rows(Xq, np.arange(len(X)), nbr.cpu().numpy(), dist.cpu().numpy(), onbr, odist)
+    bad = check_rows(Xq, np.arange(len(X)), nbr.cpu().numpy(), dist.cpu().numpy(), onbr, odist,
+                     fp8=prec == "fp8")
     assert not bad, bad[:5]
+
+
+# (row x, row y, returned distance minus the exact one): rows whose FP8 codes
+# are exact (scale 2^-8, every value a code), so that the only departure from
+# the exact distance is the instruction's in-group truncation of -2 x.y
+_FP8_GROUP_CASES = [
+    # -3 * 2^-13 shares a group with -2: grid 2^-12, truncated toward zero to -2^-12
+    ({0: 1.0, 1: 1.5 * 2.0 ** -4}, {0: 1.0, 1: 2.0 ** -9}, 2.0 ** -13),
+    # the same products in different groups of 8: each exact
+    ({0: 1.0, 8: 1.5 * 2.0 ** -4}, {0: 1.0, 8: 2.0 ** -9}, 0.0),
+    # a positive -2 x_t y_t truncates toward zero as well: the key shrinks
+    ({0: 1.0, 1: -1.5 * 2.0 ** -4}, {0: 1.0, 1: 2.0 ** -9}, -(2.0 ** -13)),
+    # -2^-19 is below the grid: lost whole
+    ({0: 1.0, 7: 2.0 ** -11}, {0: 1.0, 7: 2.0 ** -9}, 2.0 ** -19),
+    # the group boundary sits between elements 7 and 8 of the row
+    ({0: 1.0, 8: 2.0 ** -11}, {0: 1.0, 8: 2.0 ** -9}, 0.0),
+    # a group in the row's second half (element 40 is on the other lane half)
+    ({40: 1.0, 47: 1.5 * 2.0 ** -4}, {40: 1.0, 47: 2.0 ** -9}, 2.0 ** -13),
+]
+
+
+@pytest.mark.parametrize("case", range(len(_FP8_GROUP_CASES)))
+def test_fp8_instruction_truncates_within_groups_of_eight(case):
+    """Pins the FP8 term of the parity rule through the product path: on a
+    pair of rows the returned distance departs from the exact one by exactly
+    the truncation the stated instruction model predicts, and not at all when
+    the products fall in different groups."""
+    xs, ys, delta = _FP8_GROUP_CASES[case]
+    d = 64
+    X = np.zeros((2, d), np.float32)
+    for t, v in xs.items():
+        X[0, t] = v
+    for t, v in ys.items():
+        X[1, t] = v
+    oq, os_ = oracle.quant_rows_fp8(X)
+    Xq = oracle.from_fp8(oq) * os_[:, None].astype(np.float64)
+    assert np.array_equal(Xq, X.astype(np.float64)) and list(os_) == [2.0 ** -8, 2.0 ** -8]
+    exact = float(((Xq[0] - Xq[1]) ** 2).sum())
+    nbr, dist = sg.sg_knn_graph(torch.from_numpy(X).to(DEV), 1, "l2", "fp8")
+    torch.cuda.synchronize()
+    assert nbr.cpu().numpy().ravel().tolist() == [1, 0]
+    got = dist.cpu().numpy().astype(np.float64).ravel()
+    assert got.tolist() == [exact + delta, exact + delta], (got - exact, delta)
+    # the rule's FP8 term covers the departure
+    assert abs(delta) <= fp8_group_truncation(Xq, np.array([0]), np.array([[1]]))[0, 0]
