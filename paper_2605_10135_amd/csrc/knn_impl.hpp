@@ -553,11 +553,11 @@ struct Selector {
     // <= the threshold, one accumulator element at a time: from the element's
     // ballot the two lanes of a query see each other's hit, so they write
     // their keys at known slots (no atomics) and both keep the query's buffer
-    // fill in a register.  The 16 elements go in chunks of CBQ/2 (one chunk
-    // for CBQ = 32, two for CBQ = 16): round 1 stops at the first element some
+    // fill in a register.  The 16 elements go in chunks of E (one chunk of 16
+    // for CBQ = 32, two of 8 for 16 <= CBQ < 32): round 1 stops at the first element some
     // buffer cannot take; then every query whose buffer could not take two
     // keys per remaining element of the chunk is merged, and round 2 finishes
-    // the chunk without checks (an emptied buffer holds the 2 x CBQ/2 keys a
+    // the chunk without checks (an emptied buffer holds the 2E <= CBQ keys a
     // chunk can add).  A merged query's lowered threshold takes effect at the
     // next chunk.  Admission is exact in any
     // candidate order: a candidate whose distance exceeds the K-th distance of
@@ -565,7 +565,7 @@ struct Selector {
     // admitted and ranked by (distance, id) in the merge.  The query itself
     // and padding rows are NaN, which no comparison admits.
     __device__ void admit(floatx16 (&acc)[QB], int64_t cbase, const int32_t* tpid) {
-        static_assert(CBQ == 16 || CBQ == 32, "a chunk of CBQ/2 elements must fit an emptied buffer");
+        static_assert(CBQ >= 16 && CBQ <= 32, "a chunk of E elements must fit an emptied buffer");
         const int l = lane_id();
         const int ql = l & 31;
         const int h = l >> 5;
@@ -596,8 +596,8 @@ struct Selector {
 #pragma unroll
             for (int i = 0; i < 16; ++i) ids[i] = (int32_t)(cbase + out_row(i, l));
         }
-        // chunks of E elements: a chunk adds at most 2E = CBQ keys per query
-        constexpr int E = CBQ / 2;
+        // chunks of E elements: a chunk adds at most 2E <= CBQ keys per query
+        constexpr int E = CBQ == 32 ? 16 : 8;
 #pragma unroll
         for (int b = 0; b < QB; ++b) {
             float t = thr[b];
@@ -762,7 +762,7 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
     constexpr int NQ = 32 * QB * WAVES;
     constexpr int CHUNKS = BC * RB / 16;                        // 16-byte chunks per tile
     constexpr int CPT = (CHUNKS + NT - 1) / NT;                 // chunks per thread
-    constexpr int GMAX = CBQ == 16 ? 4 : 8;                     // A-fragment group (registers)
+    constexpr int GMAX = CBQ < 32 ? 4 : 8;                      // A-fragment group (registers)
 
     const int tid = threadIdx.x;
     const int l = tid & 63;
@@ -794,10 +794,11 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
     auto tile_row = [&](int t) { return order.tile(t) * BC; };
 
     // tile staging: global -> registers -> LDS (two buffers).  4-wave shapes
-    // with 32-entry buffers keep two register sets, so that a tile's loads are
-    // issued two tiles before it is committed (their tiles are short); the
+    // with 32-entry buffers, and those with more than 16 whose tile is one
+    // 16-byte load per thread, keep two register sets, so that a tile's loads
+    // are issued two tiles before it is committed (their tiles are short); the
     // others, whose registers are fuller, keep one (loads one tile ahead).
-    constexpr int DEPTH = WAVES == 4 && CBQ == 32 ? 2 : 1;
+    constexpr int DEPTH = WAVES == 4 && (CBQ == 32 || (CBQ > 16 && CPT == 1)) ? 2 : 1;
     intx4 pre[DEPTH][CPT];
     float pre_norm[DEPTH] = {};
     int32_t pre_pid[DEPTH] = {}, pre_sexp[DEPTH] = {};
@@ -959,10 +960,25 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
 }
 
 // Workgroups per CU a launch shape aims for: 32-row tiles keep the LDS of a
-// 4-wave workgroup near 50 KB, so three fit (12 waves; at most 168 VGPRs);
-// with 16-entry buffers it is 34 KB and four fit (16 waves; 128 VGPRs).
+// 4-wave workgroup with 32-entry buffers near 50 KB, so three fit (12 waves;
+// at most 168 VGPRs); with shorter buffers (cbq_four_wgs) four fit (16 waves;
+// 128 VGPRs).
 constexpr int min_waves_per_simd(int waves, int bcr, int cbq = CB) {
-    return waves == 4 && bcr == 32 ? (cbq == 16 ? 4 : 3) : 1;
+    return waves == 4 && bcr == 32 ? (cbq < 32 ? 4 : 3) : 1;
+}
+
+// Buffer entries per query of the 4-wave, 32-row-tile shape that runs four
+// workgroups per CU: the longest of 28, 24, 20 whose LDS lets four share a
+// CU's 160 KB, else 16.  Longer buffers mean fewer merges (for 128-byte rows
+// 28 entries took the INT8 batched build from 59.8 to 53.9 ms against the
+// 32-entry, three-workgroup shape).
+template <int P, int NSTEP>
+constexpr int cbq_four_wgs() {
+    constexpr size_t cap = 160 * 1024 / 4;
+    return sizeof(TopkSmem<P, NSTEP, 4, 1, 28, 32>) <= cap   ? 28
+           : sizeof(TopkSmem<P, NSTEP, 4, 1, 24, 32>) <= cap ? 24
+           : sizeof(TopkSmem<P, NSTEP, 4, 1, 20, 32>) <= cap ? 20
+                                                             : 16;
 }
 
 // One query block per workgroup (blockIdx.x).

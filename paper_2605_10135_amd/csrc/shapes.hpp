@@ -18,12 +18,12 @@ bool for_shapes_p(int d, M& m) {
         m.template add<PR, NS, 4, 1, CB, 64>();  \
         m.template add<PR, NS, 4, 1, CB, 32>();  \
     } while (0)
-// ... and, for short 16-bit / FP8 rows, 16-entry buffers with 32-row tiles
-// (four workgroups per CU)
-#define SG_FOUR(PR, NS, W0)                      \
-    do {                                         \
-        SG_THREE(PR, NS, W0);                    \
-        m.template add<PR, NS, 4, 1, 16, 32>();  \
+// ... and, for short rows, 32-row tiles with buffers short enough for four
+// workgroups per CU
+#define SG_FOUR(PR, NS, W0)                                         \
+    do {                                                            \
+        SG_THREE(PR, NS, W0);                                       \
+        m.template add<PR, NS, 4, 1, cbq_four_wgs<PR, NS>(), 32>(); \
     } while (0)
     if constexpr (PR == SG_PREC_FP32) {
         if (need <= 16) SG_THREE(SG_PREC_FP32, 16, TWAVES);
