@@ -512,6 +512,17 @@ template <int KSEL, int QB, int CBQ = CB>
 struct Selector {
     static_assert(CBQ <= 32, "a buffer is sorted inside one wave half");
     float thr[QB];
+    // INT8 keys only (qm_int = the key's factor on the accumulator, -2 or -1;
+    // 0 for other operands): the smallest subtile maximum of the accumulator
+    // that can still give a key <= thr, kept beside thr so that a subtile is
+    // rejected by one integer comparison
+    int32_t amin[QB];
+    int qm_int;
+    __device__ static int32_t i8_amin(float t, int qm) {
+        if (!(t < 3.0e38f)) return INT32_MIN;   // +inf: everything passes
+        // qm * M <= t  <=>  M >= ceil(t / qm) (t an exact integer below 2^24)
+        return (int32_t)ceilf(qm == -2 ? -0.5f * t : -t);
+    }
     int64_t qself[QB];
     int64_t qlo, qhi;  // wave-uniform range of the wave's query ids
     uint64_t* state;   // state row of the wave's first query
@@ -651,6 +662,7 @@ struct Selector {
                 }
             }
             thr[b] = t;
+            if (qm_int) amin[b] = i8_amin(t, qm_int);
             fill[b] = c;
         }
     }
@@ -784,9 +796,11 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
         q_scale[b] = 127;
         if constexpr (P == SG_PREC_FP8) q_scale[b] = 127 + A.qsexp[qg] + 1;
         sel.thr[b] = __builtin_inff();
+        sel.amin[b] = INT32_MIN;
         sel.fill[b] = 0;
         sel.qself[b] = qg < A.nq ? (A.qid ? A.qid[qg] : qg) : -1;
     }
+    sel.qm_int = P == SG_PREC_I8 ? (int)A.qmul : 0;
     sel.init_self_range();
 
     const int ntiles = (A.n + BC - 1) / BC;
@@ -880,11 +894,12 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
     auto select = [&](Acc (&acc)[QB], int buf, int sub, int64_t cb, const int32_t* tp) {
         if constexpr (P == SG_PREC_I8) {
             // reject the subtile when even the bound -2 max(acc) (IP: -max)
-            // of every lane exceeds its threshold; else form exact keys
+            // of every lane exceeds its threshold (max(acc) < amin); else
+            // form exact keys
             const int qm = (int)A.qmul;
             bool any = false;
 #pragma unroll
-            for (int b = 0; b < QB; ++b) any |= (float)(qm * max16(acc[b])) <= sel.thr[b];
+            for (int b = 0; b < QB; ++b) any |= max16(acc[b]) >= sel.amin[b];
             if (!__builtin_amdgcn_ballot_w64(any)) return;
             intx4 par[4] = {};
             if (qm == -2) {
@@ -1036,6 +1051,7 @@ __global__ __launch_bounds__(KS_WAVES * 64, 1) void dist_topk_kstream_kernel(Top
         sel.fill[0] = 0;
         sel.qself[0] = qg < nq ? (qid ? qid[qg] : qg) : -1;
     }
+    sel.qm_int = 0;
     sel.init_self_range();
 
     const int nch = DP / KS_DC;
