@@ -400,7 +400,8 @@ sg_status sg_prune_noalloc(const int32_t* knn, int64_t n, int32_t K, int32_t R, 
  * graphs holds shards 0..S-1's R-wide lists (local ids) back to back, shard
  * s's rows at [shard_offsets_h[s], shard_offsets_h[s+1]); member_ids maps a
  * local row of shard s to its global id (ascending within each shard, as
- * sg_partition writes it).  For a global id g present in shards s_1 < .. <
+ * sg_partition writes it; ids outside [0, n_global) are skipped, as are
+ * local ids outside their shard).  For a global id g present in shards s_1 < .. <
  * s_m with lists L_1..L_m translated to global ids:
  *   for pos = 0..R-1, for t = 1..m: append L_t[pos] if valid, not yet in the
  *   list and != g; stop at max_degree.

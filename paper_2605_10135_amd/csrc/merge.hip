@@ -10,7 +10,9 @@
 //  * merge_kernel: one wave per global id.  The lists of its m occurrences are
 //    read position-major (pos 0 of every occurrence, then pos 1, ...),
 //    translated to global ids and appended in that order without repeats or
-//    self, up to max_degree.
+//    self, up to max_degree.  Within a chunk of 64 entries the first
+//    occurrence of each id is found by a wave sort of (id, lane) keys; against
+//    the ids kept from earlier chunks by comparison.
 #include "common.hpp"
 
 namespace sg {
@@ -32,22 +34,22 @@ __global__ void count_kernel(const int32_t* __restrict__ member_ids, int64_t tot
 // rows [r0, r1) of one shard whose first row is r0
 __global__ void scatter_kernel(const int32_t* __restrict__ member_ids, int64_t r0, int64_t r1,
                                int64_t n_global, const int64_t* __restrict__ off, int64_t* __restrict__ fillc,
-                               int64_t* __restrict__ occ_row, int64_t* __restrict__ occ_base) {
+                               int32_t* __restrict__ occ_row, int32_t* __restrict__ occ_base) {
     for (int64_t r = r0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < r1;
          r += (int64_t)gridDim.x * blockDim.x) {
         int32_t g = member_ids[r];
         if (g < 0 || g >= n_global) continue;
         int64_t slot = off[g] + fillc[g];
         fillc[g] += 1;                       // unique g within a shard: no race
-        occ_row[slot] = r;
-        occ_base[slot] = r0;
+        occ_row[slot] = (int32_t)r;      // rows < MAX_ROWS < 2^26
+        occ_base[slot] = (int32_t)r0;
     }
 }
 
 __global__ __launch_bounds__(256) void merge_kernel(
     const int32_t* __restrict__ member_ids, const int32_t* __restrict__ graphs, int R,
     int64_t total_rows, int64_t n_global, int max_degree, const int64_t* __restrict__ off,
-    const int64_t* __restrict__ occ_row, const int64_t* __restrict__ occ_base,
+    const int32_t* __restrict__ occ_row, const int32_t* __restrict__ occ_base,
     int32_t* __restrict__ out, int32_t* __restrict__ degree) {
     __shared__ int32_t s_kl[WAVES][MAX_DEG];
     __shared__ int32_t s_chunk[WAVES][64];
@@ -58,28 +60,41 @@ __global__ __launch_bounds__(256) void merge_kernel(
     int32_t* kl = s_kl[w];
     int32_t* chunk = s_chunk[w];
     const int64_t b = off[g];
-    const int64_t m = off[g + 1] - b;
-    const int64_t L = m * R;
+    const uint32_t m = (uint32_t)(off[g + 1] - b);   // occurrences: <= S when member lists are sets
+    const uint64_t L = (uint64_t)m * (uint64_t)R;
     int kc = 0;
-    for (int64_t e0 = 0; e0 < L && kc < max_degree; e0 += 64) {
-        const int64_t e = e0 + l;
+    for (uint64_t e0 = 0; e0 < L && kc < max_degree; e0 += 64) {
+        const uint64_t e = e0 + l;
         int32_t v = SG_NONE;
         if (e < L) {
-            const int64_t pos = e / m;
-            const int64_t t = e - pos * m;
+            // position-major: entry e is position e / m of occurrence e % m
+            // (32-bit division while e fits, the usual case)
+            uint32_t pos, t;
+            if (e0 < 0xFFFFFF00ull) {
+                pos = (uint32_t)e / m;
+                t = (uint32_t)e - pos * m;
+            } else {
+                pos = (uint32_t)(e / m);
+                t = (uint32_t)(e - (uint64_t)pos * m);
+            }
             const int64_t r = occ_row[b + t];
             const int32_t lv = graphs[r * R + pos];
-            const int64_t mr = occ_base[b + t] + lv;
+            const int64_t mr = (int64_t)occ_base[b + t] + lv;
             if (lv >= 0 && mr < total_rows) {   // out-of-range local ids count as absent
                 const int32_t gv = member_ids[mr];
-                if (gv != (int32_t)g) v = gv;
+                // ids outside [0, n_global) are skipped (so every kept id is < 2^26)
+                if (gv != (int32_t)g && gv >= 0 && gv < n_global) v = gv;
             }
         }
-        chunk[l] = v;
+        // first occurrence in lane order within the chunk: sort (id, lane),
+        // flag the first lane of each run of equal ids at the lane it came from
+        const uint32_t sk = v != SG_NONE ? ((uint32_t)v << 6) | (uint32_t)l : 0xFFFFFFFFu;
+        const uint32_t srt = wave_sort_u32(sk);
+        const uint32_t prev = (uint32_t)__shfl((int)srt, l > 0 ? l - 1 : 0, 64);
+        if (srt != 0xFFFFFFFFu) chunk[srt & 63u] = (l == 0 || (prev >> 6) != (srt >> 6)) ? 1 : 0;
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        bool keep = v != SG_NONE;
+        bool keep = v != SG_NONE && chunk[l] != 0;
         for (int t = 0; t < kc && keep; ++t) keep = kl[t] != v;
-        for (int t = 0; t < l && keep; ++t) keep = chunk[t] != v;
         const uint64_t mk = __builtin_amdgcn_ballot_w64(keep);
         const int p = kc + __builtin_popcountll(mk & ((1ull << l) - 1));
         if (keep && p < max_degree) kl[p] = v;
@@ -101,7 +116,7 @@ inline Layout layout(int64_t total_rows, int64_t n_global) {
     L.cnt = align_up((size_t)(n_global + 1) * 8, 256);
     L.off = L.cnt;
     L.fillc = L.cnt;
-    L.occ_row = align_up((size_t)std::max<int64_t>(total_rows, 1) * 8, 256);
+    L.occ_row = align_up((size_t)std::max<int64_t>(total_rows, 1) * 4, 256);
     L.occ_base = L.occ_row;
     L.scan = align_up(exclusive_scan_tmp_bytes(n_global), 256);
     L.total = L.cnt + L.off + L.fillc + L.occ_row + L.occ_base + L.scan + 1024;
@@ -150,8 +165,8 @@ extern "C" sg_status sg_merge(int32_t S, const int64_t* shard_offsets_h, const i
         int64_t* cnt = cv.take<int64_t>(n_global + 1);
         int64_t* off = cv.take<int64_t>(n_global + 1);
         int64_t* fillc = cv.take<int64_t>(n_global + 1);
-        int64_t* occ_row = cv.take<int64_t>(std::max<int64_t>(total, 1));
-        int64_t* occ_base = cv.take<int64_t>(std::max<int64_t>(total, 1));
+        int32_t* occ_row = cv.take<int32_t>(std::max<int64_t>(total, 1));
+        int32_t* occ_base = cv.take<int32_t>(std::max<int64_t>(total, 1));
         void* scan_tmp = cv.take<char>(exclusive_scan_tmp_bytes(n_global));
         fill<int64_t>(cnt, 0, n_global + 1, s);
         fill<int64_t>(fillc, 0, n_global + 1, s);

@@ -40,23 +40,22 @@ constexpr int WAVES = 4;
 // slot (its id field is SG_NONE, whose position field, -1, never counts).
 constexpr uint64_t EMPTY_SLOT = ~0ull;
 
-// The low 24 bits of the id with the high bits folded in; the two hashes are
-// bits of two 24-bit products (v_mul_u32_u24, full rate: a plain 32-bit
-// product would take the quarter-rate v_mul_lo_u32 although both factors fit
-// 24 bits; the low 32 bits of the product are the same).
-__device__ inline uint32_t mix_id(int32_t z) {
-    const uint32_t u = (uint32_t)z;
-    return (u ^ (u >> 15)) & 0xFFFFFFu;
-}
+// Both slots come from one 24-bit product of the id (v_mul_u32_u24, full
+// rate; it reads the low 24 bits of the id, so ids that differ only above bit
+// 23 share both slots, which only rows of shards over 2^24 rows can meet and
+// which the compare-with-every-entry path then handles): T0 takes bits 8.. of
+// the product, T1 bits 20.. (bits 8-15 depend on the low 16 bits of the id
+// only, bits 20-29 on all 24).
 __device__ inline uint32_t mul_u24(uint32_t c, uint32_t m) {
     uint32_t r;
     asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "s"(c), "v"(m));
     return r;
 }
+__device__ inline uint32_t cuckoo_product(int32_t z) { return mul_u24(0x9E3779u, (uint32_t)z); }
 template <int CT>
-__device__ inline uint32_t cuckoo_h0(uint32_t m) { return (mul_u24(0x9E3779u, m) >> 8) & (CT - 1); }
+__device__ inline uint32_t cuckoo_h0(uint32_t p) { return (p >> 8) & (CT - 1); }
 template <int CT>
-__device__ inline uint32_t cuckoo_h1(uint32_t m) { return (mul_u24(0x85EBCBu, m) >> 16) & (CT - 1); }
+__device__ inline uint32_t cuckoo_h1(uint32_t p) { return (p >> 20) & (CT - 1); }
 
 // Flags *bad unless order[0..n) is a permutation of 0..n-1: every entry in
 // range and no row seen twice (n entries, so none is then missing).  seen
@@ -117,7 +116,7 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
         int tb = 0;
         for (int it = 0; it < 128 && __builtin_amdgcn_ballot_w64(active); ++it) {
             if (active) {
-                const uint32_t m = mix_id((int32_t)(uint32_t)e);
+                const uint32_t m = cuckoo_product((int32_t)(uint32_t)e);
                 unsigned long long* a = reinterpret_cast<unsigned long long*>(
                     tb ? &T1[cuckoo_h1<CT>(m)] : &T0[cuckoo_h0<CT>(m)]);
                 const uint64_t old = atomicExch(a, (unsigned long long)e);
@@ -159,7 +158,7 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
         for (int u = 0; u < UB; ++u)
 #pragma unroll
             for (int t = 0; t < KP; ++t) {
-                const uint32_t m = mix_id(z[u][t]);
+                const uint32_t m = cuckoo_product(z[u][t]);
                 v0[u][t] = T0[cuckoo_h0<CT>(m)];
                 v1[u][t] = T1[cuckoo_h1<CT>(m)];
             }

@@ -90,11 +90,11 @@ def test_prune_symmetric_graph(n, half, R):
 
 
 def _cuckoo_slots(z, ct=256):
-    """The two table slots the detour kernel's row hash gives id z (K <= 64)."""
-    z = np.asarray(z, np.uint64)
-    m = (z ^ (z >> np.uint64(15))) & np.uint64(0xFFFFFF)
-    return (((m * np.uint64(0x9E3779)) >> np.uint64(8)) & np.uint64(ct - 1),
-            ((m * np.uint64(0x85EBCB)) >> np.uint64(16)) & np.uint64(ct - 1))
+    """The two table slots the detour kernel's row hash gives id z (K <= 64):
+    bits 8.. and 20.. of the low 32 bits of (low 24 bits of z) * 0x9E3779."""
+    z = np.asarray(z, np.uint64) & np.uint64(0xFFFFFF)
+    p = (z * np.uint64(0x9E3779)) & np.uint64(0xFFFFFFFF)
+    return (p >> np.uint64(8)) & np.uint64(ct - 1), (p >> np.uint64(20)) & np.uint64(ct - 1)
 
 
 def test_prune_rows_whose_table_cannot_settle():
