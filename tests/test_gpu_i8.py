@@ -47,13 +47,21 @@ def test_i8_bit_exact(metric, n, d, K):
 @pytest.mark.parametrize("metric", ["l2", "ip"])
 @pytest.mark.parametrize("d", [128, 256])
 def test_i8_extreme_values_bit_exact(metric, d):
+    # accumulators near their largest magnitude (the subtile bound is an
+    # integer comparison of the largest accumulator): every launch shape
     X = _extremes(500, d, seed=d)
     m = oracle.IP if metric == "ip" else oracle.L2
-    nbr, dist = sg.sg_knn_graph(torch.from_numpy(X).to(DEV), 48, metric, "i8")
-    torch.cuda.synchronize()
+    Xg = torch.from_numpy(X).to(DEV)
     onbr, odist = oracle.knn(oracle.widen(X), 48, m)
-    np.testing.assert_array_equal(nbr.cpu().numpy(), onbr)
-    np.testing.assert_array_equal(dist.cpu().numpy(), odist.astype(np.float32))
+    try:
+        for v in range(sg.sg_knn_variant_count(d, 48, "i8")):
+            sg.sg_knn_force_variant(v)
+            nbr, dist = sg.sg_knn_graph(Xg, 48, metric, "i8")
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(nbr.cpu().numpy(), onbr, err_msg="variant %d" % v)
+            np.testing.assert_array_equal(dist.cpu().numpy(), odist.astype(np.float32))
+    finally:
+        sg.sg_knn_force_variant(-1)
 
 
 def test_i8_heavy_ties():
