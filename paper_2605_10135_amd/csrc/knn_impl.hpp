@@ -983,14 +983,15 @@ constexpr int min_waves_per_simd(int waves, int bcr, int cbq = CB) {
 }
 
 // Buffer entries per query of the 4-wave, 32-row-tile shape that runs four
-// workgroups per CU: the longest of 28, 24, 20 whose LDS lets four share a
+// workgroups per CU: the longest of 30, 28, 24, 20 whose LDS lets four share a
 // CU's 160 KB, else 16.  Longer buffers mean fewer merges (for 128-byte rows
 // 28 entries took the INT8 batched build from 59.8 to 53.9 ms against the
-// 32-entry, three-workgroup shape).
+// 32-entry, three-workgroup shape, and 30 entries (40 728 bytes) 1.5% more).
 template <int P, int NSTEP>
 constexpr int cbq_four_wgs() {
     constexpr size_t cap = 160 * 1024 / 4;
-    return sizeof(TopkSmem<P, NSTEP, 4, 1, 28, 32>) <= cap   ? 28
+    return sizeof(TopkSmem<P, NSTEP, 4, 1, 30, 32>) <= cap   ? 30
+           : sizeof(TopkSmem<P, NSTEP, 4, 1, 28, 32>) <= cap ? 28
            : sizeof(TopkSmem<P, NSTEP, 4, 1, 24, 32>) <= cap ? 24
            : sizeof(TopkSmem<P, NSTEP, 4, 1, 20, 32>) <= cap ? 20
                                                              : 16;
