@@ -136,29 +136,46 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
     // are probed
     constexpr int UB = 16 / KP;
     int32_t zA[UB][KP], zB[UB][KP];
-    auto load = [&](int32_t (&dst)[UB][KP], int i0) {
+    // Raw list entries: every lane loads an index inside a valid row (no
+    // branch, so the loads of a round stay in flight together); the returned
+    // bit u says whether list u exists (y_i != SG_NONE), and the probes mask
+    // lanes past K and absent lists when they consume the values.
+    auto load = [&](int32_t (&dst)[UB][KP], int i0) -> uint32_t {
+        uint32_t okm = 0;
 #pragma unroll
         for (int u = 0; u < UB; ++u) {
             const int i = i0 + u;
-            const int32_t yi = __builtin_amdgcn_readfirstlane(i < K - 1 ? nx[i] : SG_NONE);
-            const int32_t* row = knn + (int64_t)(yi < 0 ? 0 : yi) * K;
+            // y_i = N(x)[i], wave-uniform: read from the lane holding it (K <= 64)
+            // or from LDS
+            int32_t yi;
+            if constexpr (KP == 1)
+                yi = i < K - 1 ? __builtin_amdgcn_readlane(y[0], i) : SG_NONE;
+            else
+                yi = __builtin_amdgcn_readfirstlane(i < K - 1 ? nx[i] : SG_NONE);
+            const bool ok = yi != SG_NONE;
+            okm |= ok ? 1u << u : 0u;
+            const int32_t* row = knn + (int64_t)(ok ? yi : 0) * K;
 #pragma unroll
             for (int t = 0; t < KP; ++t) {
                 const int p = l + 64 * t;
-                dst[u][t] = (yi != SG_NONE && p < K) ? row[p] : SG_NONE;
+                dst[u][t] = row[p < K ? p : 0];
             }
         }
+        return okm;
     };
     // count the detour of position j via i: i < j and y_j before position j
     // in N(y_i) (other lanes add to their discard slot)
     auto count = [&](int j, int i, int p) { atomicAdd(&det[(j > i && p < j) ? j : 64 * KP + l], 1); };
-    auto probe = [&](const int32_t (&z)[UB][KP], int i0) {
+    auto entry = [&](const int32_t (&z)[UB][KP], uint32_t okm, int u, int t) -> int32_t {
+        return ((okm >> u) & 1u) && l + 64 * t < K ? z[u][t] : SG_NONE;
+    };
+    auto probe = [&](const int32_t (&z)[UB][KP], uint32_t okm, int i0) {
         uint64_t v0[UB][KP], v1[UB][KP];
 #pragma unroll
         for (int u = 0; u < UB; ++u)
 #pragma unroll
             for (int t = 0; t < KP; ++t) {
-                const uint32_t m = cuckoo_product(z[u][t]);
+                const uint32_t m = cuckoo_product(entry(z, okm, u, t));
                 v0[u][t] = T0[cuckoo_h0<CT>(m)];
                 v1[u][t] = T1[cuckoo_h1<CT>(m)];
             }
@@ -166,7 +183,7 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
         for (int u = 0; u < UB; ++u)
 #pragma unroll
             for (int t = 0; t < KP; ++t) {
-                const int32_t zz = z[u][t];
+                const int32_t zz = entry(z, okm, u, t);
                 const uint64_t a = v0[u][t], b = v1[u][t];
                 const int j = (int32_t)(uint32_t)a == zz ? (int)(a >> 32) : (int32_t)(uint32_t)b == zz ? (int)(b >> 32) : -1;
                 count(j, i0 + u, l + 64 * t);
@@ -174,23 +191,24 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
     };
     // a row whose insertion did not settle (never for distinct ids in
     // practice) finds positions by comparing with every entry
-    auto probe_scan = [&](const int32_t (&z)[UB][KP], int i0) {
+    auto probe_scan = [&](const int32_t (&z)[UB][KP], uint32_t okm, int i0) {
         for (int u = 0; u < UB; ++u)
 #pragma unroll
             for (int t = 0; t < KP; ++t) {
+                const int32_t zz = entry(z, okm, u, t);
                 int j = -1;
                 for (int v = K - 1; v >= 0; --v)
-                    if (z[u][t] != SG_NONE && nx[v] == z[u][t]) j = v;
+                    if (zz != SG_NONE && nx[v] == zz) j = v;
                 count(j, i0 + u, l + 64 * t);
             }
     };
-    load(zA, 0);
+    uint32_t okA = load(zA, 0), okB = 0;
     for (int i0 = 0; i0 < K - 1; i0 += 2 * UB) {
-        if (i0 + UB < K - 1) load(zB, i0 + UB);
-        if (!failed) probe(zA, i0); else probe_scan(zA, i0);
+        if (i0 + UB < K - 1) okB = load(zB, i0 + UB);
+        if (!failed) probe(zA, okA, i0); else probe_scan(zA, okA, i0);
         if (i0 + UB >= K - 1) break;
-        if (i0 + 2 * UB < K - 1) load(zA, i0 + 2 * UB);
-        if (!failed) probe(zB, i0 + UB); else probe_scan(zB, i0 + UB);
+        if (i0 + 2 * UB < K - 1) okA = load(zA, i0 + 2 * UB);
+        if (!failed) probe(zB, okB, i0 + UB); else probe_scan(zB, okB, i0 + UB);
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     // rank valid positions by (detour, j); keys are unique
