@@ -311,6 +311,20 @@ __device__ inline bool first_occurrence(int32_t v, int32_t e, int ne) {
     return keep;
 }
 
+// The same test from the other side, for a short v and a long e: lane l keeps
+// v unless some lane of e holds it, found by one ballot per lane of v below nv
+// (the lanes holding v values) instead of one comparison per lane of e.
+__device__ inline bool absent_from(int32_t v, int32_t e, int nv) {
+    bool keep = v != SG_NONE;
+    const int l = lane_id();
+    for (int t = 0; t < nv; ++t) {
+        const int32_t x = __builtin_amdgcn_readlane(v, t);
+        const bool found = __builtin_amdgcn_ballot_w64(e == x) != 0;
+        keep &= !(found && l == t);
+    }
+    return keep;
+}
+
 // Lanes below the highest lane holding a value (0 when none).
 __device__ inline int span_of(int32_t v) {
     const uint64_t m = __builtin_amdgcn_ballot_w64(v != SG_NONE);
@@ -368,16 +382,15 @@ __global__ __launch_bounds__(256) void combine_kernel(const int32_t* __restrict_
     const int32_t vc = l < R - h ? P[y * R + h + l] : SG_NONE;
     // (every ballot and lane read below runs with all lanes active: a span
     // taken under a lane condition would miss the other lanes' values)
-    const int spa = span_of(va);
+    const int spa = span_of(va), spc = span_of(vc);
     int32_t vb[NB];
     bool kb[NB];
     bool kc = vc != SG_NONE;
 #pragma unroll
     for (int p = 0; p < NB; ++p) {
         vb[p] = best[p] != RK::EMPTY ? RK::source(best[p]) : SG_NONE;
-        const int spb = span_of(vb[p]);
         kb[p] = first_occurrence(vb[p], va, spa);
-        const bool c_new = first_occurrence(vc, vb[p], spb);
+        const bool c_new = absent_from(vc, vb[p], spc);
         kc = kc & c_new;
     }
     const uint64_t below = (1ull << l) - 1;
