@@ -46,6 +46,10 @@ __global__ void scatter_kernel(const int32_t* __restrict__ member_ids, int64_t r
     }
 }
 
+// Global ids per wave: the gathers of their first chunks are issued together,
+// so that one id's dependent loads wait while the other's are in flight.
+constexpr int IDS = 2;
+
 __global__ __launch_bounds__(256) void merge_kernel(
     const int32_t* __restrict__ member_ids, const int32_t* __restrict__ graphs, int R,
     int64_t total_rows, int64_t n_global, int max_degree, const int64_t* __restrict__ off,
@@ -55,39 +59,64 @@ __global__ __launch_bounds__(256) void merge_kernel(
     __shared__ int32_t s_chunk[WAVES][64];
     const int l = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int64_t g = (int64_t)blockIdx.x * WAVES + w;
-    if (g >= n_global) return;
+    const int64_t g0 = ((int64_t)blockIdx.x * WAVES + w) * IDS;
+    if (g0 >= n_global) return;
     int32_t* kl = s_kl[w];
     int32_t* chunk = s_chunk[w];
-    const int64_t b = off[g];
-    const uint32_t m = (uint32_t)(off[g + 1] - b);   // occurrences: <= S when member lists are sets
-    const uint64_t L = (uint64_t)m * (uint64_t)R;
-    int kc = 0;
-    for (uint64_t e0 = 0; e0 < L && kc < max_degree; e0 += 64) {
-        const uint64_t e = e0 + l;
-        int32_t v = SG_NONE;
-        if (e < L) {
-            // position-major: entry e is position e / m of occurrence e % m
-            // (32-bit division while e fits, the usual case)
-            uint32_t pos, t;
-            if (e0 < 0xFFFFFF00ull) {
-                pos = (uint32_t)e / m;
-                t = (uint32_t)e - pos * m;
-            } else {
-                pos = (uint32_t)(e / m);
-                t = (uint32_t)(e - (uint64_t)pos * m);
-            }
-            const int64_t r = occ_row[b + t];
-            const int32_t lv = graphs[r * R + pos];
-            const int64_t mr = (int64_t)occ_base[b + t] + lv;
-            if (lv >= 0 && mr < total_rows) {   // out-of-range local ids count as absent
-                const int32_t gv = member_ids[mr];
-                // ids outside [0, n_global) are skipped (so every kept id is < 2^26)
-                if (gv != (int32_t)g && gv >= 0 && gv < n_global) v = gv;
-            }
+    int64_t gi[IDS], bi[IDS];
+    uint32_t mi[IDS];   // occurrences: <= S when member lists are sets
+    uint64_t Li[IDS];
+#pragma unroll
+    for (int i = 0; i < IDS; ++i) {
+        gi[i] = g0 + i;
+        const bool ok = gi[i] < n_global;
+        bi[i] = ok ? off[gi[i]] : 0;
+        mi[i] = ok ? (uint32_t)(off[gi[i] + 1] - bi[i]) : 0u;
+        Li[i] = (uint64_t)mi[i] * (uint64_t)R;
+    }
+    // Global id of list entry e of id i (position-major: position e / m of
+    // occurrence e % m), or SG_NONE: absent, self, or out of range.
+    auto finish = [&](int i, bool live, int32_t lv, int64_t base, int32_t gv) -> int32_t {
+        // ids outside [0, n_global) are skipped (so every kept id is < 2^26)
+        return live && lv >= 0 && base + lv < total_rows && gv != (int32_t)gi[i] && gv >= 0 && gv < n_global
+                   ? gv : SG_NONE;
+    };
+    // the first chunk of every id, stage by stage over the ids, without
+    // branches: lanes past an id's list read index 0 (in bounds, as
+    // total_rows > 0 here) and are masked afterwards
+    int32_t v0[IDS];
+    if (total_rows > 0) {
+        bool live[IDS];
+        uint32_t pos[IDS];
+        int64_t orow[IDS], obase[IDS];
+#pragma unroll
+        for (int i = 0; i < IDS; ++i) {
+            live[i] = (uint64_t)l < Li[i];
+            const uint32_t m1 = mi[i] > 0 ? mi[i] : 1u;
+            const uint32_t p_ = (uint32_t)l / m1;
+            const int64_t oi = live[i] ? bi[i] + ((uint32_t)l - p_ * m1) : 0;
+            const int32_t r_ = occ_row[oi], b_ = occ_base[oi];
+            orow[i] = live[i] ? r_ : 0;
+            obase[i] = live[i] ? b_ : 0;
+            pos[i] = live[i] ? p_ : 0u;
         }
-        // first occurrence in lane order within the chunk: sort (id, lane),
-        // flag the first lane of each run of equal ids at the lane it came from
+        int32_t lv[IDS];
+#pragma unroll
+        for (int i = 0; i < IDS; ++i) lv[i] = graphs[orow[i] * R + pos[i]];
+#pragma unroll
+        for (int i = 0; i < IDS; ++i) {
+            const int64_t mr = obase[i] + lv[i];
+            const bool ok = live[i] && lv[i] >= 0 && mr < total_rows;
+            v0[i] = finish(i, live[i], lv[i], obase[i], member_ids[ok ? mr : 0]);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < IDS; ++i) v0[i] = SG_NONE;
+    }
+    // Appends the chunk's first occurrences (in lane order) not yet kept:
+    // sort (id, lane) and flag the first lane of each run of equal ids at the
+    // lane it came from; then compare with the ids kept from earlier chunks.
+    auto append = [&](int32_t v, int kc) -> int {
         const uint32_t sk = v != SG_NONE ? ((uint32_t)v << 6) | (uint32_t)l : 0xFFFFFFFFu;
         const uint32_t srt = wave_sort_u32(sk);
         const uint32_t prev = (uint32_t)__shfl((int)srt, l > 0 ? l - 1 : 0, 64);
@@ -101,10 +130,43 @@ __global__ __launch_bounds__(256) void merge_kernel(
         kc += __builtin_popcountll(mk);
         if (kc > max_degree) kc = max_degree;
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        return kc;
+    };
+#pragma unroll
+    for (int i = 0; i < IDS; ++i) {
+        if (gi[i] >= n_global) break;
+        const int64_t b = bi[i];
+        const uint32_t m = mi[i];
+        const uint64_t L = Li[i];
+        int kc = append(v0[i], 0);
+        // further chunks (an id in more than 64 / R shards)
+        for (uint64_t e0 = 64; e0 < L && kc < max_degree; e0 += 64) {
+            const uint64_t e = e0 + l;
+            int32_t v = SG_NONE;
+            if (e < L) {
+                // 32-bit division while e fits, the usual case
+                uint32_t pos, t;
+                if (e0 < 0xFFFFFF00ull) {
+                    pos = (uint32_t)e / m;
+                    t = (uint32_t)e - pos * m;
+                } else {
+                    pos = (uint32_t)(e / m);
+                    t = (uint32_t)(e - (uint64_t)pos * m);
+                }
+                const int64_t r = occ_row[b + t];
+                const int32_t lv = graphs[r * R + pos];
+                const int64_t base = occ_base[b + t];
+                const bool ok = lv >= 0 && base + lv < total_rows;   // out-of-range local ids count as absent
+                v = finish(i, true, lv, base, ok ? member_ids[base + lv] : SG_NONE);
+            }
+            kc = append(v, kc);
+        }
+        int32_t* o = out + gi[i] * max_degree;
+        for (int q = l; q < max_degree; q += 64) o[q] = q < kc ? kl[q] : SG_NONE;
+        if (l == 0) degree[gi[i]] = kc;
+        // kl is rewritten by the next id: every lane has read its entries
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     }
-    int32_t* o = out + g * max_degree;
-    for (int q = l; q < max_degree; q += 64) o[q] = q < kc ? kl[q] : SG_NONE;
-    if (l == 0) degree[g] = kc;
 }
 
 struct Layout {
@@ -184,7 +246,7 @@ extern "C" sg_status sg_merge(int32_t S, const int64_t* shard_offsets_h, const i
                                                       occ_base);
             SG_LAUNCH_CHECK();
         }
-        merge::merge_kernel<<<(unsigned)cdiv(n_global, merge::WAVES), 256, 0, s>>>(
+        merge::merge_kernel<<<(unsigned)cdiv(n_global, merge::WAVES * merge::IDS), 256, 0, s>>>(
             member_ids, graphs, R, total, n_global, max_degree, off, occ_row, occ_base, out, degree);
         SG_LAUNCH_CHECK();
     });
