@@ -71,13 +71,24 @@ __global__ void place_batched_kernel(Shards sh, const int32_t* __restrict__ orde
     }
 }
 
-// Batch-row ids -> shard-local ids, in place (SG_NONE stays).
+// Batch-row ids -> shard-local ids, in place (SG_NONE stays).  A block's
+// entries are consecutive, so their rows nearly always lie in one shard: it is
+// found once per block, and per entry only where the block straddles a shard
+// boundary.
 __global__ void localize_kernel(Shards sh, int32_t* __restrict__ lists, int width) {
     const int64_t total = sh.row0[sh.S] * width;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = e / width;
-        const int32_t v = lists[e];
-        if (v >= 0) lists[e] = (int32_t)(v - sh.row0[shard_of(sh.row0, sh.S, r)]);
+    for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x; e0 < total; e0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = e0 + threadIdx.x;
+        const int64_t e1 = (e0 + blockDim.x < total ? e0 + blockDim.x : total) - 1;
+        const int s0 = shard_of(sh.row0, sh.S, e0 / width);
+        const bool one = e1 / width < sh.row0[s0 + 1];
+        if (e < total) {
+            const int32_t v = lists[e];
+            if (v >= 0) {
+                const int64_t base = one ? sh.row0[s0] : sh.row0[shard_of(sh.row0, sh.S, e / width)];
+                lists[e] = (int32_t)(v - base);
+            }
+        }
     }
 }
 
@@ -212,11 +223,11 @@ void enqueue(const Plan& p, const void* X, int dtype, int d, int64_t ld, int met
 
     maps_kernel<<<eg, 256, 0, s>>>(p.sh, idmap, perm, pid, pivmap);
     SG_LAUNCH_CHECK();
-    prep_kernel<<<(unsigned)cdiv(ppad, 4), 256, 0, s>>>(X, dtype, ppad, d, ld, pivmap, p.n_all, ppad, p.DP, prec,
-                                                       metric, pops, pinit, pnout, fp8 ? psexp : nullptr);
+    launch_prep(X, dtype, ppad, d, ld, pivmap, p.n_all, ppad, p.DP, prec,
+                metric, pops, pinit, pnout, fp8 ? psexp : nullptr, s);
     SG_LAUNCH_CHECK();
-    prep_kernel<<<(unsigned)cdiv(pad, 4), 256, 0, s>>>(X, dtype, pad, d, ld, idmap, p.n_all, pad, p.DP, prec, metric,
-                                                      ops, ninit, nout, fp8 ? sexp : nullptr);
+    launch_prep(X, dtype, pad, d, ld, idmap, p.n_all, pad, p.DP, prec, metric,
+                ops, ninit, nout, fp8 ? sexp : nullptr, s);
     SG_LAUNCH_CHECK();
     p.kern.near<<<(unsigned)(pad / (NEAR_WAVES * 32)), NEAR_WAVES * 64, 0, s>>>(
         p.sh, pops, pinit, fp8 ? psexp : nullptr, ops, fp8 ? sexp : nullptr, qmul, lab);
@@ -227,8 +238,8 @@ void enqueue(const Plan& p, const void* X, int dtype, int d, int64_t ld, int met
     label_sort(labc, p.n_all, bits_for(std::max<int64_t>(piv, 1)), order, sort_tmp, s);
     place_batched_kernel<<<eg, 256, 0, s>>>(p.sh, order, perm, pid);
     SG_LAUNCH_CHECK();
-    prep_kernel<<<(unsigned)cdiv(pad, 4), 256, 0, s>>>(X, dtype, pad, d, ld, perm, p.n_all, pad, p.DP, prec, metric,
-                                                      ops, ninit, nout, fp8 ? sexp : nullptr);
+    launch_prep(X, dtype, pad, d, ld, perm, p.n_all, pad, p.DP, prec, metric,
+                ops, ninit, nout, fp8 ? sexp : nullptr, s);
     SG_LAUNCH_CHECK();
     fill<uint64_t>(state, EMPTY_KEY, pad * p.ksel, s);
     fill<unsigned int>(counter, 0u, 1, s);

@@ -129,7 +129,6 @@ void run(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int
     const bool plain_ip = metric == SG_IP && !norm_corrected_ip(metric, prec);
     const float qmul = plain_ip ? -1.0f : -2.0f;
     const float osc = norm_corrected_ip(metric, prec) ? 0.5f : 1.0f;
-    const unsigned prep_grid = (unsigned)cdiv(L.n_pad, 4);
 
     int64_t* perm = nullptr;
     int32_t* pid = nullptr;
@@ -147,11 +146,11 @@ void run(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int
         // nearest pivot of every row (queries: all rows in their own order)
         pivot_rows_kernel<<<(unsigned)cdiv(P, 256), 256, 0, s>>>(piv, P, n);
         SG_LAUNCH_CHECK();
-        prep_kernel<<<(unsigned)cdiv(Pp, 4), 256, 0, s>>>(X, dtype, P, d, ld, piv, n, Pp, L.DP, prec, metric,
-                                                          pops, pinit, pnout, prec == SG_PREC_FP8 ? psexp : nullptr);
+        launch_prep(X, dtype, P, d, ld, piv, n, Pp, L.DP, prec, metric,
+                    pops, pinit, pnout, prec == SG_PREC_FP8 ? psexp : nullptr, s);
         SG_LAUNCH_CHECK();
-        prep_kernel<<<prep_grid, 256, 0, s>>>(X, dtype, n, d, ld, nullptr, n, L.n_pad, L.DP, prec, metric, ops,
-                                              ninit, nout, sexp);
+        launch_prep(X, dtype, n, d, ld, nullptr, n, L.n_pad, L.DP, prec, metric, ops,
+                    ninit, nout, sexp, s);
         SG_LAUNCH_CHECK();
         kern.near<<<(unsigned)(L.n_pad / (32 * NEAR_WAVES)), NEAR_WAVES * 64, 0, s>>>(
             pops, pinit, prec == SG_PREC_FP8 ? psexp : nullptr, (int)P, ops, sexp, (int)n, qmul, lab);
@@ -163,8 +162,8 @@ void run(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int
         SG_LAUNCH_CHECK();
     }
 
-    prep_kernel<<<prep_grid, 256, 0, s>>>(X, dtype, n, d, ld, perm, n, L.n_pad, L.DP, prec, metric, ops, ninit,
-                                          nout, sexp);
+    launch_prep(X, dtype, n, d, ld, perm, n, L.n_pad, L.DP, prec, metric, ops, ninit,
+                nout, sexp, s);
     SG_LAUNCH_CHECK();
     if (order_out && !subset) {   // the rows in the order the build visits them
         if (pid)
@@ -174,8 +173,8 @@ void run(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int
         SG_LAUNCH_CHECK();
     }
     if (subset) {
-        prep_kernel<<<(unsigned)cdiv(nq_pad, 4), 256, 0, s>>>(X, dtype, nq, d, ld, rows, n, nq_pad, L.DP, prec,
-                                                               metric, qops, qninit, qnout, qsexp);
+        launch_prep(X, dtype, nq, d, ld, rows, n, nq_pad, L.DP, prec,
+                    metric, qops, qninit, qnout, qsexp, s);
         SG_LAUNCH_CHECK();
     }
     fill<uint64_t>(state, EMPTY_KEY, nq_pad * L.ksel, s);
@@ -357,9 +356,9 @@ extern "C" sg_status sg_quantize_rows(const void* X, sg_dtype dtype, int64_t n, 
         SG_REQUIRE(out != nullptr, "out is NULL");
         SG_REQUIRE(prec != SG_PREC_FP8 || scale_exp != nullptr, "FP8 needs scale_exp");
         hipStream_t s = as_stream(stream);
-        knn::prep_kernel<<<(unsigned)cdiv(n, 4), 256, 0, s>>>(X, dtype, n, d, ld, nullptr, n, n, (int)ldo, prec,
-                                                               SG_L2, static_cast<uint8_t*>(out), sqnorm, nullptr,
-                                                               prec == SG_PREC_FP8 ? scale_exp : nullptr);
+        knn::launch_prep(X, dtype, n, d, ld, nullptr, n, n, (int)ldo, prec,
+                         SG_L2, static_cast<uint8_t*>(out), sqnorm, nullptr,
+                         prec == SG_PREC_FP8 ? scale_exp : nullptr, s);
         SG_LAUNCH_CHECK();
         if (prec == SG_PREC_I8 && sqnorm) {   // the INT8 start word back to the squared norm
             knn::i8_norms_kernel<<<(unsigned)std::min<int64_t>(cdiv(n, 256), 4096), 256, 0, s>>>(sqnorm, n);

@@ -132,23 +132,24 @@ __host__ __device__ inline bool norm_corrected_ip(int metric, int prec) {
     return metric == SG_IP && (prec == SG_PREC_BF16 || prec == SG_PREC_FP8);
 }
 
-// One wave per operand row (source row rowmap[row], or row itself when
-// rowmap is NULL).  Writes the converted row (zero padded to DP),
+// LPR lanes per operand row (source row rowmap[row], or row itself when
+// rowmap is NULL), 64 / LPR rows per wavefront.  Writes the converted row (zero padded to DP),
 // the accumulator start of the row as a candidate (ninit, NaN for padding
 // rows), its output offset as a query (nout) and, for FP8, the row's scale
 // exponent (ninit, nout and sexp may be NULL).
-static __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_t n, int d, int64_t ld,
+template <int LPR>
+__global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_t n, int d, int64_t ld,
                             const int64_t* __restrict__ rowmap, int64_t n_src, int64_t n_pad, int DP,
                             int prec, int metric, uint8_t* __restrict__ ops, float* __restrict__ ninit,
                             float* __restrict__ nout, int32_t* __restrict__ sexp) {
-    const int l = threadIdx.x & 63;
-    const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int l = threadIdx.x & (LPR - 1);
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / LPR) + threadIdx.x / LPR;
     if (row >= n_pad) return;
     const int eb = elem_bytes(prec);
     uint8_t* out = ops + row * (int64_t)DP * eb;
     const int64_t src_row = row < n ? (rowmap ? rowmap[row] : row) : -1;
     if (src_row < 0 || src_row >= n_src) {      // padding (or an out-of-range listed row)
-        for (int t = l; t < DP; t += 64) {
+        for (int t = l; t < DP; t += LPR) {
             if (eb == 4) reinterpret_cast<float*>(out)[t] = 0.f;
             else if (eb == 2) reinterpret_cast<uint16_t*>(out)[t] = 0;
             else out[t] = 0;
@@ -167,8 +168,8 @@ static __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_
     float inv = 1.0f;
     if (prec == SG_PREC_FP8) {
         float amax = 0.f;
-        for (int t = l; t < d; t += 64) amax = fmaxf(amax, fabsf(load_elem(X, dtype, base + t)));
-        for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+        for (int t = l; t < d; t += LPR) amax = fmaxf(amax, fabsf(load_elem(X, dtype, base + t)));
+        for (int o = LPR / 2; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
         // smallest power of two s with amax / s <= 448
         if (amax > 0.f) {
             sx = (int)ceilf(log2f(amax / 448.0f));
@@ -178,7 +179,7 @@ static __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_
         inv = __builtin_ldexpf(1.0f, -sx);
     }
     float ssq = 0.f, ssx = 0.f;
-    for (int t = l; t < DP; t += 64) {
+    for (int t = l; t < DP; t += LPR) {
         float v = t < d ? load_elem(X, dtype, base + t) : 0.f;
         float q;
         switch (prec) {
@@ -215,7 +216,7 @@ static __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_
         ssq += q * q;
         if (prec != SG_PREC_I8) ssx += v * v;
     }
-    for (int o = 32; o > 0; o >>= 1) {
+    for (int o = LPR / 2; o > 0; o >>= 1) {
         ssq += __shfl_xor(ssq, o, 64);
         ssx += __shfl_xor(ssx, o, 64);
     }
@@ -234,6 +235,24 @@ static __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_
         if (nout) nout[row] = oterm;
         if (sexp) sexp[row] = sx;
     }
+}
+
+// Operand preparation of n_pad rows with a lane count per row that suits the
+// padded row length (16 lanes for rows of up to 128 elements, 32 up to 256,
+// else a wavefront), so that short rows do not leave most of a wave idle.
+inline void launch_prep(const void* X, int dtype, int64_t n, int d, int64_t ld, const int64_t* rowmap, int64_t n_src,
+                        int64_t n_pad, int DP, int prec, int metric, uint8_t* ops, float* ninit, float* nout,
+                        int32_t* sexp, hipStream_t s) {
+    if (n_pad <= 0) return;
+    if (DP <= 128)
+        prep_kernel<16><<<(unsigned)cdiv(n_pad, 16), 256, 0, s>>>(X, dtype, n, d, ld, rowmap, n_src, n_pad, DP, prec,
+                                                                   metric, ops, ninit, nout, sexp);
+    else if (DP <= 256)
+        prep_kernel<32><<<(unsigned)cdiv(n_pad, 8), 256, 0, s>>>(X, dtype, n, d, ld, rowmap, n_src, n_pad, DP, prec,
+                                                                  metric, ops, ninit, nout, sexp);
+    else
+        prep_kernel<64><<<(unsigned)cdiv(n_pad, 4), 256, 0, s>>>(X, dtype, n, d, ld, rowmap, n_src, n_pad, DP, prec,
+                                                                  metric, ops, ninit, nout, sexp);
 }
 
 // ---------------------------------------------------------------------------
