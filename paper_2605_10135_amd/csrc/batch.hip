@@ -241,7 +241,7 @@ void enqueue(const Plan& p, const void* X, int dtype, int d, int64_t ld, int met
     launch_prep(X, dtype, pad, d, ld, perm, p.n_all, pad, p.DP, prec, metric,
                 ops, ninit, nout, fp8 ? sexp : nullptr, s);
     SG_LAUNCH_CHECK();
-    fill<uint64_t>(state, EMPTY_KEY, pad * p.ksel, s);
+    // (the distance kernel writes every list itself: no initialisation)
     fill<unsigned int>(counter, 0u, 1, s);
 
     TopkArgs A{};

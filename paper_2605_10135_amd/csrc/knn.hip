@@ -177,7 +177,8 @@ void run(const void* X, int dtype, int64_t n, int d, int64_t ld, int metric, int
                     metric, qops, qninit, qnout, qsexp, s);
         SG_LAUNCH_CHECK();
     }
-    fill<uint64_t>(state, EMPTY_KEY, nq_pad * L.ksel, s);
+    // (the resident-query kernels write every list themselves)
+    if (!kern.fn) fill<uint64_t>(state, EMPTY_KEY, nq_pad * L.ksel, s);
     const bool final_here = rerank == 0;
     TopkArgs A{};
     A.ops = ops; A.ninit = ninit; A.sexp = sexp; A.cpid = pid; A.n = (int)n;

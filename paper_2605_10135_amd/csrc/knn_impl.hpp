@@ -499,17 +499,19 @@ __device__ inline void bitonic_merge_multi(uint64_t (&v)[PER]) {
 // issued first; the buffer is sorted descending in lanes 0..31 and moved to
 // lanes 32..63, where the element-wise minimum with the list's last 64 keys
 // leaves the KSEL smallest of both as a bitonic sequence, which is then
-// merged.  Returns the new admission threshold: the KSEL-th distance (+inf
-// while the list is not full).
+// merged.  A fresh list (the query's first merge) is taken as empty without
+// reading the workspace, which therefore needs no initialisation.  Returns the
+// new admission threshold: the KSEL-th distance (+inf while the list is not
+// full).
 template <int KSEL>
-__device__ float merge_query(uint64_t* __restrict__ gstate, const uint64_t* buf, int c) {
+__device__ float merge_query(uint64_t* __restrict__ gstate, const uint64_t* buf, int c, bool fresh = false) {
     constexpr int PER = KSEL >= 64 ? KSEL / 64 : 1;
     const int l = lane_id();
     uint64_t v[PER];
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
         const int e = p * 64 + l;
-        v[p] = e < KSEL ? gstate[e] : EMPTY_KEY;
+        v[p] = e < KSEL && !fresh ? gstate[e] : EMPTY_KEY;   // a fresh list is empty, nothing to load
     }
     uint64_t b = l < c ? buf[l] : EMPTY_KEY;
     b = low_half_to_high(half_sort_desc_u64(b));
@@ -547,6 +549,7 @@ struct Selector {
     uint64_t* state;   // state row of the wave's first query
     uint64_t* buf;     // LDS buffers of the wave's queries (32*QB*CBQ keys)
     int fill[QB];      // buffer fill of the lane's query (same in both lanes)
+    uint32_t fresh[QB];  // wave-uniform: bit q set while query q's list has not been written
 
     // After qself is set: the smallest and largest query id of the wave, so
     // that a subtile whose candidate ids miss [qlo, qhi] skips the per-lane
@@ -660,7 +663,8 @@ struct Selector {
                         need &= need - 1;
                         const int q2 = b * 32 + qi;
                         const float tq = merge_query<KSEL>(state + (int64_t)q2 * KSEL, buf + q2 * CBQ,
-                                                           __builtin_amdgcn_readlane(c, qi));
+                                                           __builtin_amdgcn_readlane(c, qi), (fresh[b] >> qi) & 1u);
+                        fresh[b] &= ~(1u << qi);
                         if (ql == qi) {
                             c = 0;
                             tnext = tq;
@@ -686,20 +690,23 @@ struct Selector {
         }
     }
 
-    // Merge every non-empty buffer (end of the candidate stream).
+    // Merge every non-empty buffer, and write the list of every query still
+    // fresh (empty, or holding only the keys of its buffer), at the end of
+    // the candidate stream: every list is then in the workspace.
     __device__ void drain() {
         const int l = lane_id();
 #pragma unroll
         for (int b = 0; b < QB; ++b) {
-            const uint64_t m = __builtin_amdgcn_ballot_w64(l < 32 && fill[b] > 0);
+            const uint64_t m = __builtin_amdgcn_ballot_w64(l < 32 && (fill[b] > 0 || ((fresh[b] >> l) & 1u)));
             uint32_t need = (uint32_t)m;
             while (need) {
                 const int qi = __builtin_ctz(need);
                 need &= need - 1;
                 const int q2 = b * 32 + qi;
                 merge_query<KSEL>(state + (int64_t)q2 * KSEL, buf + q2 * CBQ,
-                                  __builtin_amdgcn_readlane(fill[b], qi));
+                                  __builtin_amdgcn_readlane(fill[b], qi), (fresh[b] >> qi) & 1u);
             }
+            fresh[b] = 0;
         }
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
@@ -816,6 +823,7 @@ __device__ void topk_block(TopkSmem<P, NSTEP, WAVES, QB, CBQ, BCR>& sm, int64_t 
         if constexpr (P == SG_PREC_FP8) q_scale[b] = 127 + A.qsexp[qg] + 1;
         sel.thr[b] = __builtin_inff();
         sel.amin[b] = INT32_MIN;
+        sel.fresh[b] = ~0u;
         sel.fill[b] = 0;
         sel.qself[b] = qg < A.nq ? (A.qid ? A.qid[qg] : qg) : -1;
     }
@@ -1069,6 +1077,7 @@ __global__ __launch_bounds__(KS_WAVES * 64, 1) void dist_topk_kstream_kernel(Top
         const int64_t qg = qblk0 + ql;
         sel.thr[0] = __builtin_inff();
         sel.fill[0] = 0;
+        sel.fresh[0] = 0;   // this kernel's workspace lists are initialised by the caller
         sel.qself[0] = qg < nq ? (qid ? qid[qg] : qg) : -1;
     }
     sel.qm_int = 0;
