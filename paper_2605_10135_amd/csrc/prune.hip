@@ -74,6 +74,43 @@ __device__ inline int64_t visit_row(const int32_t* order, const int32_t* order_b
     return (order && *order_bad == 0) ? (int64_t)order[slot] : slot;
 }
 
+// Ascending bitonic sort of 64 KP 32-bit keys, element p * 64 + l in v[p]:
+// exchanges at distances of 64 and more compare registers of one lane, shorter
+// ones compare lanes (lane_xor).
+template <int KP>
+__device__ inline void sort_multi_u32(uint32_t (&v)[KP]) {
+    const int l = lane_id();
+#pragma unroll
+    for (int k = 2; k <= 64 * KP; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 64) {
+                const int jp = j >> 6;
+#pragma unroll
+                for (int p = 0; p < KP; ++p) {
+                    const int q = p ^ jp;
+                    if (q > p) {
+                        const bool up = ((p * 64) & k) == 0;   // element p*64+l; bit k of it
+                        const uint32_t a = v[p], b = v[q];
+                        const bool sw = up ? a > b : a < b;
+                        v[p] = sw ? b : a;
+                        v[q] = sw ? a : b;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int p = 0; p < KP; ++p) {
+                    const int e = p * 64 + l;
+                    const uint32_t o = lane_xor(v[p], j);
+                    const bool low = (e & j) == 0, up = (e & k) == 0;
+                    // the lower element of a pair keeps the smaller key in an ascending block
+                    v[p] = (o < v[p]) == (low == up) ? o : v[p];
+                }
+            }
+        }
+    }
+}
+
 // KP: list entries per lane (ceil(K/64)); CT: slots per cuckoo table (power of
 // two, 4 * 64 * KP).  Also counts the in-degree of every row in P (cnt,
 // zeroed by the caller).
@@ -221,24 +258,26 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
             if (v != SG_NONE) rslot[x * R + l] = (int32_t)atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[v]), 1ull);
         }
     } else {
-        int nvalid = 0;
-#pragma unroll
-        for (int t = 0; t < KP; ++t) nvalid += __builtin_popcountll(__builtin_amdgcn_ballot_w64(y[t] != SG_NONE));
+        // 32-bit keys (detour << 10 | j): detour <= K - 1 < 2^10 and j < 2^10;
+        // absent positions all ones, after every valid key.  A bitonic sort of
+        // the 64 KP keys (element p * 64 + l in key[p]) puts the rank-r key
+        // in element r.
+        uint32_t key[KP];
 #pragma unroll
         for (int t = 0; t < KP; ++t) {
-            int j = l + 64 * t;
-            if (y[t] == SG_NONE) continue;
-            int kj = det[j] * 1024 + j;
-            int rank = 0;
-            for (int u = 0; u < K; ++u) {
-                if (nx[u] != SG_NONE && det[u] * 1024 + u < kj) ++rank;
-            }
-            if (rank < R) {
-                P[x * R + rank] = y[t];
-                rslot[x * R + rank] = (int32_t)atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[y[t]]), 1ull);
+            const int j = l + 64 * t;
+            key[t] = y[t] != SG_NONE ? ((uint32_t)det[j] << 10) | (uint32_t)j : ~0u;
+        }
+        sort_multi_u32<KP>(key);
+#pragma unroll
+        for (int p = 0; p < KP; ++p) {
+            const int r = p * 64 + l;
+            if (r < R) {
+                const int32_t v = key[p] == ~0u ? SG_NONE : nx[key[p] & 1023u];
+                P[x * R + r] = v;
+                if (v != SG_NONE) rslot[x * R + r] = (int32_t)atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[v]), 1ull);
             }
         }
-        for (int r = nvalid + l; r < R; r += 64) P[x * R + r] = SG_NONE;
     }
 }
 
