@@ -249,15 +249,7 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     // rank valid positions by (detour, j); keys are unique
-    if constexpr (KP == 1) {
-        uint64_t key = y[0] != SG_NONE ? ((uint64_t)(uint32_t)det[l] << 10) | (uint32_t)l : EMPTY_KEY;
-        key = wave_sort_u64(key);
-        if (l < R) {
-            const int32_t v = key == EMPTY_KEY ? SG_NONE : nx[key & 1023];
-            P[x * R + l] = v;
-            if (v != SG_NONE) rslot[x * R + l] = (int32_t)atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[v]), 1ull);
-        }
-    } else {
+    {
         // 32-bit keys (detour << 10 | j): detour <= K - 1 < 2^10 and j < 2^10;
         // absent positions all ones, after every valid key.  A bitonic sort of
         // the 64 KP keys (element p * 64 + l in key[p]) puts the rank-r key
