@@ -34,7 +34,7 @@ namespace prune {
 constexpr int WAVES = 4;
 
 // A row's neighbour table, id -> list position, by cuckoo hashing over two
-// tables of CT slots (together one eighth full): every id sits in T0[h0(id)]
+// tables of CT slots (together at most a quarter full): every id sits in T0[h0(id)]
 // or in T1[h1(id)], so a lookup is two independent 64-bit LDS reads with no
 // probe loop.  A slot holds (position << 32) | id; all ones marks an empty
 // slot (its id field is SG_NONE, whose position field, -1, never counts).
@@ -112,8 +112,10 @@ __device__ inline void sort_multi_u32(uint32_t (&v)[KP]) {
 }
 
 // KP: list entries per lane (ceil(K/64)); CT: slots per cuckoo table (power of
-// two, 4 * 64 * KP).  Also counts the in-degree of every row in P (cnt,
-// zeroed by the caller).
+// two: 256 for K <= 128, so that the tables of K = 128 are a quarter full and
+// six waves per SIMD fit; 1024 for K = 256, where a quarter-full table let too
+// many rows fall back to comparing every entry).  Also counts the in-degree of
+// every row in P (cnt, zeroed by the caller).
 template <int KP, int CT>
 __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__ knn, int64_t n,
                                                      int K, int R, const int32_t* __restrict__ order,
@@ -501,7 +503,7 @@ inline void enqueue(const int32_t* knn, int64_t n, int K, int R, const int32_t* 
     if (K <= 64)
         detour_kernel<1, 256><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt);
     else if (K <= 128)
-        detour_kernel<2, 512><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt);
+        detour_kernel<2, 256><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt);
     else
         detour_kernel<4, 1024><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt);
     SG_LAUNCH_CHECK();
