@@ -51,7 +51,10 @@ __device__ inline uint32_t mul_u24(uint32_t c, uint32_t m) {
     asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "s"(c), "v"(m));
     return r;
 }
-__device__ inline uint32_t cuckoo_product(int32_t z) { return mul_u24(0x9E3779u, (uint32_t)z); }
+// The hash constants: K <= 128 uses the first; rows of K > 128 whose insertion
+// does not settle insert again with the next one before falling back.
+constexpr uint32_t CUCKOO_C0 = 0x9E3779u, CUCKOO_C1 = 0x85EBCBu, CUCKOO_C2 = 0xC2B2AFu;
+__device__ inline uint32_t cuckoo_product(uint32_t c, int32_t z) { return mul_u24(c, (uint32_t)z); }
 template <int CT>
 __device__ inline uint32_t cuckoo_h0(uint32_t p) { return (p >> 8) & (CT - 1); }
 template <int CT>
@@ -112,10 +115,10 @@ __device__ inline void sort_multi_u32(uint32_t (&v)[KP]) {
 }
 
 // KP: list entries per lane (ceil(K/64)); CT: slots per cuckoo table (power of
-// two: 256 for K <= 128, so that the tables of K = 128 are a quarter full and
-// six waves per SIMD fit; 1024 for K = 256, where a quarter-full table let too
-// many rows fall back to comparing every entry).  Also counts the in-degree of
-// every row in P (cnt, zeroed by the caller).
+// two: 256 for K <= 64 (one eighth full), 256 and 512 for K = 128 and 256 (a
+// quarter full, so that six and three waves per SIMD fit; rows of K = 256 that
+// do not settle rehash before comparing every entry)).  Also counts the
+// in-degree of every row in P (cnt, zeroed by the caller).
 template <int KP, int CT>
 __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__ knn, int64_t n,
                                                      int K, int R, const int32_t* __restrict__ order,
@@ -146,30 +149,41 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     // insert (ids of a row are distinct): every lane carries an entry until it
-    // lands in an empty slot, evicting the occupant to its other table
-    bool failed = false;
+    // lands in an empty slot, evicting the occupant to its other table; for
+    // K > 128 a row that does not settle starts again with the next constant
+    constexpr int ATTEMPTS = KP >= 4 ? 3 : 1;   // (more attempts cost K = 128 registers)
+    uint32_t hc = CUCKOO_C0;
+    bool failed = true;
+    for (int attempt = 0; attempt < ATTEMPTS && failed; ++attempt) {
+        if (attempt > 0) {
+            hc = attempt == 1 ? CUCKOO_C1 : CUCKOO_C2;
+            for (int t = l; t < 2 * CT; t += 64) T0[t] = EMPTY_SLOT;
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        }
+        failed = false;
 #pragma unroll
-    for (int t = 0; t < KP; ++t) {
-        bool active = y[t] != SG_NONE;
-        uint64_t e = ((uint64_t)(uint32_t)(l + 64 * t) << 32) | (uint32_t)y[t];
-        int tb = 0;
-        for (int it = 0; it < 128 && __builtin_amdgcn_ballot_w64(active); ++it) {
-            if (active) {
-                const uint32_t m = cuckoo_product((int32_t)(uint32_t)e);
-                unsigned long long* a = reinterpret_cast<unsigned long long*>(
-                    tb ? &T1[cuckoo_h1<CT>(m)] : &T0[cuckoo_h0<CT>(m)]);
-                const uint64_t old = atomicExch(a, (unsigned long long)e);
-                if (old == EMPTY_SLOT) {
-                    active = false;
-                } else {
-                    e = old;        // the evicted entry moves to its slot in the other table
-                    tb ^= 1;
+        for (int t = 0; t < KP; ++t) {
+            bool active = y[t] != SG_NONE;
+            uint64_t e = ((uint64_t)(uint32_t)(l + 64 * t) << 32) | (uint32_t)y[t];
+            int tb = 0;
+            for (int it = 0; it < 128 && __builtin_amdgcn_ballot_w64(active); ++it) {
+                if (active) {
+                    const uint32_t m = cuckoo_product(hc, (int32_t)(uint32_t)e);
+                    unsigned long long* a = reinterpret_cast<unsigned long long*>(
+                        tb ? &T1[cuckoo_h1<CT>(m)] : &T0[cuckoo_h0<CT>(m)]);
+                    const uint64_t old = atomicExch(a, (unsigned long long)e);
+                    if (old == EMPTY_SLOT) {
+                        active = false;
+                    } else {
+                        e = old;        // the evicted entry moves to its slot in the other table
+                        tb ^= 1;
+                    }
                 }
             }
+            failed |= __builtin_amdgcn_ballot_w64(active) != 0;
         }
-        failed |= __builtin_amdgcn_ballot_w64(active) != 0;
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     }
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     // detour counts: for each i, lane p reads z = N(y_i)[p] and looks it up;
     // UB lists per round, the next round's lists loading while this round's
     // are probed
@@ -214,7 +228,7 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
         for (int u = 0; u < UB; ++u)
 #pragma unroll
             for (int t = 0; t < KP; ++t) {
-                const uint32_t m = cuckoo_product(entry(z, okm, u, t));
+                const uint32_t m = cuckoo_product(hc, entry(z, okm, u, t));
                 v0[u][t] = T0[cuckoo_h0<CT>(m)];
                 v1[u][t] = T1[cuckoo_h1<CT>(m)];
             }
@@ -505,7 +519,7 @@ inline void enqueue(const int32_t* knn, int64_t n, int K, int R, const int32_t* 
     else if (K <= 128)
         detour_kernel<2, 256><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt);
     else
-        detour_kernel<4, 1024><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt);
+        detour_kernel<4, 512><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt);
     SG_LAUNCH_CHECK();
     int64_t total = n * (int64_t)R;
     unsigned eg = (unsigned)std::min<int64_t>(cdiv(total, 256), 8192);
