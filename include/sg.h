@@ -383,14 +383,15 @@ sg_status sg_prune(const int32_t* knn, int64_t n, int32_t K, int32_t R, const in
  * process ends; its device address is looked up on the first call on each
  * GPU).  The call makes no allocation of any kind.
  *  Limit: sg_prune_workspace_size(n, K, R) must not exceed
- *  SG_PRUNE_NOALLOC_SCRATCH_BYTES (64 MiB: about 166 000 rows at R = 32,
- *  85 000 at R = 64); larger calls return SG_ERR_ARG before any launch.
+ *  SG_PRUNE_NOALLOC_SCRATCH_BYTES (128 MiB: about 200 000 rows at R = 32,
+ *  102 000 at R = 64, 32 000 at R = 128); larger calls return SG_ERR_ARG
+ *  before any launch.
  *  Every call on one GPU shares that GPU's scratch (it keeps the last call's
  *  contents; the call clears what must start at zero): calls that may overlap
  *  on one GPU (different streams, or different host threads) race, and the
  *  caller must order them.
  * ---------------------------------------------------------------------- */
-#define SG_PRUNE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+#define SG_PRUNE_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
 sg_status sg_prune_noalloc(const int32_t* knn, int64_t n, int32_t K, int32_t R, const int32_t* order,
                            int32_t* out, void* stream);
 

@@ -15,11 +15,14 @@
 //    and counts, for every position j, the i < j whose list holds y_j before
 //    position j.  Positions are ranked by (detour, j) (a wave sort of the
 //    keys) and the first R written: P(x); the in-degree histogram of P is
-//    counted as they are written, and the count an edge x -> y reads is kept
-//    as its slot in y's reverse list.
-//  * exclusive scan of the in-degrees, scatter of the 32-bit reverse keys
-//    (p << 26 | x) to those slots (no atomics; the slot order depends on
-//    timing, but the next pass sorts, so the output does not).
+//    counted as they are written, and the count an edge x -> y reads is its
+//    slot in y's reverse list: the edge's reverse key (p << 26 | x, 32 bits)
+//    goes straight to y's fixed bucket of 2R slots when the slot is below 2R
+//    (the slot order depends on timing, but the combine sorts, so the output
+//    does not).
+//  * exclusive scan of the in-degrees' excess over the bucket, and placement
+//    of the few overflowing keys (rows of in-degree above 2R) by their slots
+//    (no atomics).
 //  * combine_kernel: one wave per row y: the R smallest reverse keys (wave
 //    bitonic sort, chunked for high in-degree), then the list
 //    P(y)[0:h] ++ Rev(y) ++ P(y)[h:R] is deduplicated in order (values
@@ -114,17 +117,55 @@ __device__ inline void sort_multi_u32(uint32_t (&v)[KP]) {
     }
 }
 
+// Reverse-edge keys (p, x) ordered by p, then x.  For R <= 64 they are
+// 32-bit (p << 26 | x): p < 64 and x < MAX_ROWS < 2^26 - 1, so no key equals
+// the all-ones empty marker, and the reverse lists hold and the combine sorts
+// half the bytes of a 64-bit key.  Wider rows (R <= 128) use (p << 32 | x).
+constexpr int REV_XBITS = 26;
+static_assert(MAX_ROWS < (int64_t(1) << REV_XBITS) - 1, "row ids must fit the reverse key");
+template <typename KT>
+struct RevKey;
+template <>
+struct RevKey<uint32_t> {
+    static constexpr uint32_t EMPTY = ~0u;
+    __device__ static uint32_t make(int p, int64_t x) { return ((uint32_t)p << REV_XBITS) | (uint32_t)x; }
+    __device__ static int32_t source(uint32_t k) { return (int32_t)(k & ((1u << REV_XBITS) - 1)); }
+    __device__ static uint32_t sort(uint32_t k) { return wave_sort_u32(k); }
+    __device__ static uint32_t xor_lane(uint32_t k, int j) { return lane_xor(k, j); }
+    __device__ static uint32_t from_lane(uint32_t k, int src) { return (uint32_t)__shfl((int)k, src, 64); }
+};
+template <>
+struct RevKey<uint64_t> {
+    static constexpr uint64_t EMPTY = ~0ull;
+    __device__ static uint64_t make(int p, int64_t x) { return ((uint64_t)(uint32_t)p << 32) | (uint64_t)x; }
+    __device__ static int32_t source(uint64_t k) { return (int32_t)(uint32_t)k; }
+    __device__ static uint64_t sort(uint64_t k) { return wave_sort_u64(k); }
+    __device__ static uint64_t xor_lane(uint64_t k, int j) { return lane_xor_u64(k, j); }
+    __device__ static uint64_t from_lane(uint64_t k, int src) { return shfl_u64(k, src); }
+};
+
+// Row y's reverse keys: the first CAP (in the order the detour pass counts
+// them) in y's bucket rev[y * CAP ..], written by the detour pass as it
+// counts the edge, the rest (rows of in-degree above CAP) in the overflow
+// area at oof[y] .. (exclusive scan of the excess), placed by overflow_kernel.
+// CAP = 2R rounded up to 16 entries: the mean in-degree is at most R, so few
+// edges overflow.
+inline int bucket_cap(int R) { return (2 * R + 15) / 16 * 16; }
+
 // KP: list entries per lane (ceil(K/64)); CT: slots per cuckoo table (power of
 // two: 256 for K <= 64 (one eighth full), 256 and 512 for K = 128 and 256 (a
 // quarter full, so that six and three waves per SIMD fit; rows of K = 256 that
 // do not settle rehash before comparing every entry)).  Also counts the
-// in-degree of every row in P (cnt, zeroed by the caller).
+// in-degree of every row in P (cnt, zeroed by the caller): the count edge
+// x -> y reads is its slot in y's reverse list, kept in rslot (-1 for absent
+// positions), and the edge's key goes to y's bucket when the slot is below
+// cap (rev: 32-bit keys for R <= 64, else 64-bit).
 template <int KP, int CT>
 __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__ knn, int64_t n,
                                                      int K, int R, const int32_t* __restrict__ order,
                                                      const int32_t* __restrict__ order_bad,
                                                      int32_t* __restrict__ P, int32_t* __restrict__ rslot,
-                                                     int64_t* __restrict__ cnt) {
+                                                     int64_t* __restrict__ cnt, int cap, void* __restrict__ rev) {
     __shared__ uint64_t s_t[WAVES][2 * CT];
     __shared__ int32_t s_det[WAVES][64 * KP + 64];   // + one discard slot per lane
     __shared__ int32_t s_nx[WAVES][64 * KP];
@@ -283,38 +324,22 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
             if (r < R) {
                 const int32_t v = key[p] == ~0u ? SG_NONE : nx[key[p] & 1023u];
                 P[x * R + r] = v;
-                if (v != SG_NONE) rslot[x * R + r] = (int32_t)atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[v]), 1ull);
+                int32_t sl = -1;
+                if (v != SG_NONE) {
+                    sl = (int32_t)atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[v]), 1ull);
+                    if (sl < cap) {
+                        const int64_t at = (int64_t)v * cap + sl;
+                        if (R <= 64)
+                            static_cast<uint32_t*>(rev)[at] = RevKey<uint32_t>::make(r, x);
+                        else
+                            static_cast<uint64_t*>(rev)[at] = RevKey<uint64_t>::make(r, x);
+                    }
+                }
+                rslot[x * R + r] = sl;
             }
         }
     }
 }
-
-// Reverse-edge keys (p, x) ordered by p, then x.  For R <= 64 they are
-// 32-bit (p << 26 | x): p < 64 and x < MAX_ROWS < 2^26 - 1, so no key equals
-// the all-ones empty marker, and the scatter moves and the combine sorts half
-// the bytes of a 64-bit key.  Wider rows (R <= 128) use (p << 32 | x).
-constexpr int REV_XBITS = 26;
-static_assert(MAX_ROWS < (int64_t(1) << REV_XBITS) - 1, "row ids must fit the reverse key");
-template <typename KT>
-struct RevKey;
-template <>
-struct RevKey<uint32_t> {
-    static constexpr uint32_t EMPTY = ~0u;
-    __device__ static uint32_t make(int p, int64_t x) { return ((uint32_t)p << REV_XBITS) | (uint32_t)x; }
-    __device__ static int32_t source(uint32_t k) { return (int32_t)(k & ((1u << REV_XBITS) - 1)); }
-    __device__ static uint32_t sort(uint32_t k) { return wave_sort_u32(k); }
-    __device__ static uint32_t xor_lane(uint32_t k, int j) { return lane_xor(k, j); }
-    __device__ static uint32_t from_lane(uint32_t k, int src) { return (uint32_t)__shfl((int)k, src, 64); }
-};
-template <>
-struct RevKey<uint64_t> {
-    static constexpr uint64_t EMPTY = ~0ull;
-    __device__ static uint64_t make(int p, int64_t x) { return ((uint64_t)(uint32_t)p << 32) | (uint64_t)x; }
-    __device__ static int32_t source(uint64_t k) { return (int32_t)(uint32_t)k; }
-    __device__ static uint64_t sort(uint64_t k) { return wave_sort_u64(k); }
-    __device__ static uint64_t xor_lane(uint64_t k, int j) { return lane_xor_u64(k, j); }
-    __device__ static uint64_t from_lane(uint64_t k, int src) { return shfl_u64(k, src); }
-};
 
 // Ascending order of a bitonic sequence of one key per lane (the merge
 // stages of a bitonic sort).
@@ -329,20 +354,28 @@ __device__ inline KT bitonic_finish(KT x) {
     return x;
 }
 
-// Edge e = x * R + p (P[e] = y) goes to rev[off[y] + rslot[e]]: rslot[e] is the
-// in-degree count of y that the edge read when the detour pass counted it, so
-// the slots of y's edges are 0 .. in-degree(y) - 1, each taken once.
+// The excess of each row's in-degree over the bucket: ovn[y] = max(cnt[y] - cap, 0).
+__global__ void excess_kernel(const int64_t* __restrict__ cnt, int64_t n, int cap, int64_t* __restrict__ ovn) {
+    for (int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; y < n; y += (int64_t)gridDim.x * blockDim.x)
+        ovn[y] = cnt[y] > cap ? cnt[y] - cap : 0;
+}
+
+// Edge e = x * R + p whose slot rslot[e] (its in-degree count of y = P[e]) is
+// cap or more goes to over[oof[y] + rslot[e] - cap]: the slots of y's
+// overflowing edges are cap .. in-degree(y) - 1, each taken once.  Only those
+// edges read P and oof; the rest of the pass is one read of rslot.
 template <typename KT>
-__global__ void scatter_kernel(const int32_t* __restrict__ P, const int32_t* __restrict__ rslot,
-                               int64_t total, int R, const int64_t* __restrict__ off,
-                               KT* __restrict__ rev) {
+__global__ void overflow_kernel(const int32_t* __restrict__ P, const int32_t* __restrict__ rslot,
+                                int64_t total, int R, int cap, const int64_t* __restrict__ oof,
+                                KT* __restrict__ over) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
-        int32_t y = P[e];
-        if (y == SG_NONE) continue;
-        int64_t x = e / R;
-        int p = (int)(e - x * R);
-        rev[off[y] + rslot[e]] = RevKey<KT>::make(p, x);
+        const int32_t sl = rslot[e];
+        if (sl < cap) continue;   // in the bucket, or no edge (-1)
+        const int32_t y = P[e];
+        const int64_t x = e / R;
+        const int p = (int)(e - x * R);
+        over[oof[y] + (sl - cap)] = RevKey<KT>::make(p, x);
     }
 }
 
@@ -384,8 +417,10 @@ __device__ inline int span_of(int32_t v) {
 // repeats, and the rest fill the R - h places left before P(y)[h:R] is reached.
 template <typename KT, int NB>
 __global__ __launch_bounds__(256) void combine_kernel(const int32_t* __restrict__ P, int64_t n, int R,
-                                                      const int64_t* __restrict__ off,
+                                                      const int64_t* __restrict__ cnts, int cap,
                                                       const KT* __restrict__ rev,
+                                                      const int64_t* __restrict__ oof,
+                                                      const KT* __restrict__ over,
                                                       const int32_t* __restrict__ order,
                                                       const int32_t* __restrict__ order_bad,
                                                       int32_t* __restrict__ F) {
@@ -396,20 +431,24 @@ __global__ __launch_bounds__(256) void combine_kernel(const int32_t* __restrict_
     if (slot >= n) return;
     const int64_t y = visit_row(order, order_bad, slot);
     const int h = (R + 1) / 2;
-    const int64_t b = off[y], cnt = off[y + 1] - off[y];
+    const int64_t cnt = cnts[y];
+    const KT* bk = rev + y * cap;
+    const int64_t ob = cnt > cap ? oof[y] : 0;
+    // reverse key i of y (EMPTY past the in-degree): bucket, then overflow area
+    auto key_at = [&](int64_t i) -> KT { return i < cnt ? (i < cap ? bk[i] : over[ob + (i - cap)]) : RK::EMPTY; };
     // the 64 * NB smallest reverse keys, ascending: element p * 64 + l in best[p]
     KT best[NB];
-    best[0] = RK::sort(l < cnt ? rev[b + l] : RK::EMPTY);
+    best[0] = RK::sort(key_at(l));
     if constexpr (NB == 2) {
         // two sorted runs; the second reversed makes the pair one bitonic sequence
-        const KT v = RK::sort(64 + l < cnt ? rev[b + 64 + l] : RK::EMPTY);
+        const KT v = RK::sort(key_at(64 + l));
         best[1] = RK::from_lane(v, 63 - l);
         const KT lo = best[0] < best[1] ? best[0] : best[1], hi = best[0] < best[1] ? best[1] : best[0];
         best[0] = bitonic_finish(lo);
         best[1] = bitonic_finish(hi);
     }
     for (int64_t c0 = 64 * NB; c0 < cnt; c0 += 64) {
-        const KT v = RK::sort(c0 + l < cnt ? rev[b + c0 + l] : RK::EMPTY);
+        const KT v = RK::sort(key_at(c0 + l));
         // the element-wise minimum of the list's last run and the reversed new
         // run leaves the 64 * NB smallest of both as a bitonic sequence
         const KT vr = RK::from_lane(v, 63 - l);
@@ -465,7 +504,7 @@ __global__ __launch_bounds__(256) void combine_kernel(const int32_t* __restrict_
 }
 
 struct Layout {
-    size_t P, rslot, cnt, off, rev, scan, seen, total;
+    size_t P, rslot, cnt, ovn, oof, rev, over, scan, seen, total;
 };
 
 // Reverse keys are 4 bytes for R <= 64, 8 beyond.
@@ -476,11 +515,13 @@ inline Layout layout(int64_t n, int R) {
     L.P = align_up((size_t)n * R * 4, 256);
     L.rslot = align_up((size_t)n * R * 4, 256);
     L.cnt = align_up((size_t)(n + 1) * 8, 256);
-    L.off = align_up((size_t)(n + 1) * 8, 256);
-    L.rev = align_up((size_t)n * R * rev_bytes(R), 256);
+    L.ovn = align_up((size_t)(n + 1) * 8, 256);
+    L.oof = align_up((size_t)(n + 1) * 8, 256);
+    L.rev = align_up((size_t)n * bucket_cap(R) * rev_bytes(R), 256);
+    L.over = align_up((size_t)n * R * rev_bytes(R), 256);   // at most every edge overflows
     L.scan = align_up(exclusive_scan_tmp_bytes(n), 256);
     L.seen = align_up((size_t)(n + 64) * 4, 256);   // order check: per-row counters + flag
-    L.total = L.P + L.rslot + L.cnt + L.off + L.rev + L.scan + L.seen + 1024;
+    L.total = L.P + L.rslot + L.cnt + L.ovn + L.oof + L.rev + L.over + L.scan + L.seen + 1024;
     return L;
 }
 
@@ -500,8 +541,11 @@ inline void enqueue(const int32_t* knn, int64_t n, int K, int R, const int32_t* 
     int32_t* P = cv.take<int32_t>((size_t)n * R);
     int32_t* rslot = cv.take<int32_t>((size_t)n * R);
     int64_t* cnt = cv.take<int64_t>(n + 1);
-    int64_t* off = cv.take<int64_t>(n + 1);
-    void* rev = cv.take<char>((size_t)n * R * rev_bytes(R));
+    int64_t* ovn = cv.take<int64_t>(n + 1);
+    int64_t* oof = cv.take<int64_t>(n + 1);
+    const int cap = bucket_cap(R);
+    void* rev = cv.take<char>((size_t)n * cap * rev_bytes(R));
+    void* over = cv.take<char>((size_t)n * R * rev_bytes(R));
     void* scan_tmp = cv.take<char>(exclusive_scan_tmp_bytes(n));
     int32_t* seen = cv.take<int32_t>(n + 64);
     int32_t* order_bad = seen + n;
@@ -515,25 +559,30 @@ inline void enqueue(const int32_t* knn, int64_t n, int K, int R, const int32_t* 
         SG_LAUNCH_CHECK();
     }
     if (K <= 64)
-        detour_kernel<1, 256><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt);
+        detour_kernel<1, 256><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt, cap,
+                                                     rev);
     else if (K <= 128)
-        detour_kernel<2, 256><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt);
+        detour_kernel<2, 256><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt, cap,
+                                                     rev);
     else
-        detour_kernel<4, 512><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt);
+        detour_kernel<4, 512><<<grid, 256, 0, s>>>(knn, n, K, R, order, order_bad, P, rslot, cnt, cap,
+                                                     rev);
     SG_LAUNCH_CHECK();
     int64_t total = n * (int64_t)R;
     unsigned eg = (unsigned)std::min<int64_t>(cdiv(total, 256), 8192);
-    exclusive_scan_i64(cnt, off, n, scan_tmp, s);
+    excess_kernel<<<(unsigned)std::min<int64_t>(cdiv(n, 256), 4096), 256, 0, s>>>(cnt, n, cap, ovn);
+    SG_LAUNCH_CHECK();
+    exclusive_scan_i64(ovn, oof, n, scan_tmp, s);
     if (R <= 64) {
-        scatter_kernel<uint32_t><<<eg, 256, 0, s>>>(P, rslot, total, R, off, static_cast<uint32_t*>(rev));
+        overflow_kernel<uint32_t><<<eg, 256, 0, s>>>(P, rslot, total, R, cap, oof, static_cast<uint32_t*>(over));
         SG_LAUNCH_CHECK();
-        combine_kernel<uint32_t, 1><<<grid, 256, 0, s>>>(P, n, R, off, static_cast<const uint32_t*>(rev), order,
-                                                         order_bad, out);
+        combine_kernel<uint32_t, 1><<<grid, 256, 0, s>>>(P, n, R, cnt, cap, static_cast<const uint32_t*>(rev), oof,
+                                                         static_cast<const uint32_t*>(over), order, order_bad, out);
     } else {
-        scatter_kernel<uint64_t><<<eg, 256, 0, s>>>(P, rslot, total, R, off, static_cast<uint64_t*>(rev));
+        overflow_kernel<uint64_t><<<eg, 256, 0, s>>>(P, rslot, total, R, cap, oof, static_cast<uint64_t*>(over));
         SG_LAUNCH_CHECK();
-        combine_kernel<uint64_t, 2><<<grid, 256, 0, s>>>(P, n, R, off, static_cast<const uint64_t*>(rev), order,
-                                                         order_bad, out);
+        combine_kernel<uint64_t, 2><<<grid, 256, 0, s>>>(P, n, R, cnt, cap, static_cast<const uint64_t*>(rev), oof,
+                                                         static_cast<const uint64_t*>(over), order, order_bad, out);
     }
     SG_LAUNCH_CHECK();
 }
