@@ -246,10 +246,11 @@ def main():
     e4.record()
     torch.cuda.synchronize()
     prune_ms = e3.elapsed_time(e4)
-    # compulsory HBM bytes per row: the prune reads its K ids once, writes P
-    # and each edge's reverse slot, rereads them to scatter the 32-bit reverse
-    # keys, rereads P and the keys to write F (4K + 24R + 24 with the counts
-    # and offsets); the K lists of K ids it gathers per row are re-reads of the
+    # compulsory HBM bytes per row: the prune reads its K ids once, writes P,
+    # each edge's reverse slot and its 32-bit reverse key, rereads P and the
+    # keys to write F (4K + 24R + 24 with the counts and offsets; the reread
+    # of the slots that places the few keys past a row's bucket is not
+    # counted); the K lists of K ids it gathers per row are re-reads of the
     # same graph (cache hits), counted apart.  The merge reads each shard row's
     # R ids and member id and writes the merged rows and degrees.
     prune_bytes = float(total) * (4 * K + 24 * R + 24)
