@@ -323,19 +323,20 @@ __global__ __launch_bounds__(256) void detour_kernel(const int32_t* __restrict__
             const int r = p * 64 + l;
             if (r < R) {
                 const int32_t v = key[p] == ~0u ? SG_NONE : nx[key[p] & 1023u];
-                P[x * R + r] = v;
+                // (streaming stores: this pass never reads these lines back)
+                __builtin_nontemporal_store(v, &P[x * R + r]);
                 int32_t sl = -1;
                 if (v != SG_NONE) {
                     sl = (int32_t)atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[v]), 1ull);
                     if (sl < cap) {
                         const int64_t at = (int64_t)v * cap + sl;
                         if (R <= 64)
-                            static_cast<uint32_t*>(rev)[at] = RevKey<uint32_t>::make(r, x);
+                            __builtin_nontemporal_store(RevKey<uint32_t>::make(r, x), &static_cast<uint32_t*>(rev)[at]);
                         else
-                            static_cast<uint64_t*>(rev)[at] = RevKey<uint64_t>::make(r, x);
+                            __builtin_nontemporal_store(RevKey<uint64_t>::make(r, x), &static_cast<uint64_t*>(rev)[at]);
                     }
                 }
-                rslot[x * R + r] = sl;
+                __builtin_nontemporal_store(sl, &rslot[x * R + r]);
             }
         }
     }
@@ -363,20 +364,35 @@ __global__ void excess_kernel(const int64_t* __restrict__ cnt, int64_t n, int ca
 // Edge e = x * R + p whose slot rslot[e] (its in-degree count of y = P[e]) is
 // cap or more goes to over[oof[y] + rslot[e] - cap]: the slots of y's
 // overflowing edges are cap .. in-degree(y) - 1, each taken once.  Only those
-// edges read P and oof; the rest of the pass is one read of rslot.
+// edges read P and oof; the rest of the pass is one read of rslot, four slots
+// per 16-byte load when rslot is 16-byte aligned.
 template <typename KT>
 __global__ void overflow_kernel(const int32_t* __restrict__ P, const int32_t* __restrict__ rslot,
                                 int64_t total, int R, int cap, const int64_t* __restrict__ oof,
                                 KT* __restrict__ over) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t sl = rslot[e];
-        if (sl < cap) continue;   // in the bucket, or no edge (-1)
+    auto place = [&](int64_t e, int32_t sl) {
+        if (sl < cap) return;   // in the bucket, or no edge (-1)
         const int32_t y = P[e];
         const int64_t x = e / R;
         const int p = (int)(e - x * R);
         over[oof[y] + (sl - cap)] = RevKey<KT>::make(p, x);
+    };
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t e0 = 0;
+    if ((reinterpret_cast<uintptr_t>(rslot) & 15) == 0) {
+        const int64_t quads = total / 4;
+        const int4* r4 = reinterpret_cast<const int4*>(rslot);
+        for (int64_t q = t0; q < quads; q += stride) {
+            const int4 v = r4[q];
+            place(4 * q, v.x);
+            place(4 * q + 1, v.y);
+            place(4 * q + 2, v.z);
+            place(4 * q + 3, v.w);
+        }
+        e0 = quads * 4;
     }
+    for (int64_t e = e0 + t0; e < total; e += stride) place(e, rslot[e]);
 }
 
 // Keeps, of one value per lane (SG_NONE = absent), those that no lane of the
@@ -569,17 +585,17 @@ inline void enqueue(const int32_t* knn, int64_t n, int K, int R, const int32_t* 
                                                      rev);
     SG_LAUNCH_CHECK();
     int64_t total = n * (int64_t)R;
-    unsigned eg = (unsigned)std::min<int64_t>(cdiv(total, 256), 8192);
+    const unsigned og = (unsigned)std::min<int64_t>(cdiv(total, 1024), 8192);   // four slots per thread
     excess_kernel<<<(unsigned)std::min<int64_t>(cdiv(n, 256), 4096), 256, 0, s>>>(cnt, n, cap, ovn);
     SG_LAUNCH_CHECK();
     exclusive_scan_i64(ovn, oof, n, scan_tmp, s);
     if (R <= 64) {
-        overflow_kernel<uint32_t><<<eg, 256, 0, s>>>(P, rslot, total, R, cap, oof, static_cast<uint32_t*>(over));
+        overflow_kernel<uint32_t><<<og, 256, 0, s>>>(P, rslot, total, R, cap, oof, static_cast<uint32_t*>(over));
         SG_LAUNCH_CHECK();
         combine_kernel<uint32_t, 1><<<grid, 256, 0, s>>>(P, n, R, cnt, cap, static_cast<const uint32_t*>(rev), oof,
                                                          static_cast<const uint32_t*>(over), order, order_bad, out);
     } else {
-        overflow_kernel<uint64_t><<<eg, 256, 0, s>>>(P, rslot, total, R, cap, oof, static_cast<uint64_t*>(over));
+        overflow_kernel<uint64_t><<<og, 256, 0, s>>>(P, rslot, total, R, cap, oof, static_cast<uint64_t*>(over));
         SG_LAUNCH_CHECK();
         combine_kernel<uint64_t, 2><<<grid, 256, 0, s>>>(P, n, R, cnt, cap, static_cast<const uint64_t*>(rev), oof,
                                                          static_cast<const uint64_t*>(over), order, order_bad, out);
