@@ -427,6 +427,25 @@ __device__ inline int span_of(int32_t v) {
     return m ? 64 - __builtin_clzll(m) : 0;
 }
 
+// Ascending sort of one 32-bit key per lane when only the lanes below m (a
+// wave-uniform count) hold keys and the rest hold the all-ones key: after the
+// bitonic stage of block size k, lanes 0..k-1 are ascending, so the stages
+// stop once m <= k (10 compare-exchange steps for m <= 16, 15 for m <= 32,
+// all 21 beyond).
+__device__ inline uint32_t wave_sort_u32_first(uint32_t x, int m) {
+    const int l = lane_id();
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+        if (m <= (k >> 1)) break;
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t o = lane_xor(x, j);
+            x = (o < x) == (((l & k) == 0) == ((l & j) == 0)) ? o : x;
+        }
+    }
+    return x;
+}
+
 // NB: the reverse list is cut to its 64 * NB smallest keys (NB = 1 for
 // R <= 64, 2 for R <= 128), which always suffices: h = ceil(R/2) <= 32 * NB
 // entries of P(y) come first, so at most that many of the smallest keys are
@@ -454,7 +473,10 @@ __global__ __launch_bounds__(256) void combine_kernel(const int32_t* __restrict_
     auto key_at = [&](int64_t i) -> KT { return i < cnt ? (i < cap ? bk[i] : over[ob + (i - cap)]) : RK::EMPTY; };
     // the 64 * NB smallest reverse keys, ascending: element p * 64 + l in best[p]
     KT best[NB];
-    best[0] = RK::sort(key_at(l));
+    if constexpr (NB == 1)   // a low in-degree sorts only the lanes it fills
+        best[0] = wave_sort_u32_first(key_at(l), __builtin_amdgcn_readfirstlane((int)(cnt < 64 ? cnt : 64)));
+    else
+        best[0] = RK::sort(key_at(l));
     if constexpr (NB == 2) {
         // two sorted runs; the second reversed makes the pair one bitonic sequence
         const KT v = RK::sort(key_at(64 + l));
