@@ -77,17 +77,28 @@ __global__ void place_batched_kernel(Shards sh, const int32_t* __restrict__ orde
 // boundary.
 __global__ void localize_kernel(Shards sh, int32_t* __restrict__ lists, int width) {
     const int64_t total = sh.row0[sh.S] * width;
-    for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x; e0 < total; e0 += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t e = e0 + threadIdx.x;
-        const int64_t e1 = (e0 + blockDim.x < total ? e0 + blockDim.x : total) - 1;
+    // four entries per work-item (one 16-byte load and store, all four in one
+    // row) when rows are a multiple of four entries wide and the lists 16-byte
+    // aligned, else one
+    const int per = (width % 4 == 0 && (reinterpret_cast<uintptr_t>(lists) & 15) == 0) ? 4 : 1;
+    const int64_t chunk = (int64_t)blockDim.x * per;
+    for (int64_t e0 = (int64_t)blockIdx.x * chunk; e0 < total; e0 += (int64_t)gridDim.x * chunk) {
+        const int64_t e = e0 + (int64_t)threadIdx.x * per;
+        const int64_t e1 = (e0 + chunk < total ? e0 + chunk : total) - 1;
         const int s0 = shard_of(sh.row0, sh.S, e0 / width);
         const bool one = e1 / width < sh.row0[s0 + 1];
-        if (e < total) {
+        if (e >= total) continue;
+        const int64_t base = one ? sh.row0[s0] : sh.row0[shard_of(sh.row0, sh.S, e / width)];
+        if (per == 4) {
+            int4 v = *reinterpret_cast<const int4*>(lists + e);
+            v.x = v.x >= 0 ? (int32_t)(v.x - base) : v.x;
+            v.y = v.y >= 0 ? (int32_t)(v.y - base) : v.y;
+            v.z = v.z >= 0 ? (int32_t)(v.z - base) : v.z;
+            v.w = v.w >= 0 ? (int32_t)(v.w - base) : v.w;
+            *reinterpret_cast<int4*>(lists + e) = v;
+        } else {
             const int32_t v = lists[e];
-            if (v >= 0) {
-                const int64_t base = one ? sh.row0[s0] : sh.row0[shard_of(sh.row0, sh.S, e / width)];
-                lists[e] = (int32_t)(v - base);
-            }
+            if (v >= 0) lists[e] = (int32_t)(v - base);
         }
     }
 }
