@@ -179,7 +179,28 @@ __global__ void prep_kernel(const void* __restrict__ X, int dtype, int64_t n, in
         inv = __builtin_ldexpf(1.0f, -sx);
     }
     float ssq = 0.f, ssx = 0.f;
-    for (int t = l; t < DP; t += LPR) {
+    // u8 rows to INT8 operands, eight elements per lane and access when rows
+    // and operand rows are 8-byte aligned (every element lies in a group of
+    // eight wholly below d or wholly in the padding); the sums are exact
+    // integers, so their order does not matter
+    const bool u8_vec = prec == SG_PREC_I8 && dtype == SG_U8 && (d & 7) == 0 && (DP & 7) == 0 && (ld & 7) == 0 &&
+                        (reinterpret_cast<uintptr_t>(X) & 7) == 0 && (reinterpret_cast<uintptr_t>(ops) & 7) == 0;
+    if (u8_vec) {
+        const uint8_t* src = static_cast<const uint8_t*>(X) + base;
+        for (int t = 8 * l; t < DP; t += 8 * LPR) {
+            uint2 w = make_uint2(0x80808080u, 0x80808080u);   // padding: c = 0
+            if (t < d) w = *reinterpret_cast<const uint2*>(src + t);
+            // c = b - 128 as a signed byte is b with its top bit flipped
+            *reinterpret_cast<uint2*>(out + t) = make_uint2(w.x ^ 0x80808080u, w.y ^ 0x80808080u);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int c = (int)(((k < 4 ? w.x : w.y) >> (8 * (k & 3))) & 0xFFu) - 128;
+                ssx += (float)c;
+                ssq += (float)(c * c);
+            }
+        }
+    }
+    for (int t = l; t < DP && !u8_vec; t += LPR) {
         float v = t < d ? load_elem(X, dtype, base + t) : 0.f;
         float q;
         switch (prec) {
